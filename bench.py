@@ -1,0 +1,194 @@
+"""Benchmark: NLL+gradient evaluations per second of the full amplitude model.
+
+Workload "full_grad_1m": ten K* + Z(4430) (Eq. 12), 1,000,000 data events drawn by
+accept-reject from the model and 2,000,000 flat phase-space normalisation events (all
+generated on the GPU by the library's Philox generators), masses and widths of
+K*(1410) and Z(4430) floating.  One step = one kpsi_nll_and_grad call: every data and
+normalisation event is evaluated, -2 ln L and its 54 free-parameter gradient are
+reduced and returned to the host (what a minimiser sees per iteration).
+
+Prints one JSON line.  `value` is host-visible evaluations/s with the events resident
+in HBM; `roofline` refers to the per-event kernel, timed with HIP events on the
+library's stream; `cpu_baseline` is the FP64 CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic floating-point work per event of one NLL+gradient call of this workload
+# (fused multiply-add = 2, reciprocal/rsqrt/log = 1), from the op count of the
+# per-call formulation: forward amplitudes 541, adjoint 418.
+FLOP_PER_EVENT = {"full_grad": 959}
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}        # MI355X published vector peaks
+PEAK_TFLOPS_UNPACKED = {"f32": 78.6, "f64": 78.6}  # without packed-FP32 instructions
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(res, par, floating, n_data: int, n_mc: int, seconds: float = 15.0) -> dict:
+    """The FP64 oracle (dual-number gradient) on a bounded sample of the workload, scaled to
+    evaluations/s of the full workload."""
+    from oracle import oracle as O
+    from paper_2007_14931_amd import workloads as W
+    K = W.KIN
+    dirs = np.flatnonzero(W.free_mask(res, floating))
+    nd_s, nm_s = 2000, 4000
+    data = W.neutral_events(nd_s, 91, peaked=True)
+    mc = O.gen_phsp(K, 92, nm_s, W.PHSP_WMAX)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        st, v, g = O.nll(K, res, par, data, mc, dirs=dirs)
+        reps += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    scale = (n_data + n_mc) / (nd_s + nm_s)
+    return {"value": 1.0 / (dt * scale), "unit": "NLL+grad evals/s", "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"{nd_s} data + {nm_s} normalisation events, {len(dirs)} gradient directions, "
+                      f"{reps} evaluations in {dt * reps:.1f} s, scaled by {scale:.0f} to the full workload"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--ept", type=int, default=0, help="events per thread (0 = automatic)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported on this build "
+              "(the per-call work shards by events with one small all-reduce; see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2007_14931_amd import kpsi
+    from paper_2007_14931_amd import workloads as W
+
+    wl = W.WORKLOADS["full_grad_1m"]
+    res = W.model(wl.model)
+    truth = W.params(res, wl.coup_seed)
+    floating = wl.floating
+    flags = [1 if r.name in floating else 0 for r in res]
+    K = W.KIN
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    stream = torch.cuda.current_stream(dev)
+
+    t0 = time.perf_counter()
+    gen = kpsi.Engine(0, "fp64", stream.cuda_stream)
+    gen.set_model(K, res)
+    mc = gen.generate_phsp(wl.mc_seed, wl.n_mc, W.PHSP_WMAX)
+    # envelope for accept-reject: 1.5 x the largest density over a phase-space scan
+    scan = gen.generate_phsp(wl.mc_seed + 7, 1_000_000, W.PHSP_WMAX)
+    gen.load(kpsi.DATA, scan)
+    smax = 1.5 * float(gen.density(kpsi.DATA, truth).max())
+    data, n_prop, n_over = gen.generate_model(truth, wl.data_seed, wl.n_data, W.PHSP_WMAX, smax)
+    gen.close()
+    del scan
+    log(f"generated {wl.n_data} data events from {n_prop} proposals (over envelope: {n_over}), "
+        f"{wl.n_mc} normalisation events in {time.perf_counter() - t0:.1f} s")
+
+    def make(prec):
+        e = kpsi.Engine(0, prec, stream.cuda_stream)
+        e.set_model(K, res)
+        e.set_floating(flags)
+        e.load(kpsi.DATA, data)
+        e.load(kpsi.NORM, mc)
+        if args.ept:
+            e.set_events_per_thread(args.ept)
+        return e
+
+    par = truth + 0.05 * np.where(W.free_mask(res, floating), 1.0, 0.0)
+    eng = make(args.precision)
+    for _ in range(args.warmup):
+        eng.nll_and_grad(par)
+    eng.set_timing(True)
+    eng.timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        v, g = eng.nll_and_grad(par)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, kn = eng.timing(reset=True)
+    eng.set_timing(False)
+    ms_step = wall / args.steps * 1e3
+    kernel_ms = kms / max(kn, 1)
+    n_ev = wl.n_data + wl.n_mc
+    dt = "f32" if args.precision == "fp32" else "f64"
+    flops = FLOP_PER_EVENT["full_grad"] * n_ev
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    log(f"{args.precision}: {ms_step:.4f} ms/step host, kernel {kernel_ms:.4f} ms, nll {v:.6f}")
+
+    # the other precision, for the record (same events, same parameters)
+    other = "fp64" if args.precision == "fp32" else "fp32"
+    e2 = make(other)
+    for _ in range(5):
+        e2.nll_and_grad(par)
+    e2.set_timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n2 = max(20, args.steps // 5)
+    for _ in range(n2):
+        v2, g2 = e2.nll_and_grad(par)
+    torch.cuda.synchronize()
+    ms2 = (time.perf_counter() - t1) / n2 * 1e3
+    k2, kn2 = e2.timing(reset=True)
+    e2.close()
+
+    out = {
+        "metric": "NLL+grad evals/s at 1M events, full K* model",
+        "value": 1e3 / ms_step,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dt,
+        "data": "synthetic: model accept-reject data and flat phase-space normalisation events from seeded "
+                "Philox generators; seeded couplings",
+        "config": {"workload": "full_grad_1m", "model": "10 K* + Z(4430)", "n_data": wl.n_data,
+                   "n_norm": wl.n_mc, "free_params": int(W.free_mask(res, floating).sum()),
+                   "floating_lineshapes": list(floating), "precision": args.precision,
+                   "reductions": "f64 compensated"},
+        "events_per_s": n_ev / (kernel_ms * 1e-3),
+        "kernel_ms": kernel_ms,
+        "nll": v,
+        "other_precision": {"precision": other, "ms_per_step": ms2, "kernel_ms": k2 / max(kn2, 1),
+                            "evals_per_s": 1e3 / ms2, "nll": v2, "rel_nll_diff": abs(v2 - v) / abs(v)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS[dt], "traffic": None,
+                     "peak_unpacked": PEAK_TFLOPS_UNPACKED[dt],
+                     "frac_unpacked": achieved / PEAK_TFLOPS_UNPACKED[dt],
+                     "flop_per_event": FLOP_PER_EVENT["full_grad"], "events_per_launch": n_ev,
+                     "kernel": "amp_kernel<GRAD>"},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(res, par, floating, wl.n_data, wl.n_mc, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    eng.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

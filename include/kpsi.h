@@ -1,0 +1,164 @@
+/* kpsi.h -- C ABI of the MI355X likelihood engine for the four-dimensional
+ * B0 -> J/psi K pi amplitude fit (arXiv:2007.14931).
+ *
+ * The library evaluates, on one GPU, the unbinned negative log-likelihood of the
+ * paper's amplitude model and its gradient.  The host-side minimiser calls a
+ * function of the fit parameters while the device evaluates the PDF over all events
+ * (Introduction: the fit parameters are stepped on the host, the PDF/NLL is evaluated
+ * on the device; State-of-the-art section: the normalisation is evaluated numerically
+ * over millions of phase-space points).
+ *
+ * Conventions shared by every call
+ *  - Every function returns kpsi_status (0 = KPSI_OK, < 0 = error) and never throws.
+ *    On error a message is available from kpsi_last_error(ctx) until the next call on
+ *    that context.
+ *  - Units: GeV for masses and momenta, GeV^-1 for barrier radii, radians for angles.
+ *  - Host arrays passed in are copied before the call returns; the caller keeps
+ *    ownership.  Device pointers passed to *_device calls are borrowed: the caller
+ *    keeps them alive and unchanged until the context is destroyed or the set is
+ *    reloaded; the library never frees them.
+ *  - All device work runs on the context's stream (the one given to kpsi_create, or a
+ *    stream the library creates).  Calls returning results to the host synchronise
+ *    that stream once.  A context is not thread-safe; separate contexts are
+ *    independent.
+ *
+ * Observables (Eq. 1, with theta_K* in place of m_J/psi pi, which it determines at
+ * fixed m_Kpi): per event m_Kpi, cos theta_K*, cos theta_J/psi and phi (Eq. 4 and
+ * the definitions below it).  Events are accepted only inside the physical region:
+ * mK + mpi <= m_Kpi <= mB - mJ/psi, |cos| <= 1, |phi| <= pi (a tolerance of 1e-12 is
+ * allowed and values are clamped to the boundary).
+ *
+ * Parameter vector (double, length from kpsi_n_params): for each resonance in the
+ * order given to kpsi_set_model, its helicity couplings as (magnitude, phase) pairs --
+ * K* (Eq. 4): lambda = -1, 0, +1, or only lambda = 0 for spin 0; Z (Eq. 10, spin-parity
+ * 1+): lambda' = 0 and lambda' = +1, with H'_-1 = H'_+1 from Eq. (11) -- followed by
+ * (M, Gamma0) of every resonance in table order (Eq. 2-3).  The overall phase and
+ * magnitude convention of Eq. (6) is the caller's business (fix those entries).
+ */
+#ifndef KPSI_H
+#define KPSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kpsi_ctx kpsi_ctx;
+
+typedef enum {
+  KPSI_OK = 0,
+  KPSI_E_ARG = -1,         /* NULL pointer, bad size, value outside the physical region */
+  KPSI_E_STATE = -2,       /* model or event set missing, or a call made in the wrong order */
+  KPSI_E_HIP = -3,         /* a HIP runtime call failed */
+  KPSI_E_OOM = -4,         /* device or pinned-host allocation failed */
+  KPSI_E_NONFINITE = -5,   /* a data-event density is <= 0 or not finite, or the MC
+                              normalisation is <= 0; *nll is set to +inf */
+  KPSI_E_UNSUPPORTED = -6  /* model outside what the compiled kernels cover */
+} kpsi_status;
+
+typedef enum {
+  KPSI_FP64 = 0,           /* every per-event step in double precision */
+  KPSI_FP32 = 1            /* per-event amplitudes in float with hardware transcendentals;
+                              thresholds (breakup momenta) and the Z-chain frame computed
+                              once in double; log-likelihood and normalisation sums in
+                              double with compensated summation */
+} kpsi_precision;
+
+typedef enum { KPSI_DATA = 0, KPSI_NORM = 1 } kpsi_set;
+
+typedef struct {
+  int chain;     /* 0 = K* -> K pi (Eq. 4), 1 = Z -> J/psi pi (Eq. 10) */
+  int spin;      /* J: 0..4 for K*, 1 for Z */
+  int parity;    /* +1 / -1; Z must be 1+ (Eq. 11 relation is then H'_-1 = H'_+1) */
+  int lb, lr;    /* orbital momenta of the B and resonance decays; < 0 selects the lowest
+                    allowed value (text below Eq. 3), the only values supported */
+  double mass;   /* nominal M (used only as the default entry of the parameter vector) */
+  double width;  /* nominal Gamma0 (idem) */
+} kpsi_resonance;
+
+typedef struct {
+  double m_b, m_jpsi, m_k, m_pi;   /* particle masses */
+  double r_b, r_r;                 /* Blatt-Weisskopf radii of the B and resonance decays */
+} kpsi_kinematics;
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t to run on, or NULL
+ * for a library-owned stream.  `prec` selects the per-event arithmetic. */
+kpsi_status kpsi_create(int device, void* stream, kpsi_precision prec, kpsi_ctx** out);
+/* Free every device and pinned buffer the context owns (borrowed pointers untouched). */
+kpsi_status kpsi_destroy(kpsi_ctx* ctx);
+
+/* Set the decay constants and the resonance table (Eq. 2-4, 10-12).  Supported: up to
+ * ten K* of spin 0..4 with at most 3, 3, 2, 1, 1 states of spin 0, 1, 2, 3, 4, and up to
+ * two Z of spin-parity 1+.  Loaded events are re-derived for the new constants. */
+kpsi_status kpsi_set_model(kpsi_ctx* ctx, const kpsi_kinematics* kin, const kpsi_resonance* res, int n_res);
+/* Length of the canonical parameter vector of the current model. */
+kpsi_status kpsi_n_params(const kpsi_ctx* ctx, int* n_full);
+/* Select the resonances whose (M, Gamma0) gradient kpsi_nll_and_grad computes
+ * (flags[i] != 0, at most two).  Gradient entries of other lineshape parameters are
+ * returned as NaN.  Default: none. */
+kpsi_status kpsi_set_floating(kpsi_ctx* ctx, const int* flags, int n_res);
+
+/* Load the data set (KPSI_DATA) or the phase-space normalisation set (KPSI_NORM) from
+ * host arrays of n doubles each (copied).  Replaces a previously loaded set. */
+kpsi_status kpsi_load_events(kpsi_ctx* ctx, kpsi_set set, int64_t n, const double* m_kpi, const double* cos_k,
+                             const double* cos_j, const double* phi);
+/* Same from device arrays (borrowed; see ownership above). */
+kpsi_status kpsi_load_events_device(kpsi_ctx* ctx, kpsi_set set, int64_t n, const double* m_kpi,
+                                    const double* cos_k, const double* cos_j, const double* phi);
+
+/* Efficiency eps(Phi) of Eq. (14) on the normalisation set: flat (default), or one value
+ * per normalisation event (host array of n_norm doubles, copied; 0 <= eps <= 1). */
+kpsi_status kpsi_set_efficiency_flat(kpsi_ctx* ctx);
+kpsi_status kpsi_set_efficiency_values(kpsi_ctx* ctx, const double* eps, int64_t n);
+/* Binned efficiency: a row-major float histogram of nb[0]*nb[1]*nb[2]*nb[3] bins over
+ * (m_Kpi, cos theta_K*, cos theta_J/psi, phi) with lower edges lo[] and upper edges hi[]
+ * (bins [lo, hi), the upper edge falls in the last bin), looked up once per
+ * normalisation event on the device. */
+kpsi_status kpsi_set_efficiency_hist(kpsi_ctx* ctx, const float* eff, const int nb[4], const double lo[4],
+                                     const double hi[4]);
+
+/* -2 ln L (Eq. 14 signal part, purity 1):
+ *   NLL = -2 sum_data ln S(x_i) + 2 N_data ln( (1/N_norm) sum_norm eps_j S(y_j) )
+ * with S of Eq. (12) (Eq. 5 when no Z is present).  params: canonical vector. */
+kpsi_status kpsi_nll(kpsi_ctx* ctx, const double* params, double* nll);
+/* NLL and its gradient with respect to every coupling entry and the (M, Gamma0) of the
+ * resonances selected with kpsi_set_floating, in one pass (hand-written adjoint). */
+kpsi_status kpsi_nll_and_grad(kpsi_ctx* ctx, const double* params, double* nll, double* grad);
+
+/* Diagnostics (not on the fit path).  Per-event density S of a loaded set into a host
+ * array of n doubles; per-event Z-chain observables into a host array of 5n doubles
+ * (m_Jpsi pi, cos theta_Z, cos theta~_J/psi, phi~, alpha). */
+kpsi_status kpsi_density(kpsi_ctx* ctx, kpsi_set set, const double* params, double* out);
+kpsi_status kpsi_invariants(kpsi_ctx* ctx, kpsi_set set, double* out);
+
+/* Generators (Philox4x32-10 counters, so results depend only on the seed and event
+ * index).  Flat phase space: m_Kpi ~ p_B(m) q(m) by accept-reject under the envelope
+ * wmax, angles uniform.  Output: four device arrays of n doubles. */
+kpsi_status kpsi_generate_phsp(kpsi_ctx* ctx, uint64_t seed, int64_t n, double wmax, double* m_kpi,
+                               double* cos_k, double* cos_j, double* phi);
+/* Accept-reject from eps_true(Phi) * S(Phi; params) over phase-space proposals: proposal e
+ * is kept when u_e * smax < eps S, in proposal order, until n are kept.  acc_coef is NULL
+ * (no acceptance) or 12 doubles of the seeded analytic acceptance.  Outputs: four device
+ * arrays of n doubles; *n_prop proposals used; *n_over proposals with eps S > smax. */
+kpsi_status kpsi_generate_model(kpsi_ctx* ctx, const double* params, uint64_t seed, int64_t n, double wmax,
+                                double smax, const double* acc_coef, double* m_kpi, double* cos_k, double* cos_j,
+                                double* phi, int64_t* n_prop, int64_t* n_over);
+
+/* Device timing of the per-event kernel: when enabled, each nll / nll_and_grad call
+ * records HIP events around it on the context stream.  kpsi_timing returns the summed
+ * kernel milliseconds and the number of calls since the last reset. */
+kpsi_status kpsi_set_timing(kpsi_ctx* ctx, int enable);
+kpsi_status kpsi_timing(kpsi_ctx* ctx, double* kernel_ms, int64_t* n_calls, int reset);
+
+/* Launch tuning: events handled by each thread of the per-event kernel (1..1024), or 0
+ * for the automatic choice (about 2048 blocks over the two sets). */
+kpsi_status kpsi_set_events_per_thread(kpsi_ctx* ctx, int ept);
+
+/* Message of the last error on ctx (or of the last failed kpsi_create when ctx is NULL). */
+const char* kpsi_last_error(const kpsi_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPSI_H */

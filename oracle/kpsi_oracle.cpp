@@ -276,9 +276,11 @@ ZAng z_angles(const Kin& k, double m, double cK, double cJ, double phi) {
   z.thJ = std::acos(std::max(-1.0, std::min(1.0, ct)));
   z.phiZ = std::atan2(dot3(mu, y2), dot3(mu, x2));
   // Muon helicity frames of the two chains: the x axis of R(phi, theta, 0) applied to
-  // each chain's frame, x' = cos(theta) (cos(phi) x + sin(phi) y) - sin(theta) n.
-  double th1 = std::acos(std::max(-1.0, std::min(1.0, dot3(mu, n1))));
-  double ph1 = std::atan2(dot3(mu, y1), dot3(mu, x1));
+  // each chain's frame, x' = cos(theta) (cos(phi) x + sin(phi) y) - sin(theta) n.  In the
+  // K* chain (theta, phi) are the event's theta_J/psi and phi themselves (Eq. 4), which
+  // stay meaningful when sin(theta_J/psi) = 0.
+  double th1 = std::acos(std::max(-1.0, std::min(1.0, cJ)));
+  double ph1 = phi;
   V4 xa = sub3(scale3(add4(scale3(x1, std::cos(ph1)), scale3(y1, std::sin(ph1))), std::cos(th1)),
                scale3(n1, std::sin(th1)));
   V4 xb = sub3(scale3(add4(scale3(x2, std::cos(z.phiZ)), scale3(y2, std::sin(z.phiZ))), std::cos(z.thJ)),

@@ -1,0 +1,805 @@
+// Device code of the MI355X likelihood engine (gfx950).
+//
+//   invariants_kernel   once per event set: FP64 kinematics -> structure-of-arrays
+//                       columns (breakup momenta, sines, phi as cos/sin, the Z-chain
+//                       lineshape factors and angular factors of Eq. 10)
+//   amp_kernel          per call: Eq. (2)-(5), (10)-(12) per event, -2 ln L terms and
+//                       the adjoint of S with respect to every coupling and the
+//                       floating masses/widths, reduced per block
+//   reduce_final        fixed-order compensated sum of the block partials
+//   phsp/accept kernels Philox4x32-10 phase-space and accept-reject generators
+//
+// Wavefronts are 64 lanes.  Every reduction is atomic-free and in a fixed order,
+// so results are bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "kpsi_internal.h"
+
+namespace kpsi {
+
+// ------------------------------------------------------------------ math helpers
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq_(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  double e = __builtin_fma(-h * r, r, 0.5);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-h * r, r, 0.5);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float log_(float x) { return __logf(x); }
+__device__ __forceinline__ double log_(double x) { return log(x); }
+
+template <typename T> __device__ __forceinline__ T ldnt(const T* p) { return __builtin_nontemporal_load(p); }
+
+// Opaque copy of a pointer to uniform kernel-argument data.  Re-deriving it inside the
+// event loop keeps the compiler from hoisting every per-resonance constant out of the
+// loop into vector registers: the constants are re-read with scalar loads instead.
+template <typename P> using kconst_ptr = __attribute__((address_space(4))) const P*;
+template <typename P> __device__ __forceinline__ kconst_ptr<P> kernarg_laundered() {
+  kconst_ptr<P> p = (kconst_ptr<P>)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// ------------------------------------------------------------------ invariants
+// Columns written per event (type T, stride ld):
+//   K* chain  : m, q(m), p_B(m), cos/sin theta_K*, cos/sin theta_J/psi, cos/sin phi
+//   Z chain   : m^2_Jpsi pi, nZ = (p_B/M_B) / sqrt(1 + (r_B p_B)^2), gZ = q/m_Jpsi pi,
+//               and the four complex angular factors Zang[l'][xi] of Eq. (10)
+//               (l' = 0 and l' = +-1 combined through Eq. 11, xi = +1, -1).
+// All arithmetic in double; stored in T.
+template <typename T>
+__global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
+  // One-time kinematics without contraction: at the threshold and end point of m_Kpi the
+  // breakup momenta then round to exactly zero, as the plain double-precision definition does.
+#pragma clang fp contract(off)
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.n) return;
+  const double mB = a.mB, mJ = a.mJ, mK = a.mK, mP = a.mPi;
+  double m = a.obs[0][e], cK = a.obs[1][e], cJ = a.obs[2][e], ph = a.obs[3][e];
+  // two-body momenta in the K pi frame and in the B frame
+  const double s = m * m;
+  const double q2 = (s - (mK + mP) * (mK + mP)) * (s - (mK - mP) * (mK - mP));
+  const double q = q2 > 0.0 ? sqrt(q2) / (2.0 * m) : 0.0;
+  const double mB2 = mB * mB;
+  const double pb2 = (mB2 - (mJ + m) * (mJ + m)) * (mB2 - (mJ - m) * (mJ - m));
+  const double pB = pb2 > 0.0 ? sqrt(pb2) / (2.0 * mB) : 0.0;
+  const double sK = sqrt(fmax(0.0, (1.0 - cK) * (1.0 + cK)));
+  const double sJ = sqrt(fmax(0.0, (1.0 - cJ) * (1.0 + cJ)));
+  double sph, cph;
+  sincos(ph, &sph, &cph);
+  T* c = a.cols;
+  const int64_t ld = a.ld;
+  c[0 * ld + e] = (T)m;
+  c[1 * ld + e] = (T)q;
+  c[2 * ld + e] = (T)pB;
+  c[3 * ld + e] = (T)cK;
+  c[4 * ld + e] = (T)sK;
+  c[5 * ld + e] = (T)cJ;
+  c[6 * ld + e] = (T)sJ;
+  c[7 * ld + e] = (T)cph;
+  c[8 * ld + e] = (T)sph;
+  if (!a.with_z && !a.diag) return;
+
+  // J/psi rest frame, reached by a boost along z from the B frame, in which the K pi
+  // system moves along +z and the J/psi along -z.  The K pi system moves along +z in
+  // the J/psi frame with gamma = p_Kpi.p_J/(m mJ) and gamma*beta = pB mB/(m mJ).
+  const double EK = sqrt(mK * mK + q * q), EP = sqrt(mP * mP + q * q);
+  const double g = (mB2 - s - mJ * mJ) / (2.0 * m * mJ);
+  const double gb = pB * mB / (m * mJ);
+  // K and pi momenta in the J/psi frame (x: K side of the hadron plane)
+  const double kx = q * sK, kz = g * (q * cK) + gb * EK;
+  const double px = -q * sK, pz = g * (-q * cK) + gb * EP;
+  const double Epi = g * EP + gb * (-q * cK);
+  // m^2_Jpsi pi = mJ^2 + mpi^2 + 2 mJ E_pi(J/psi frame)
+  const double mz2 = mJ * mJ + mP * mP + 2.0 * mJ * Epi;
+  const double mz = sqrt(mz2);
+  // cos theta_Z from invariants: K and pi energies and momenta in the J/psi pi frame
+  const double EKz = (mB2 - mz2 - mK * mK) / (2.0 * mz);
+  const double EPz = (mz2 + mP * mP - mJ * mJ) / (2.0 * mz);
+  const double pKz = sqrt(fmax(0.0, EKz * EKz - mK * mK)), pPz = sqrt(fmax(0.0, EPz * EPz - mP * mP));
+  const double dotKP = EKz * EPz - 0.5 * (s - mK * mK - mP * mP);
+  double cZ = (pKz * pPz > 0.0) ? dotKP / (pKz * pPz) : 1.0;
+  cZ = fmin(1.0, fmax(-1.0, cZ));
+  const double sZ = sqrt(fmax(0.0, (1.0 - cZ) * (1.0 + cZ)));
+  // Z-chain frame in the J/psi frame: n2 = -pi direction, x2 = K side perpendicular to n2
+  const double pn = sqrt(px * px + pz * pz);
+  const double n2x = -px / pn, n2z = -pz / pn;       // (y component is zero: hadron plane is x-z)
+  const double kd = kx * n2x + kz * n2z;
+  double x2x = kx - kd * n2x, x2z = kz - kd * n2z;
+  const double kn = sqrt(x2x * x2x + x2z * x2z);
+  if (kn * kn > 1e-24 * (kx * kx + kz * kz)) { x2x /= kn; x2z /= kn; }
+  else {  // collinear hadrons: take the K* frame's x axis projected off n2
+    const double d1 = n2x;
+    x2x = 1.0 - d1 * n2x; x2z = -d1 * n2z;
+    const double nn = sqrt(x2x * x2x + x2z * x2z);
+    x2x /= nn; x2z /= nn;
+  }
+  // y2 = n2 x x2 (only the y component survives for vectors in the x-z plane)
+  const double y2y = n2z * x2x - n2x * x2z;
+  // mu+ direction in the J/psi frame: theta_J/psi from n1 = -z, azimuth phi from x1 = +x,
+  // right-handed about n1 (y1 = -y)
+  const double ux = sJ * cph, uy = -sJ * sph, uz = -cJ;
+  const double ct = ux * n2x + uz * n2z;                 // cos theta~
+  const double ux2 = ux * x2x + uz * x2z;                 // sin theta~ cos phi~
+  const double uy2 = uy * y2y;                            // sin theta~ sin phi~
+  const double st = sqrt(ux2 * ux2 + uy2 * uy2);
+  double cpt = 1.0, spt = 0.0;
+  if (st > 0.0) { cpt = ux2 / st; spt = uy2 / st; }
+  // muon helicity frame x axes: x' = cos(theta)(cos(phi) x + sin(phi) y) - sin(theta) n
+  //  K* chain: x1 = +x, y1 = -y, n1 = -z
+  const double xa_x = cJ * cph, xa_y = -cJ * sph, xa_z = sJ;
+  //  Z chain
+  const double xb_x = ct * (cpt * x2x) - st * n2x;
+  const double xb_y = ct * (spt * y2y);
+  const double xb_z = ct * (cpt * x2z) - st * n2z;
+  // alpha: rotation about mu+ taking the Z-chain axis xb onto the K*-chain axis xa
+  const double ca = xb_x * xa_x + xb_y * xa_y + xb_z * xa_z;
+  const double crx = xb_y * xa_z - xb_z * xa_y, cry = xb_z * xa_x - xb_x * xa_z, crz = xb_x * xa_y - xb_y * xa_x;
+  const double sa = crx * ux + cry * uy + crz * uz;
+  if (a.diag) {
+    double* o = a.diag + 5 * e;
+    o[0] = mz; o[1] = cZ; o[2] = ct; o[3] = atan2(spt, cpt); o[4] = atan2(sa, ca);
+  }
+  if (!a.with_z) return;
+  // Z lineshape factors (B -> Z K with L_B = 1, Z -> J/psi pi with L_R = 0)
+  const double qz2 = (mz2 - (mJ + mP) * (mJ + mP)) * (mz2 - (mJ - mP) * (mJ - mP));
+  const double qz = qz2 > 0.0 ? sqrt(qz2) / (2.0 * mz) : 0.0;
+  const double pbz2 = (mB2 - (mz + mK) * (mz + mK)) * (mB2 - (mz - mK) * (mz - mK));
+  const double pbz = pbz2 > 0.0 ? sqrt(pbz2) / (2.0 * mB) : 0.0;
+  const double zb = a.rB * pbz * a.rB * pbz;
+  c[9 * ld + e] = (T)mz2;
+  c[10 * ld + e] = (T)((pbz / mB) / sqrt(1.0 + zb));
+  c[11 * ld + e] = (T)(qz / mz);
+  // Angular factors of Eq. (10): d^1_{0l'}(theta_Z) e^{i l' phi~} d^1_{l' xi}(theta~) e^{i xi alpha}
+  const double r2 = 0.7071067811865475244;
+  //  l' = 0:  xi = +1: cZ st/sqrt2 e^{i alpha};  xi = -1: -cZ st/sqrt2 e^{-i alpha}
+  const double z0 = cZ * st * r2;
+  c[12 * ld + e] = (T)(z0 * ca);
+  c[13 * ld + e] = (T)(z0 * sa);
+  c[14 * ld + e] = (T)(-z0 * ca);
+  c[15 * ld + e] = (T)(z0 * sa);
+  //  l' = +-1 (H'_{-1} = H'_{+1}):  xi = +1: sZ/sqrt2 (ct cpt + i spt) e^{i alpha}
+  //                                 xi = -1: sZ/sqrt2 (-ct cpt + i spt) e^{-i alpha}
+  const double z1 = sZ * r2;
+  const double pr = ct * cpt, pi_ = spt;
+  c[16 * ld + e] = (T)(z1 * (pr * ca - pi_ * sa));
+  c[17 * ld + e] = (T)(z1 * (pr * sa + pi_ * ca));
+  c[18 * ld + e] = (T)(z1 * (-pr * ca + pi_ * sa));
+  c[19 * ld + e] = (T)(z1 * (pr * sa + pi_ * ca));
+}
+
+// ------------------------------------------------------------------ per-event amplitude
+template <typename T> struct Cx { T re, im; };
+template <typename T> __device__ __forceinline__ void cmac(Cx<T>& acc, T ar, T ai, T br, T bi) {
+  acc.re = __builtin_fma(ar, br, __builtin_fma(-ai, bi, acc.re));
+  acc.im = __builtin_fma(ar, bi, __builtin_fma(ai, br, acc.im));
+}
+
+// Blatt-Weisskopf polynomial B_L(z) (Horner form)
+template <int L, typename T> __device__ __forceinline__ T bpoly(T z) {
+  if constexpr (L == 0) return T(1);
+  else if constexpr (L == 1) return T(1) + z;
+  else if constexpr (L == 2) return T(9) + z * (T(3) + z);
+  else if constexpr (L == 3) return T(225) + z * (T(45) + z * (T(6) + z));
+  else return T(11025) + z * (T(1575) + z * (T(135) + z * (T(10) + z)));
+}
+template <int J> struct LBof { static constexpr int v = (J == 0) ? 1 : J - 1; };
+
+template <typename T, int n> __device__ __forceinline__ T ipow(T x) {
+  T r = T(1);
+#pragma unroll
+  for (int i = 0; i < n; ++i) r *= x;
+  return r;
+}
+
+// d^J_{00}(theta_K) and d^J_{10}(theta_K) (d^J_{-1,0} = -d^J_{10}) as polynomials in cos and sin.
+template <int J, typename T> __device__ __forceinline__ T d00(T c) {
+  if constexpr (J == 0) return T(1);
+  else if constexpr (J == 1) return c;
+  else if constexpr (J == 2) return T(1.5) * c * c - T(0.5);
+  else if constexpr (J == 3) return c * (T(2.5) * c * c - T(1.5));
+  else { T c2 = c * c; return (T(35) * c2 * c2 - T(30) * c2 + T(3)) * T(0.125); }
+}
+template <int J, typename T> __device__ __forceinline__ T d10(T c, T s) {
+  // -sin * P_J'(cos) / sqrt(J (J+1))
+  if constexpr (J == 1) return -s * T(0.70710678118654752440);
+  else if constexpr (J == 2) return -s * c * T(1.22474487139158904910);
+  else if constexpr (J == 3) return -s * (T(15) * c * c - T(3)) * T(0.14433756729740644113);
+  else if constexpr (J == 4) return -s * c * (T(35) * c * c - T(15)) * T(0.11180339887498948482);
+  else return T(0);
+}
+
+template <class Sh> __host__ __device__ constexpr int slot_base(int J) {
+  int b = 0;
+  for (int j = 0; j < J; ++j) b += Sh::N[j];
+  return b;
+}
+template <class Sh> __host__ __device__ constexpr int acc_base(int J) {   // accumulator offset of spin J
+  int b = 3;
+  for (int j = 0; j < J; ++j) b += Sh::N[j] * (j == 0 ? 2 : 6);
+  return b;
+}
+
+// Accumulator indices (per block record of NACC doubles):
+//   0, 1 : main sum and its (negated Kahan) compensation, total = [0] + [1]
+//          (data: sum ln S; norm: sum eps S)
+//   2    : number of data events with S <= 0 or non-finite
+//   then per K* slot (spin order) 2 (spin 0) or 6 (lambda = -1, 0, +1) values re/im of
+//   sum w * dS/dH (before the factor 2), then per Z slot 4 values (lambda' = 0, +-1),
+//   then 2 per floating slot (d/dM, d/dGamma0).
+
+template <typename T, class Sh, int MODE>
+__global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
+  constexpr int NK = Sh::NK;
+  constexpr int NZ = Sh::NZ;
+  constexpr bool GRAD = (MODE == MODE_GRAD);
+  using A_t = typename AccType<T>::type;   // per-thread gradient accumulator type
+
+  const int set = (blockIdx.x < (unsigned)a.nb_data) ? 0 : 1;
+  const int64_t blk = set == 0 ? blockIdx.x : blockIdx.x - a.nb_data;
+  const int64_t n = a.n[set];
+  const T* __restrict__ col = a.cols[set];
+  const int64_t ld = a.ld[set];
+  const int64_t e0 = blk * (int64_t)a.chunk;
+  const int64_t e1 = (e0 + a.chunk < n) ? e0 + a.chunk : n;
+
+  double ms = 0.0, mc = 0.0;   // Kahan pair
+  double nbad = 0.0;
+  A_t gk[Sh::NKACC > 0 ? Sh::NKACC : 1];
+  A_t gz[NZ > 0 ? 4 * NZ : 1];
+  A_t gf[2 * NFL];
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int i = 0; i < Sh::NKACC; ++i) gk[i] = 0;
+#pragma unroll
+    for (int i = 0; i < 4 * NZ; ++i) gz[i] = 0;
+#pragma unroll
+    for (int i = 0; i < 2 * NFL; ++i) gf[i] = 0;
+  }
+
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const auto& ka = *kernarg_laundered<AmpArgs<T, Sh>>();
+    const T m = ldnt(col + e), q = ldnt(col + ld + e), pB = ldnt(col + 2 * ld + e);
+    const T cK = ldnt(col + 3 * ld + e), sK = ldnt(col + 4 * ld + e);
+    const T cJ = ldnt(col + 5 * ld + e), sJ = ldnt(col + 6 * ld + e);
+    const T cph = ldnt(col + 7 * ld + e), sph = ldnt(col + 8 * ld + e);
+
+    const T m2 = m * m;
+    const T im = rcp_(m);
+    const T zR = (ka.rR * q) * (ka.rR * q);
+    const T zB = (ka.rB * pB) * (ka.rB * pB);
+    const T qm = q * im;
+    const T pbm = pB * ka.invMB;
+    const T qq = q * q;
+
+    // ---- K* lineshapes (Eq. 2-3) and coupling sums T_{J lambda}
+    Cx<T> Amp[NK > 0 ? NK : 1];
+    T gJv[5] = {T(0), T(0), T(0), T(0), T(0)};   // g_J(m) per spin (width derivative)
+    Cx<T> Tl[5][3];
+#pragma unroll
+    for (int J = 0; J < 5; ++J)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) Tl[J][l] = Cx<T>{T(0), T(0)};
+
+    auto do_spin = [&](auto Jc) {
+      constexpr int J = decltype(Jc)::value;
+      if constexpr (Sh::N[J] > 0) {
+        if (a.cnt[J] > 0) {
+          constexpr int LB = LBof<J>::v;
+          const T BR = bpoly<J>(zR), BB = bpoly<LB>(zB);
+          const T rJ = rsq_(BR * BB);
+          const T nJ = ipow<T, LB>(pbm) * ipow<T, J>(qm) * rJ;
+          const T gJ = qm * ipow<T, J>(qq) * rcp_(BR);
+          gJv[J] = gJ;
+          constexpr int sb = slot_base<Sh>(J);
+#pragma unroll
+          for (int j = 0; j < Sh::N[J]; ++j) {
+            if (j < a.cnt[J]) {
+              const auto& rc = ka.ks[sb + j];
+              const T dre = rc.M2 - m2;
+              const T dim = -rc.P * gJ;
+              const T inv = rcp_(__builtin_fma(dre, dre, dim * dim));
+              const T sc = rc.K * nJ * inv;
+              const T Ar = sc * dre, Ai = -sc * dim;
+              Amp[sb + j] = Cx<T>{Ar, Ai};
+              if constexpr (J == 0) {
+                cmac(Tl[0][1], rc.hr[1], rc.hi[1], Ar, Ai);
+              } else {
+#pragma unroll
+                for (int l = 0; l < 3; ++l) cmac(Tl[J][l], rc.hr[l], rc.hi[l], Ar, Ai);
+              }
+            }
+          }
+        }
+      }
+    };
+    do_spin(std::integral_constant<int, 0>{});
+    do_spin(std::integral_constant<int, 1>{});
+    do_spin(std::integral_constant<int, 2>{});
+    do_spin(std::integral_constant<int, 3>{});
+    do_spin(std::integral_constant<int, 4>{});
+
+    // ---- angular sums (Eq. 4): U_lambda = sum_J d^J_{lambda 0}(theta_K) T_{J lambda}
+    T dd0[5], dd1[5];
+    dd0[0] = T(1); dd1[0] = T(0);
+    dd0[1] = d00<1>(cK); dd1[1] = d10<1>(cK, sK);
+    dd0[2] = d00<2>(cK); dd1[2] = d10<2>(cK, sK);
+    dd0[3] = d00<3>(cK); dd1[3] = d10<3>(cK, sK);
+    dd0[4] = d00<4>(cK); dd1[4] = d10<4>(cK, sK);
+    Cx<T> U0{T(0), T(0)}, Up{T(0), T(0)}, Um{T(0), T(0)};
+#pragma unroll
+    for (int J = 0; J < 5; ++J) {
+      if (Sh::N[J] == 0) continue;
+      U0.re = __builtin_fma(dd0[J], Tl[J][1].re, U0.re);
+      U0.im = __builtin_fma(dd0[J], Tl[J][1].im, U0.im);
+      if (J > 0) {
+        Up.re = __builtin_fma(dd1[J], Tl[J][2].re, Up.re);
+        Up.im = __builtin_fma(dd1[J], Tl[J][2].im, Up.im);
+        Um.re = __builtin_fma(-dd1[J], Tl[J][0].re, Um.re);
+        Um.im = __builtin_fma(-dd1[J], Tl[J][0].im, Um.im);
+      }
+    }
+    // e^{i lambda phi} d^1_{lambda xi}(theta_J):  lambda=+1: (1+c)/2, (1-c)/2;  0: s/sqrt2, -s/sqrt2;
+    // lambda=-1: (1-c)/2, (1+c)/2   for xi = +1, -1
+    const T hp = T(0.5) * (T(1) + cJ), hm = T(0.5) * (T(1) - cJ), s0 = sJ * T(0.70710678118654752440);
+    const Cx<T> eUp{cph * Up.re - sph * Up.im, cph * Up.im + sph * Up.re};
+    const Cx<T> eUm{cph * Um.re + sph * Um.im, cph * Um.im - sph * Um.re};
+    Cx<T> ap{hp * eUp.re + s0 * U0.re + hm * eUm.re, hp * eUp.im + s0 * U0.im + hm * eUm.im};
+    Cx<T> am{hm * eUp.re - s0 * U0.re + hp * eUm.re, hm * eUp.im - s0 * U0.im + hp * eUm.im};
+
+    // ---- Z chain (Eq. 10-12)
+    Cx<T> AZ[NZ > 0 ? NZ : 1];
+    T za[8];
+    T gzv = T(0), dzr[NZ > 0 ? NZ : 1], dzi[NZ > 0 ? NZ : 1], zinv[NZ > 0 ? NZ : 1];
+    if constexpr (NZ > 0) {
+      if (a.cnt[5] > 0) {
+        const T mz2 = ldnt(col + 9 * ld + e), nz = ldnt(col + 10 * ld + e);
+        gzv = ldnt(col + 11 * ld + e);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) za[i] = ldnt(col + (12 + i) * ld + e);
+        Cx<T> T0{T(0), T(0)}, T1{T(0), T(0)};
+#pragma unroll
+        for (int z = 0; z < NZ; ++z) {
+          if (z < a.cnt[5]) {
+            const auto& rc = ka.zs[z];
+            const T dre = rc.M2 - mz2;
+            const T dim = -rc.P * gzv;
+            const T inv = rcp_(__builtin_fma(dre, dre, dim * dim));
+            const T sc = rc.K * nz * inv;
+            AZ[z] = Cx<T>{sc * dre, -sc * dim};
+            dzr[z] = dre; dzi[z] = dim; zinv[z] = inv;
+            cmac(T0, rc.hr[0], rc.hi[0], AZ[z].re, AZ[z].im);
+            cmac(T1, rc.hr[1], rc.hi[1], AZ[z].re, AZ[z].im);
+          }
+        }
+        cmac(ap, T0.re, T0.im, za[0], za[1]);
+        cmac(am, T0.re, T0.im, za[2], za[3]);
+        cmac(ap, T1.re, T1.im, za[4], za[5]);
+        cmac(am, T1.re, T1.im, za[6], za[7]);
+      }
+    }
+
+    const T S = ap.re * ap.re + ap.im * ap.im + am.re * am.re + am.im * am.im;
+
+    if constexpr (MODE == MODE_DENSITY) {
+      a.s_out[set][e] = (double)S;
+      continue;
+    }
+
+    // ---- likelihood terms
+    T w;
+    if (set == 0) {
+      if (!(S > T(0)) || !(S < T(INFINITY))) { nbad += 1.0; continue; }
+      const double x = (double)log_(S);
+      const double y = x - mc;
+      const double t = ms + y;
+      mc = (t - ms) - y;
+      ms = t;
+      w = rcp_(S);
+    } else {
+      const T eps = a.eps ? ldnt(a.eps + e) : T(1);
+      const double x = (double)(eps * S);
+      const double y = x - mc;
+      const double t = ms + y;
+      mc = (t - ms) - y;
+      ms = t;
+      w = eps;
+    }
+
+    if constexpr (GRAD) {
+      // adjoint of S = sum_xi |a_xi|^2: b_xi = w conj(a_xi); W_lambda = sum_xi E_{lambda xi} b_xi
+      const Cx<T> bp{w * ap.re, -w * ap.im}, bm{w * am.re, -w * am.im};
+      const Cx<T> Wp0{hp * bp.re + hm * bm.re, hp * bp.im + hm * bm.im};
+      const Cx<T> Wp{cph * Wp0.re - sph * Wp0.im, cph * Wp0.im + sph * Wp0.re};   // e^{+i phi}
+      const Cx<T> W0{s0 * (bp.re - bm.re), s0 * (bp.im - bm.im)};
+      const Cx<T> Wm0{hm * bp.re + hp * bm.re, hm * bp.im + hp * bm.im};
+      const Cx<T> Wm{cph * Wm0.re + sph * Wm0.im, cph * Wm0.im - sph * Wm0.re};   // e^{-i phi}
+
+      auto grad_spin = [&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        if constexpr (Sh::N[J] > 0) {
+          if (a.cnt[J] > 0) {
+            constexpr int sb = slot_base<Sh>(J);
+            constexpr int ab = acc_base<Sh>(J) - 3;
+            // V_{J lambda} = d^J_{lambda 0} W_lambda
+            const Cx<T> V0{dd0[J] * W0.re, dd0[J] * W0.im};
+            const Cx<T> Vp{dd1[J] * Wp.re, dd1[J] * Wp.im};
+            const Cx<T> Vm{-dd1[J] * Wm.re, -dd1[J] * Wm.im};
+#pragma unroll
+            for (int j = 0; j < Sh::N[J]; ++j) {
+              if (j < a.cnt[J]) {
+                const Cx<T> A = Amp[sb + j];
+                const auto& rc = ka.ks[sb + j];
+                Cx<T> Q{T(0), T(0)};
+                if constexpr (J == 0) {
+                  A_t* g = gk + ab + 2 * j;
+                  g[0] += (A_t)(A.re * V0.re - A.im * V0.im);
+                  g[1] += (A_t)(A.re * V0.im + A.im * V0.re);
+                  if (rc.flt >= 0) cmac(Q, rc.hr[1], rc.hi[1], V0.re, V0.im);
+                } else {
+                  A_t* g = gk + ab + 6 * j;
+                  g[0] += (A_t)(A.re * Vm.re - A.im * Vm.im);
+                  g[1] += (A_t)(A.re * Vm.im + A.im * Vm.re);
+                  g[2] += (A_t)(A.re * V0.re - A.im * V0.im);
+                  g[3] += (A_t)(A.re * V0.im + A.im * V0.re);
+                  g[4] += (A_t)(A.re * Vp.re - A.im * Vp.im);
+                  g[5] += (A_t)(A.re * Vp.im + A.im * Vp.re);
+                  if (rc.flt >= 0) {
+                    cmac(Q, rc.hr[0], rc.hi[0], Vm.re, Vm.im);
+                    cmac(Q, rc.hr[1], rc.hi[1], V0.re, V0.im);
+                    cmac(Q, rc.hr[2], rc.hi[2], Vp.re, Vp.im);
+                  }
+                }
+                if (rc.flt >= 0) {
+                  // X = A Q;  d/dM: Re[X (kappa - (2M - i P' g) conj(den)/|den|^2)]
+                  //           d/dGamma0: Re[X i (P/Gamma0) g conj(den)/|den|^2]
+                  const T Xr = A.re * Q.re - A.im * Q.im, Xi = A.re * Q.im + A.im * Q.re;
+                  const T g_ = gJv[J];
+                  const T dre = rc.M2 - m2, dim = -rc.P * g_;
+                  const T inv = rcp_(__builtin_fma(dre, dre, dim * dim));
+                  // Y = (2M - i P' g)(dre - i dim) inv
+                  const T pr = rc.twoM, pim = -rc.dP * g_;
+                  const T Yr = (pr * dre + pim * dim) * inv;
+                  const T Yi = (pim * dre - pr * dim) * inv;
+                  const T dM = rc.kap * Xr - (Xr * Yr - Xi * Yi);
+                  const T zf = rc.PoG * g_ * inv;
+                  const T dG = zf * (Xr * dim - Xi * dre);
+#pragma unroll
+                  for (int f = 0; f < NFL; ++f)
+                    if (rc.flt == f) { gf[2 * f] += (A_t)dM; gf[2 * f + 1] += (A_t)dG; }
+                }
+              }
+            }
+          }
+        }
+      };
+      grad_spin(std::integral_constant<int, 0>{});
+      grad_spin(std::integral_constant<int, 1>{});
+      grad_spin(std::integral_constant<int, 2>{});
+      grad_spin(std::integral_constant<int, 3>{});
+      grad_spin(std::integral_constant<int, 4>{});
+
+      if constexpr (NZ > 0) {
+        if (a.cnt[5] > 0) {
+          // WZ_{l'} = sum_xi Zang_{l' xi} b_xi
+          const Cx<T> WZ0{za[0] * bp.re - za[1] * bp.im + za[2] * bm.re - za[3] * bm.im,
+                          za[0] * bp.im + za[1] * bp.re + za[2] * bm.im + za[3] * bm.re};
+          const Cx<T> WZ1{za[4] * bp.re - za[5] * bp.im + za[6] * bm.re - za[7] * bm.im,
+                          za[4] * bp.im + za[5] * bp.re + za[6] * bm.im + za[7] * bm.re};
+#pragma unroll
+          for (int z = 0; z < NZ; ++z) {
+            if (z < a.cnt[5]) {
+              const Cx<T> A = AZ[z];
+              A_t* g = gz + 4 * z;
+              g[0] += (A_t)(A.re * WZ0.re - A.im * WZ0.im);
+              g[1] += (A_t)(A.re * WZ0.im + A.im * WZ0.re);
+              g[2] += (A_t)(A.re * WZ1.re - A.im * WZ1.im);
+              g[3] += (A_t)(A.re * WZ1.im + A.im * WZ1.re);
+              const auto& rc = ka.zs[z];
+              if (rc.flt >= 0) {
+                Cx<T> Q{T(0), T(0)};
+                cmac(Q, rc.hr[0], rc.hi[0], WZ0.re, WZ0.im);
+                cmac(Q, rc.hr[1], rc.hi[1], WZ1.re, WZ1.im);
+                const T Xr = A.re * Q.re - A.im * Q.im, Xi = A.re * Q.im + A.im * Q.re;
+                const T dre = dzr[z], dim = dzi[z], inv = zinv[z];
+                const T pr = rc.twoM, pim = -rc.dP * gzv;
+                const T Yr = (pr * dre + pim * dim) * inv;
+                const T Yi = (pim * dre - pr * dim) * inv;
+                const T dM = rc.kap * Xr - (Xr * Yr - Xi * Yi);
+                const T zf = rc.PoG * gzv * inv;
+                const T dG = zf * (Xr * dim - Xi * dre);
+#pragma unroll
+                for (int f = 0; f < NFL; ++f)
+                  if (rc.flt == f) { gf[2 * f] += (A_t)dM; gf[2 * f + 1] += (A_t)dG; }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+
+  if constexpr (MODE == MODE_DENSITY) return;
+
+  // ---- block reduction: wave transpose-butterfly, then the 4 waves in order
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double red[4][NACC];
+  if constexpr (GRAD) {
+    // accumulator i of this lane as double (compile-time index after unrolling)
+    auto accv = [&](int i) -> double {
+      if (i == 0) return ms;
+      if (i == 1) return -mc;   // Kahan: the running sum exceeds the exact one by mc
+      if (i == 2) return nbad;
+      if (i < 3 + Sh::NKACC) return (double)gk[i - 3];
+      if (i < 3 + Sh::NKACC + 4 * NZ) return (double)gz[i - 3 - Sh::NKACC];
+      if (i < 3 + Sh::NKACC + 4 * NZ + 2 * NFL) return (double)gf[i - 3 - Sh::NKACC - 4 * NZ];
+      return 0.0;
+    };
+    // Transpose butterfly: after the step of width h, lane l keeps h values, each summed
+    // with its partner lane's; after the last step lane l holds the wave sum of value l.
+    // The first step reads the typed accumulators directly so that at most 32 doubles are
+    // live at once.
+    double v[32];
+    {
+      const bool up = (lane >> 5) & 1;
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        const double lo = accv(i), hi = accv(i + 32);
+        const double keep = up ? hi : lo;
+        const double send = up ? lo : hi;
+        v[i] = keep + __shfl_xor(send, 32, 64);
+      }
+    }
+#pragma unroll
+    for (int s = 4; s >= 0; --s) {
+      const int half = 1 << s;
+      const bool up = (lane >> s) & 1;
+#pragma unroll
+      for (int i = 0; i < half; ++i) {
+        const double keep = up ? v[i + half] : v[i];
+        const double send = up ? v[i] : v[i + half];
+        v[i] = keep + __shfl_xor(send, half, 64);
+      }
+    }
+    red[wave][lane] = v[0];
+  } else {
+    double v0 = ms, v1 = -mc, v2 = nbad;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+      v0 += __shfl_xor(v0, s, 64);
+      v1 += __shfl_xor(v1, s, 64);
+      v2 += __shfl_xor(v2, s, 64);
+    }
+    if (lane < NACC) red[wave][lane] = (lane == 0) ? v0 : (lane == 1 ? v1 : (lane == 2 ? v2 : 0.0));
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const double t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    a.partial[(int64_t)blockIdx.x * NACC + lane] = t;
+  }
+}
+
+// Fixed-order Neumaier sum of the block partials: block 0 reduces the data blocks,
+// block 1 the normalisation blocks; thread t sums value t%64 over blocks t/64, t/64+4, ...
+__global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ partial, int nb_data, int nb_mc,
+                                                    double* __restrict__ out) {
+  const int set = blockIdx.x;
+  const int v = threadIdx.x & 63, sub = threadIdx.x >> 6;
+  const int b0 = set ? nb_data : 0;
+  const int nb = set ? nb_mc : nb_data;
+  double s = 0.0, c = 0.0;
+  for (int b = sub; b < nb; b += 4) {
+    const double x = partial[(int64_t)(b0 + b) * NACC + v];
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  __shared__ double S[4][NACC], C[4][NACC];
+  S[sub][v] = s;
+  C[sub][v] = c;
+  __syncthreads();
+  if (sub == 0) {
+    double ts = 0.0, tc = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      const double x = S[k][v];
+      const double t = ts + x;
+      tc += (fabs(ts) >= fabs(x)) ? (ts - t) + x : (x - t) + ts;
+      ts = t;
+      tc += C[k][v];
+    }
+    out[set * NACC + v] = ts + tc;
+  }
+}
+
+// ------------------------------------------------------------------ efficiency histogram
+__global__ __launch_bounds__(256) void hist_lookup_kernel(HistArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.n) return;
+  int64_t idx = 0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const double x = a.obs[d][e];
+    int b = (int)floor((x - a.lo[d]) / (a.hi[d] - a.lo[d]) * a.nb[d]);
+    b = b < 0 ? 0 : (b >= a.nb[d] ? a.nb[d] - 1 : b);
+    idx = idx * a.nb[d] + b;
+  }
+  a.out_f64[e] = (double)a.table[idx];
+}
+
+// ------------------------------------------------------------------ generators
+// Philox4x32-10 from its published definition (Salmon et al., SC'11).
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+  }
+}
+__device__ __forceinline__ void u2(uint64_t e, uint32_t w2, uint32_t w3, uint64_t seed, double& ua, double& ub) {
+  uint32_t c[4] = {(uint32_t)e, (uint32_t)(e >> 32), w2, w3};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  ua = (double)(((uint64_t)(c[0] >> 5) << 26) | (uint64_t)(c[1] >> 6)) * (1.0 / 9007199254740992.0);
+  ub = (double)(((uint64_t)(c[2] >> 5) << 26) | (uint64_t)(c[3] >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+#pragma clang fp contract(off)
+// Phase-space event e: m_Kpi by accept-reject on p_B(m) q(m) < u * wmax with trial t drawn
+// from counter (e, t, 0); angles from counters (e, 0, 1) and (e, 0, 2).  The acceptance
+// test is evaluated without contraction so it is bit-identical to a plain FP64 host.
+__device__ int phsp_event(const GenArgs& a, uint64_t e, double* ev, double* spare) {
+  const double lo = a.mK + a.mPi, hi = a.mB - a.mJ;
+  const double c1 = (a.mK + a.mPi) * (a.mK + a.mPi), c2 = (a.mK - a.mPi) * (a.mK - a.mPi);
+  double ua, ub;
+  for (int t = 0; t < 4096; ++t) {
+    u2(e, (uint32_t)t, 0u, a.seed, ua, ub);
+    const double m = lo + (hi - lo) * ua;
+    // p_B(m) = sqrt((mB^2 - (mJ+m)^2)(mB^2 - (mJ-m)^2)) / (2 mB);  q(m) analogous
+    const double s = a.mB * a.mB;
+    const double pa = s - (a.mJ + m) * (a.mJ + m);
+    const double pb = s - (a.mJ - m) * (a.mJ - m);
+    const double px = pa * pb;
+    const double pB = px <= 0.0 ? 0.0 : sqrt(px) / (2.0 * a.mB);
+    const double mm = m * m;
+    const double qa = mm - c1;
+    const double qb = mm - c2;
+    const double qx = qa * qb;
+    const double q = qx <= 0.0 ? 0.0 : sqrt(qx) / (2.0 * m);
+    if (ub * a.wmax < pB * q) {
+      ev[0] = m;
+      u2(e, 0u, 1u, a.seed, ua, ub);
+      ev[1] = 2.0 * ua - 1.0;
+      ev[2] = 2.0 * ub - 1.0;
+      u2(e, 0u, 2u, a.seed, ua, ub);
+      ev[3] = 3.14159265358979323846 * (2.0 * ua - 1.0);
+      *spare = ub;
+      return t + 1;
+    }
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(256) void phsp_kernel(GenArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  double ev[4], sp;
+  const int t = phsp_event(a, (uint64_t)(a.e0 + i), ev, &sp);
+  if (t < 0) { a.flag[i] = 0; a.out[0][i] = NAN; return; }
+  a.out[0][i] = ev[0];
+  a.out[1][i] = ev[1];
+  a.out[2][i] = ev[2];
+  a.out[3][i] = ev[3];
+  if (a.spare) a.spare[i] = sp;
+  a.flag[i] = 1;
+}
+
+// Seeded analytic acceptance (same definition as the generator's truth efficiency):
+// eps = 0.9 prod_d (1 - delta (1 - t_d)/2), t_d = sum_l a_dl P_l(u_d) / sum_l |a_dl|.
+__device__ double acceptance(const double* co, double delta, double lo, double hi, double m, double cK, double cJ,
+                             double ph) {
+  const double u[4] = {2.0 * (m - lo) / (hi - lo) - 1.0, cK, cJ, ph / 3.14159265358979323846};
+  double eps = 0.9;
+  for (int d = 0; d < 4; ++d) {
+    const double x = u[d];
+    const double P1 = x, P2 = 0.5 * (3.0 * x * x - 1.0), P3 = 0.5 * (5.0 * x * x * x - 3.0 * x);
+    const double num = co[3 * d] * P1 + co[3 * d + 1] * P2 + co[3 * d + 2] * P3;
+    const double den = fabs(co[3 * d]) + fabs(co[3 * d + 1]) + fabs(co[3 * d + 2]);
+    const double t = den > 0.0 ? num / den : 0.0;
+    eps *= 1.0 - delta * (1.0 - t) / 2.0;
+  }
+  return eps;
+}
+#pragma clang fp contract(on)
+
+// Accept flags of proposals: flag = spare * smax < eps * S (S from the density kernel).
+__global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  if (!a.valid[i]) { a.flag[i] = 0; return; }
+  double s = a.S[i];
+  if (a.acc_on) {
+    s *= acceptance(a.coef, a.delta, a.lo, a.hi, a.obs[0][i], a.obs[1][i], a.obs[2][i], a.obs[3][i]);
+  }
+  a.over[i] = (s > a.smax) ? 1 : 0;
+  a.flag[i] = (a.spare[i] * a.smax < s) ? 1 : 0;
+}
+
+// Stable compaction of accepted proposals: pos = exclusive prefix sum of flags (computed by
+// the caller), write accepted events to out[base + pos] while pos < limit.
+__global__ __launch_bounds__(256) void compact_kernel(CompactArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n || !a.flag[i]) return;
+  const int64_t p = a.base + a.pos[i];
+  if (p >= a.limit) return;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) a.out[d][p] = a.obs[d][i];
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T> hipError_t launch_invariants(const InvArgs<T>& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((a.n + 255) / 256);
+  hipLaunchKernelGGL(invariants_kernel<T>, dim3(nb), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+template hipError_t launch_invariants<float>(const InvArgs<float>&, hipStream_t);
+template hipError_t launch_invariants<double>(const InvArgs<double>&, hipStream_t);
+
+template <typename T, class Sh>
+hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (mode == MODE_GRAD) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_GRAD>), dim3(nblocks), dim3(256), 0, st, a);
+  else if (mode == MODE_NLL) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_NLL>), dim3(nblocks), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_DENSITY>), dim3(nblocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+template hipError_t launch_amp<float, ShapeSmall>(const AmpArgs<float, ShapeSmall>&, int, int, hipStream_t);
+template hipError_t launch_amp<double, ShapeSmall>(const AmpArgs<double, ShapeSmall>&, int, int, hipStream_t);
+template hipError_t launch_amp<float, ShapeFull>(const AmpArgs<float, ShapeFull>&, int, int, hipStream_t);
+template hipError_t launch_amp<double, ShapeFull>(const AmpArgs<double, ShapeFull>&, int, int, hipStream_t);
+
+hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_final, dim3(2), dim3(256), 0, st, partial, nb_data, nb_mc, out);
+  return hipGetLastError();
+}
+hipError_t launch_hist_lookup(const HistArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hist_lookup_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_phsp(const GenArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(phsp_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_accept(const AcceptArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(accept_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_compact(const CompactArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace kpsi

@@ -1,0 +1,112 @@
+// Internal declarations shared by the device code and the host runtime of libkpsi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kpsi {
+
+constexpr int BLOCK = 256;      // threads per block (4 wavefronts of 64)
+constexpr int NACC = 64;        // doubles per block partial (one per lane of a wavefront)
+constexpr int NFL = 2;          // floating (M, Gamma0) slots in the adjoint
+constexpr int NCOL_KSTAR = 9;   // per-event columns of the K* chain
+constexpr int NCOL_Z = 11;      // extra per-event columns of the Z chain
+constexpr int NCOL_MAX = NCOL_KSTAR + NCOL_Z;
+
+enum { MODE_DENSITY = 0, MODE_NLL = 1, MODE_GRAD = 2 };
+
+// Per-resonance constants of one call (host-computed in double, stored as T).
+//   den(m) = M2 - m^2 - i P g(m),  A(m) = K n(m) / den(m)
+template <typename T> struct RC {
+  T M2, P, K;
+  T hr[3], hi[3];     // K*: lambda = -1, 0, +1; Z: [0] lambda' = 0, [1] lambda' = +-1
+  T kap, twoM, dP, PoG;   // d ln K/dM, 2M, dP/dM, P/Gamma0
+  int flt;            // floating slot or -1
+};
+
+// Compile-time capacity of a kernel instantiation: K* slots per spin 0..4 and Z slots.
+template <int N0, int N1, int N2, int N3, int N4, int NZ_> struct Shape {
+  static constexpr int N[5] = {N0, N1, N2, N3, N4};
+  static constexpr int NK = N0 + N1 + N2 + N3 + N4;
+  static constexpr int NZ = NZ_;
+  static constexpr int NKACC = 2 * N0 + 6 * (N1 + N2 + N3 + N4);
+  static_assert(3 + NKACC + 4 * NZ_ + 2 * NFL <= NACC, "accumulators exceed the block record");
+};
+using ShapeSmall = Shape<0, 1, 0, 0, 0, 0>;   // one spin-1 K*
+using ShapeFull = Shape<3, 3, 2, 1, 1, 2>;    // the ten K* of the paper and two Z
+
+template <typename T> struct AccType { using type = T; };
+
+template <typename T, class Sh> struct AmpArgs {
+  const T* cols[2];     // data, normalisation column bases
+  int64_t ld[2];        // column strides (elements)
+  int64_t n[2];         // events per set
+  const T* eps;         // per-normalisation-event efficiency, or null (flat)
+  double* partial;      // [blocks][NACC]
+  double* s_out[2];     // density mode: per-event S of each set
+  int nb_data;          // blocks of the data set; the rest cover the normalisation set
+  int chunk;            // events per block
+  int cnt[6];           // slots in use per spin 0..4 and Z
+  T rR, rB, invMB;
+  RC<T> ks[Sh::NK > 0 ? Sh::NK : 1];
+  RC<T> zs[Sh::NZ > 0 ? Sh::NZ : 1];
+};
+
+template <typename T> struct InvArgs {
+  const double* obs[4];   // m_Kpi, cos theta_K*, cos theta_J/psi, phi
+  T* cols;
+  int64_t ld, n;
+  double mB, mJ, mK, mPi, rB, rR;
+  int with_z;
+  double* diag;           // optional (n, 5) output: m_Jpsi pi, cos theta_Z, cos theta~, phi~, alpha
+};
+
+struct HistArgs {
+  const double* obs[4];
+  const float* table;
+  int nb[4];
+  double lo[4], hi[4];
+  int64_t n;
+  double* out_f64;
+};
+
+struct GenArgs {
+  uint64_t seed;
+  int64_t e0, n;
+  double wmax, mB, mJ, mK, mPi;
+  double* out[4];
+  double* spare;
+  int* flag;
+};
+
+struct AcceptArgs {
+  const double* obs[4];
+  const double* S;
+  const double* spare;
+  const int* valid;
+  int acc_on;
+  double coef[12];
+  double delta, lo, hi, smax;
+  int64_t n;
+  int* flag;
+  int* over;
+};
+
+struct CompactArgs {
+  const double* obs[4];
+  const int* flag;
+  const int* pos;
+  int64_t n, base, limit;
+  double* out[4];
+};
+
+template <typename T> hipError_t launch_invariants(const InvArgs<T>& a, hipStream_t st);
+template <typename T, class Sh> hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st);
+hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, double* out, hipStream_t st);
+hipError_t launch_hist_lookup(const HistArgs& a, hipStream_t st);
+hipError_t launch_phsp(const GenArgs& a, hipStream_t st);
+hipError_t launch_accept(const AcceptArgs& a, hipStream_t st);
+hipError_t launch_compact(const CompactArgs& a, hipStream_t st);
+hipError_t exclusive_scan_int(const int* in, int* out, int64_t n, void* tmp, size_t* tmp_bytes, hipStream_t st);
+
+}  // namespace kpsi

@@ -1,0 +1,926 @@
+// Host runtime of libkpsi: the C ABI of include/kpsi.h.
+//
+// Owns the device buffers of a context (event columns, efficiency, block partials,
+// pinned result staging), packs the fit parameters into per-resonance constants,
+// launches the per-event kernel and the final reduction on the context stream, and
+// assembles -2 ln L and its gradient from the reduced sums.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kpsi.h"
+#include "kpsi_internal.h"
+
+using namespace kpsi;
+
+namespace {
+
+struct DevSet {
+  int64_t n = 0;
+  const double* obs[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* owned = nullptr;      // owned FP64 copy (4 columns)
+  void* cols = nullptr;         // derived columns (T)
+  int64_t ld = 0;
+  size_t cols_cap = 0;
+};
+
+std::string g_create_error;
+
+}  // namespace
+
+struct kpsi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  kpsi_precision prec = KPSI_FP64;
+  bool has_model = false;
+  kpsi_kinematics kin{};
+  std::vector<kpsi_resonance> res;
+  int shape = 0;                // 0: ShapeSmall, 1: ShapeFull
+  std::vector<int> slot;        // table index -> K* slot index, or Z index
+  std::vector<int> coff;        // table index -> coupling offset in the parameter vector
+  int cnt[6] = {0, 0, 0, 0, 0, 0};
+  int nparams = 0;
+  bool has_z = false;
+  std::vector<int> fslot;       // table index -> floating slot or -1
+  DevSet set[2];
+  void* eps = nullptr;          // T array over the normalisation set, or null (flat)
+  double* partial = nullptr;
+  size_t partial_cap = 0;       // in doubles
+  double* red = nullptr;        // [2][NACC]
+  double* red_host = nullptr;   // pinned
+  std::string err;
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double t_ms = 0.0;
+  int64_t t_n = 0;
+  int ept_override = 0;
+};
+
+namespace {
+
+kpsi_status fail(kpsi_ctx* c, kpsi_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf; else g_create_error = buf;
+  return s;
+}
+
+#define HIPCHECK(c, call)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) return fail((c), KPSI_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t tsize(const kpsi_ctx* c) { return c->prec == KPSI_FP32 ? sizeof(float) : sizeof(double); }
+
+int lowest_lb(const kpsi_resonance& r) { return r.chain == 0 ? (r.spin == 0 ? 1 : r.spin - 1) : 1; }
+int lowest_lr(const kpsi_resonance& r) { return r.chain == 0 ? r.spin : 0; }
+int ncoup(const kpsi_resonance& r) { return r.chain == 0 ? (r.spin == 0 ? 1 : 3) : 2; }
+
+// ---------------------------------------------------------------- lineshape constants
+// A(m) = K n(m) / (M^2 - m^2 - i P g(m)) reproduces Eq. (2)-(3) with the per-event
+// factors n(m) = (p_B/M_B)^LB (q/m)^LR / sqrt(B_LB(z_B) B_LR(z_R)) and
+// g(m) = q^(2LR+1) / (m B_LR(z_R)); here K = sqrt(B_LB(z_B0) B_LR(z_R0)) and
+// P = Gamma0 M^2 B_LR(z_R0) / q0^(2LR+1), plus their M derivatives.
+struct LsConst { double M2, P, K, kap, twoM, dP, PoG; };
+
+double bpoly(int L, double z) {
+  switch (L) {
+    case 0: return 1.0;
+    case 1: return 1.0 + z;
+    case 2: return 9.0 + z * (3.0 + z);
+    case 3: return 225.0 + z * (45.0 + z * (6.0 + z));
+    default: return 11025.0 + z * (1575.0 + z * (135.0 + z * (10.0 + z)));
+  }
+}
+double dbpoly(int L, double z) {
+  switch (L) {
+    case 0: return 0.0;
+    case 1: return 1.0;
+    case 2: return 3.0 + 2.0 * z;
+    case 3: return 45.0 + z * (12.0 + 3.0 * z);
+    default: return 1575.0 + z * (270.0 + z * (30.0 + 4.0 * z));
+  }
+}
+
+LsConst lineshape_consts(const kpsi_kinematics& k, const kpsi_resonance& r, double M, double G0) {
+  const int LR = lowest_lr(r), LB = lowest_lb(r);
+  double m1, m2, mp;
+  if (r.chain == 0) { m1 = k.m_k; m2 = k.m_pi; mp = k.m_jpsi; }
+  else { m1 = k.m_jpsi; m2 = k.m_pi; mp = k.m_k; }
+  const double a2 = (m1 + m2) * (m1 + m2), b2 = (m1 - m2) * (m1 - m2);
+  const double f = (M * M - a2) * (M * M - b2);
+  const double sf = std::sqrt(std::fmax(f, 0.0));
+  const double q0 = sf / (2.0 * M);
+  const double dq0 = (2.0 * M * M - a2 - b2) / (2.0 * sf) - q0 / M;
+  const double mB2 = k.m_b * k.m_b;
+  const double u = mB2 - (mp + M) * (mp + M), v = mB2 - (mp - M) * (mp - M);
+  const double h = u * v;
+  const double sh = std::sqrt(std::fmax(h, 0.0));
+  const double pB0 = sh / (2.0 * k.m_b);
+  const double dh = -2.0 * (mp + M) * v + 2.0 * (mp - M) * u;
+  const double dpB0 = dh / (4.0 * k.m_b * sh);
+  const double zR0 = (k.r_r * q0) * (k.r_r * q0), dzR0 = 2.0 * k.r_r * k.r_r * q0 * dq0;
+  const double zB0 = (k.r_b * pB0) * (k.r_b * pB0), dzB0 = 2.0 * k.r_b * k.r_b * pB0 * dpB0;
+  const double BR0 = bpoly(LR, zR0), dBR0 = dbpoly(LR, zR0);
+  const double BB0 = bpoly(LB, zB0), dBB0 = dbpoly(LB, zB0);
+  LsConst c;
+  c.M2 = M * M;
+  c.twoM = 2.0 * M;
+  c.K = std::sqrt(BB0 * BR0);
+  c.kap = 0.5 * (dBB0 * dzB0 / BB0 + dBR0 * dzR0 / BR0);
+  double q0p = 1.0;
+  for (int i = 0; i < 2 * LR + 1; ++i) q0p *= q0;
+  c.PoG = M * M * BR0 / q0p;
+  c.P = G0 * c.PoG;
+  c.dP = c.P * (2.0 / M + dBR0 * dzR0 / BR0 - (2 * LR + 1) * dq0 / q0);
+  return c;
+}
+
+template <typename T> void fill_rc(RC<T>& rc, const LsConst& c, const double* hr, const double* hi, int nl, int flt) {
+  rc.M2 = (T)c.M2; rc.P = (T)c.P; rc.K = (T)c.K;
+  for (int l = 0; l < 3; ++l) { rc.hr[l] = (T)(l < nl ? hr[l] : 0.0); rc.hi[l] = (T)(l < nl ? hi[l] : 0.0); }
+  rc.kap = (T)c.kap; rc.twoM = (T)c.twoM; rc.dP = (T)c.dP; rc.PoG = (T)c.PoG;
+  rc.flt = flt;
+}
+
+// Pack the canonical parameter vector into kernel arguments.
+template <typename T, class Sh> void pack(const kpsi_ctx* c, const double* par, AmpArgs<T, Sh>& a) {
+  const int ncr = c->nparams - 2 * (int)c->res.size();
+  for (size_t i = 0; i < c->res.size(); ++i) {
+    const kpsi_resonance& r = c->res[i];
+    const double M = par[ncr + 2 * i], G = par[ncr + 2 * i + 1];
+    LsConst lc = lineshape_consts(c->kin, r, M, G);
+    const double* p = par + c->coff[i];
+    double hr[3], hi[3];
+    int nl;
+    if (r.chain == 0) {
+      if (r.spin == 0) {   // only lambda = 0, stored in the middle slot
+        hr[0] = hi[0] = hr[2] = hi[2] = 0.0;
+        hr[1] = p[0] * std::cos(p[1]); hi[1] = p[0] * std::sin(p[1]);
+      } else {
+        for (int l = 0; l < 3; ++l) { hr[l] = p[2 * l] * std::cos(p[2 * l + 1]); hi[l] = p[2 * l] * std::sin(p[2 * l + 1]); }
+      }
+      nl = 3;
+      fill_rc(a.ks[c->slot[i]], lc, hr, hi, nl, c->fslot[i]);
+    } else {
+      for (int l = 0; l < 2; ++l) { hr[l] = p[2 * l] * std::cos(p[2 * l + 1]); hi[l] = p[2 * l] * std::sin(p[2 * l + 1]); }
+      nl = 2;
+      fill_rc(a.zs[c->slot[i]], lc, hr, hi, nl, c->fslot[i]);
+    }
+  }
+  for (int j = 0; j < 6; ++j) a.cnt[j] = c->cnt[j];
+  a.rR = (T)c->kin.r_r;
+  a.rB = (T)c->kin.r_b;
+  a.invMB = (T)(1.0 / c->kin.m_b);
+}
+
+// Accumulator offset of the couplings of table resonance i inside the block record.
+int acc_offset(const kpsi_ctx* c, size_t i, const int* N) {
+  const kpsi_resonance& r = c->res[i];
+  int nkacc = 0;
+  for (int j = 0; j < 5; ++j) nkacc += N[j] * (j == 0 ? 2 : 6);
+  if (r.chain == 1) return 3 + nkacc + 4 * c->slot[i];
+  int off = 3, base = 0;
+  for (int j = 0; j < r.spin; ++j) { off += N[j] * (j == 0 ? 2 : 6); base += N[j]; }
+  return off + (c->slot[i] - base) * (r.spin == 0 ? 2 : 6);
+}
+
+int shape_counts(int shape, int* N, int* NZ) {
+  if (shape == 0) { int n[5] = {0, 1, 0, 0, 0}; for (int j = 0; j < 5; ++j) N[j] = n[j]; *NZ = 0; }
+  else { int n[5] = {3, 3, 2, 1, 1}; for (int j = 0; j < 5; ++j) N[j] = n[j]; *NZ = 2; }
+  return 0;
+}
+
+kpsi_status ensure_partial(kpsi_ctx* c, size_t nblocks) {
+  const size_t need = nblocks * NACC;
+  if (need <= c->partial_cap) return KPSI_OK;
+  if (c->partial) hipFree(c->partial);
+  c->partial = nullptr;
+  c->partial_cap = 0;
+  if (hipMalloc(&c->partial, need * sizeof(double)) != hipSuccess) return fail(c, KPSI_E_OOM, "partial buffer");
+  c->partial_cap = need;
+  return KPSI_OK;
+}
+
+// Events per thread: enough blocks to fill 256 compute units several times over while
+// keeping each thread's accumulators busy over many events.
+int pick_ept(const kpsi_ctx* c, int64_t n_total) {
+  if (c->ept_override > 0) return c->ept_override;
+  const int64_t target_blocks = 2048;
+  int64_t ept = (n_total + (int64_t)BLOCK * target_blocks - 1) / ((int64_t)BLOCK * target_blocks);
+  if (ept < 1) ept = 1;
+  if (ept > 64) ept = 64;
+  return (int)ept;
+}
+
+kpsi_status derive_columns(kpsi_ctx* c, int s) {
+  DevSet& d = c->set[s];
+  if (d.n == 0 || !c->has_model) return KPSI_OK;
+  const int ncol = NCOL_KSTAR + (c->has_z ? NCOL_Z : 0);
+  const int64_t ld = (d.n + 63) / 64 * 64;
+  const size_t bytes = (size_t)ld * ncol * tsize(c);
+  if (bytes > d.cols_cap) {
+    if (d.cols) hipFree(d.cols);
+    d.cols = nullptr;
+    d.cols_cap = 0;
+    if (hipMalloc(&d.cols, bytes) != hipSuccess) return fail(c, KPSI_E_OOM, "event columns (%zu bytes)", bytes);
+    d.cols_cap = bytes;
+  }
+  d.ld = ld;
+  auto go = [&](auto tag) -> hipError_t {
+    using T = decltype(tag);
+    InvArgs<T> a{};
+    for (int j = 0; j < 4; ++j) a.obs[j] = d.obs[j];
+    a.cols = (T*)d.cols;
+    a.ld = ld;
+    a.n = d.n;
+    a.mB = c->kin.m_b; a.mJ = c->kin.m_jpsi; a.mK = c->kin.m_k; a.mPi = c->kin.m_pi;
+    a.rB = c->kin.r_b; a.rR = c->kin.r_r;
+    a.with_z = c->has_z ? 1 : 0;
+    a.diag = nullptr;
+    return launch_invariants<T>(a, c->stream);
+  };
+  hipError_t e = c->prec == KPSI_FP32 ? go(float{}) : go(double{});
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "invariants kernel: %s", hipGetErrorString(e));
+  return KPSI_OK;
+}
+
+__global__ void validate_kernel(const double* m, const double* ck, const double* cj, const double* ph, int64_t n,
+                                double lo, double hi, unsigned int* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double tol = 1e-12;
+  const bool ok = (m[i] >= lo - tol) && (m[i] <= hi + tol) && (fabs(ck[i]) <= 1.0 + tol) &&
+                  (fabs(cj[i]) <= 1.0 + tol) && (fabs(ph[i]) <= 3.14159265358979323846 + tol);
+  if (!ok) atomicOr(bad, 1u);
+}
+
+template <typename T> __global__ void to_t_kernel(const double* in, T* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (T)in[i];
+}
+
+kpsi_status validate(kpsi_ctx* c, int64_t n, const double* const* obs) {
+  if (n == 0) return KPSI_OK;
+  unsigned int* bad = nullptr;
+  HIPCHECK(c, hipMalloc(&bad, sizeof(unsigned int)));
+  hipMemsetAsync(bad, 0, sizeof(unsigned int), c->stream);
+  const double lo = c->kin.m_k + c->kin.m_pi, hi = c->kin.m_b - c->kin.m_jpsi;
+  hipLaunchKernelGGL(validate_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, obs[0], obs[1],
+                     obs[2], obs[3], n, lo, hi, bad);
+  unsigned int h = 0;
+  hipMemcpyAsync(&h, bad, sizeof h, hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  hipFree(bad);
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "validation: %s", hipGetErrorString(e));
+  if (h) return fail(c, KPSI_E_ARG, "event outside the physical region (m in [%.6f, %.6f], |cos| <= 1, |phi| <= pi)",
+                     lo, hi);
+  return KPSI_OK;
+}
+
+// ---------------------------------------------------------------- per-call driver
+template <typename T, class Sh>
+kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: both*/, double** dens_out) {
+  AmpArgs<T, Sh> a{};
+  for (int s = 0; s < 2; ++s) {
+    a.cols[s] = (const T*)c->set[s].cols;
+    a.ld[s] = c->set[s].ld;
+    a.n[s] = c->set[s].n;
+    a.s_out[s] = dens_out ? dens_out[s] : nullptr;
+  }
+  a.eps = (const T*)c->eps;
+  pack<T, Sh>(c, par, a);
+  int64_t nd = (which == 1) ? 0 : c->set[0].n, nm = (which == 0) ? 0 : c->set[1].n;
+  const int ept = pick_ept(c, nd + nm);
+  a.chunk = BLOCK * ept;
+  const int nbd = (int)((nd + a.chunk - 1) / a.chunk), nbm = (int)((nm + a.chunk - 1) / a.chunk);
+  a.nb_data = nbd;
+  if (mode != MODE_DENSITY) {
+    kpsi_status st = ensure_partial(c, (size_t)(nbd + nbm));
+    if (st) return st;
+  }
+  a.partial = c->partial;
+  if (c->timing && mode != MODE_DENSITY) hipEventRecord(c->ev0, c->stream);
+  hipError_t e = launch_amp<T, Sh>(a, mode, nbd + nbm, c->stream);
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "amplitude kernel: %s", hipGetErrorString(e));
+  if (c->timing && mode != MODE_DENSITY) hipEventRecord(c->ev1, c->stream);
+  if (mode == MODE_DENSITY) return KPSI_OK;
+  e = launch_reduce_final(c->partial, nbd, nbm, c->red, c->stream);
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "reduction kernel: %s", hipGetErrorString(e));
+  HIPCHECK(c, hipMemcpyAsync(c->red_host, c->red, 2 * NACC * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  if (c->timing) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) { c->t_ms += ms; c->t_n += 1; }
+  }
+  return KPSI_OK;
+}
+
+kpsi_status dispatch(kpsi_ctx* c, int mode, const double* par, int which, double** dens) {
+  if (c->prec == KPSI_FP32) {
+    return c->shape == 0 ? run_amp<float, ShapeSmall>(c, mode, par, which, dens)
+                         : run_amp<float, ShapeFull>(c, mode, par, which, dens);
+  }
+  return c->shape == 0 ? run_amp<double, ShapeSmall>(c, mode, par, which, dens)
+                       : run_amp<double, ShapeFull>(c, mode, par, which, dens);
+}
+
+kpsi_status check_ready(kpsi_ctx* c, const double* params) {
+  if (!c) return KPSI_E_ARG;
+  if (!params) return fail(c, KPSI_E_ARG, "params is NULL");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set");
+  if (c->set[0].n <= 0) return fail(c, KPSI_E_STATE, "no data events loaded");
+  if (c->set[1].n <= 0) return fail(c, KPSI_E_STATE, "no normalisation events loaded");
+  for (int i = 0; i < c->nparams; ++i)
+    if (!std::isfinite(params[i])) return fail(c, KPSI_E_ARG, "parameter %d is not finite", i);
+  const int ncr = c->nparams - 2 * (int)c->res.size();
+  for (size_t i = 0; i < c->res.size(); ++i) {
+    const double M = params[ncr + 2 * i], G = params[ncr + 2 * i + 1];
+    const kpsi_resonance& r = c->res[i];
+    const double thr = r.chain == 0 ? c->kin.m_k + c->kin.m_pi : c->kin.m_jpsi + c->kin.m_pi;
+    const double top = r.chain == 0 ? c->kin.m_b - c->kin.m_jpsi : c->kin.m_b - c->kin.m_k;
+    if (!(M > thr) || !(M < top)) return fail(c, KPSI_E_ARG, "mass of resonance %zu outside (%.5f, %.5f)", i, thr, top);
+    if (!(G > 0.0)) return fail(c, KPSI_E_ARG, "width of resonance %zu not positive", i);
+  }
+  return KPSI_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+kpsi_status kpsi_create(int device, void* stream, kpsi_precision prec, kpsi_ctx** out) {
+  if (!out) return fail(nullptr, KPSI_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (prec != KPSI_FP64 && prec != KPSI_FP32) return fail(nullptr, KPSI_E_ARG, "unknown precision %d", (int)prec);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(nullptr, KPSI_E_HIP, "no HIP device");
+  if (device < 0 || device >= ndev) return fail(nullptr, KPSI_E_ARG, "device %d out of range", device);
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, KPSI_E_HIP, "hipSetDevice failed");
+  kpsi_ctx* c = new kpsi_ctx();
+  c->device = device;
+  c->prec = prec;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(nullptr, KPSI_E_HIP, "stream creation failed");
+    }
+    c->own_stream = true;
+  }
+  if (hipMalloc(&c->red, 2 * NACC * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&c->red_host, 2 * NACC * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    kpsi_destroy(c);
+    return fail(nullptr, KPSI_E_OOM, "result buffers");
+  }
+  hipEventCreate(&c->ev0);
+  hipEventCreate(&c->ev1);
+  *out = c;
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_destroy(kpsi_ctx* c) {
+  if (!c) return KPSI_E_ARG;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  for (int s = 0; s < 2; ++s) {
+    if (c->set[s].owned) hipFree(c->set[s].owned);
+    if (c->set[s].cols) hipFree(c->set[s].cols);
+  }
+  if (c->eps) hipFree(c->eps);
+  if (c->partial) hipFree(c->partial);
+  if (c->red) hipFree(c->red);
+  if (c->red_host) hipHostFree(c->red_host);
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_set_model(kpsi_ctx* c, const kpsi_kinematics* kin, const kpsi_resonance* res, int n_res) {
+  if (!c) return KPSI_E_ARG;
+  if (!kin || !res || n_res <= 0) return fail(c, KPSI_E_ARG, "kinematics/resonances missing");
+  const kpsi_kinematics& k = *kin;
+  if (!(k.m_b > k.m_jpsi + k.m_k + k.m_pi) || !(k.m_k > 0) || !(k.m_pi > 0) || !(k.m_jpsi > 0) || !(k.r_b >= 0) ||
+      !(k.r_r >= 0))
+    return fail(c, KPSI_E_ARG, "unphysical kinematics");
+  int counts[5] = {0, 0, 0, 0, 0}, nz = 0;
+  for (int i = 0; i < n_res; ++i) {
+    const kpsi_resonance& r = res[i];
+    if (r.chain == 0) {
+      if (r.spin < 0 || r.spin > 4) return fail(c, KPSI_E_UNSUPPORTED, "K* spin %d not in 0..4", r.spin);
+      counts[r.spin]++;
+    } else if (r.chain == 1) {
+      if (r.spin != 1 || r.parity != 1) return fail(c, KPSI_E_UNSUPPORTED, "only 1+ Z states are supported");
+      nz++;
+    } else {
+      return fail(c, KPSI_E_ARG, "resonance %d: chain must be 0 or 1", i);
+    }
+    if ((r.lb >= 0 && r.lb != lowest_lb(r)) || (r.lr >= 0 && r.lr != lowest_lr(r)))
+      return fail(c, KPSI_E_UNSUPPORTED, "resonance %d: only the lowest orbital momenta are supported", i);
+  }
+  int shape = -1;
+  const int small[5] = {0, 1, 0, 0, 0}, full[5] = {3, 3, 2, 1, 1};
+  bool fits_small = nz == 0, fits_full = nz <= 2;
+  for (int j = 0; j < 5; ++j) { fits_small &= counts[j] <= small[j]; fits_full &= counts[j] <= full[j]; }
+  if (fits_small) shape = 0;
+  else if (fits_full) shape = 1;
+  else return fail(c, KPSI_E_UNSUPPORTED, "model exceeds the compiled capacity (K* per spin 3,3,2,1,1; 2 Z)");
+  c->kin = k;
+  c->res.assign(res, res + n_res);
+  c->shape = shape;
+  c->slot.assign(n_res, 0);
+  c->coff.assign(n_res, 0);
+  c->fslot.assign(n_res, -1);
+  int N[5], NZ;
+  shape_counts(shape, N, &NZ);
+  int used[5] = {0, 0, 0, 0, 0}, zused = 0, off = 0;
+  c->has_z = false;
+  for (int i = 0; i < n_res; ++i) {
+    const kpsi_resonance& r = res[i];
+    c->coff[i] = off;
+    off += 2 * ncoup(r);
+    if (r.chain == 0) {
+      int base = 0;
+      for (int j = 0; j < r.spin; ++j) base += N[j];
+      c->slot[i] = base + used[r.spin]++;
+    } else {
+      c->slot[i] = zused++;
+      c->has_z = true;
+    }
+  }
+  for (int j = 0; j < 5; ++j) c->cnt[j] = counts[j];
+  c->cnt[5] = nz;
+  c->nparams = off + 2 * n_res;
+  c->has_model = true;
+  hipSetDevice(c->device);
+  for (int s = 0; s < 2; ++s) {
+    kpsi_status st = derive_columns(c, s);
+    if (st) return st;
+  }
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_n_params(const kpsi_ctx* c, int* n) {
+  if (!c || !n) return KPSI_E_ARG;
+  if (!c->has_model) return KPSI_E_STATE;
+  *n = c->nparams;
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_set_floating(kpsi_ctx* c, const int* flags, int n_res) {
+  if (!c) return KPSI_E_ARG;
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set");
+  if (n_res != (int)c->res.size()) return fail(c, KPSI_E_ARG, "expected %zu flags", c->res.size());
+  int k = 0;
+  std::vector<int> fs(n_res, -1);
+  for (int i = 0; i < n_res; ++i) {
+    if (flags && flags[i]) {
+      if (k >= NFL) return fail(c, KPSI_E_UNSUPPORTED, "at most %d floating lineshapes", NFL);
+      fs[i] = k++;
+    }
+  }
+  c->fslot = fs;
+  return KPSI_OK;
+}
+
+static kpsi_status load_common(kpsi_ctx* c, kpsi_set set, int64_t n) {
+  if (!c) return KPSI_E_ARG;
+  if (set != KPSI_DATA && set != KPSI_NORM) return fail(c, KPSI_E_ARG, "unknown set");
+  if (n <= 0) return fail(c, KPSI_E_ARG, "n must be positive");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "set the model before loading events");
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_load_events(kpsi_ctx* c, kpsi_set set, int64_t n, const double* m, const double* ck,
+                             const double* cj, const double* phi) {
+  kpsi_status st = load_common(c, set, n);
+  if (st) return st;
+  if (!m || !ck || !cj || !phi) return fail(c, KPSI_E_ARG, "NULL event array");
+  hipSetDevice(c->device);
+  DevSet& d = c->set[set];
+  if (d.owned) hipFree(d.owned);
+  d.owned = nullptr;
+  d.n = 0;
+  if (hipMalloc(&d.owned, 4 * (size_t)n * sizeof(double)) != hipSuccess) return fail(c, KPSI_E_OOM, "event copy");
+  const double* src[4] = {m, ck, cj, phi};
+  for (int j = 0; j < 4; ++j) {
+    d.obs[j] = d.owned + (size_t)j * n;
+    HIPCHECK(c, hipMemcpyAsync((void*)d.obs[j], src[j], n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
+  st = validate(c, n, d.obs);
+  if (st) return st;
+  d.n = n;
+  if (set == KPSI_NORM && c->eps) { hipFree(c->eps); c->eps = nullptr; }
+  st = derive_columns(c, set);
+  if (st) return st;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_load_events_device(kpsi_ctx* c, kpsi_set set, int64_t n, const double* m, const double* ck,
+                                    const double* cj, const double* phi) {
+  kpsi_status st = load_common(c, set, n);
+  if (st) return st;
+  if (!m || !ck || !cj || !phi) return fail(c, KPSI_E_ARG, "NULL event array");
+  hipSetDevice(c->device);
+  DevSet& d = c->set[set];
+  if (d.owned) hipFree(d.owned);
+  d.owned = nullptr;
+  d.n = 0;
+  const double* src[4] = {m, ck, cj, phi};
+  st = validate(c, n, src);
+  if (st) return st;
+  for (int j = 0; j < 4; ++j) d.obs[j] = src[j];
+  d.n = n;
+  if (set == KPSI_NORM && c->eps) { hipFree(c->eps); c->eps = nullptr; }
+  st = derive_columns(c, set);
+  if (st) return st;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_set_efficiency_flat(kpsi_ctx* c) {
+  if (!c) return KPSI_E_ARG;
+  if (c->eps) hipFree(c->eps);
+  c->eps = nullptr;
+  return KPSI_OK;
+}
+
+static kpsi_status eps_from_device_f64(kpsi_ctx* c, const double* d_eps, int64_t n) {
+  void* e = nullptr;
+  if (hipMalloc(&e, (size_t)n * tsize(c)) != hipSuccess) return fail(c, KPSI_E_OOM, "efficiency column");
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (c->prec == KPSI_FP32) hipLaunchKernelGGL(to_t_kernel<float>, dim3(nb), dim3(256), 0, c->stream, d_eps, (float*)e, n);
+  else hipLaunchKernelGGL(to_t_kernel<double>, dim3(nb), dim3(256), 0, c->stream, d_eps, (double*)e, n);
+  hipError_t er = hipStreamSynchronize(c->stream);
+  if (er != hipSuccess) { hipFree(e); return fail(c, KPSI_E_HIP, "efficiency conversion: %s", hipGetErrorString(er)); }
+  if (c->eps) hipFree(c->eps);
+  c->eps = e;
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_set_efficiency_values(kpsi_ctx* c, const double* eps, int64_t n) {
+  if (!c) return KPSI_E_ARG;
+  if (!eps) return fail(c, KPSI_E_ARG, "eps is NULL");
+  if (c->set[1].n <= 0) return fail(c, KPSI_E_STATE, "load the normalisation set first");
+  if (n != c->set[1].n) return fail(c, KPSI_E_ARG, "expected %lld efficiency values", (long long)c->set[1].n);
+  for (int64_t i = 0; i < n; ++i)
+    if (!(eps[i] >= 0.0 && eps[i] <= 1.0)) return fail(c, KPSI_E_ARG, "efficiency %lld outside [0, 1]", (long long)i);
+  hipSetDevice(c->device);
+  double* d = nullptr;
+  if (hipMalloc(&d, (size_t)n * sizeof(double)) != hipSuccess) return fail(c, KPSI_E_OOM, "efficiency staging");
+  hipError_t er = hipMemcpyAsync(d, eps, (size_t)n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  kpsi_status st = er == hipSuccess ? eps_from_device_f64(c, d, n) : fail(c, KPSI_E_HIP, "efficiency upload");
+  hipFree(d);
+  return st;
+}
+
+kpsi_status kpsi_set_efficiency_hist(kpsi_ctx* c, const float* eff, const int nb[4], const double lo[4],
+                                     const double hi[4]) {
+  if (!c) return KPSI_E_ARG;
+  if (!eff || !nb || !lo || !hi) return fail(c, KPSI_E_ARG, "NULL histogram argument");
+  if (c->set[1].n <= 0) return fail(c, KPSI_E_STATE, "load the normalisation set first");
+  int64_t nbins = 1;
+  for (int d = 0; d < 4; ++d) {
+    if (nb[d] <= 0 || !(hi[d] > lo[d])) return fail(c, KPSI_E_ARG, "bad histogram axis %d", d);
+    nbins *= nb[d];
+  }
+  for (int64_t i = 0; i < nbins; ++i)
+    if (!(eff[i] >= 0.0f && eff[i] <= 1.0f)) return fail(c, KPSI_E_ARG, "bin %lld outside [0, 1]", (long long)i);
+  hipSetDevice(c->device);
+  float* table = nullptr;
+  double* vals = nullptr;
+  const int64_t n = c->set[1].n;
+  if (hipMalloc(&table, nbins * sizeof(float)) != hipSuccess || hipMalloc(&vals, n * sizeof(double)) != hipSuccess) {
+    if (table) hipFree(table);
+    return fail(c, KPSI_E_OOM, "histogram");
+  }
+  HistArgs a{};
+  for (int d = 0; d < 4; ++d) { a.obs[d] = c->set[1].obs[d]; a.nb[d] = nb[d]; a.lo[d] = lo[d]; a.hi[d] = hi[d]; }
+  a.table = table;
+  a.n = n;
+  a.out_f64 = vals;
+  hipError_t er = hipMemcpyAsync(table, eff, nbins * sizeof(float), hipMemcpyHostToDevice, c->stream);
+  if (er == hipSuccess) er = launch_hist_lookup(a, c->stream);
+  kpsi_status st = er == hipSuccess ? eps_from_device_f64(c, vals, n) : fail(c, KPSI_E_HIP, "histogram lookup");
+  hipFree(table);
+  hipFree(vals);
+  return st;
+}
+
+kpsi_status kpsi_nll(kpsi_ctx* c, const double* params, double* nll) {
+  kpsi_status st = check_ready(c, params);
+  if (st) return st;
+  if (!nll) return fail(c, KPSI_E_ARG, "nll is NULL");
+  hipSetDevice(c->device);
+  st = dispatch(c, MODE_NLL, params, -1, nullptr);
+  if (st) return st;
+  const double* rd = c->red_host;
+  const double* rm = c->red_host + NACC;
+  const double nd = (double)c->set[0].n, nm = (double)c->set[1].n;
+  const double sm = rm[0] + rm[1];
+  if (rd[2] > 0.0 || !(sm > 0.0)) {
+    *nll = INFINITY;
+    return fail(c, KPSI_E_NONFINITE, "%.0f data events with non-positive density; normalisation %g", rd[2], sm);
+  }
+  *nll = -2.0 * (rd[0] + rd[1]) + 2.0 * nd * std::log(sm / nm);
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, double* grad) {
+  kpsi_status st = check_ready(c, params);
+  if (st) return st;
+  if (!nll || !grad) return fail(c, KPSI_E_ARG, "nll/grad is NULL");
+  hipSetDevice(c->device);
+  st = dispatch(c, MODE_GRAD, params, -1, nullptr);
+  if (st) return st;
+  const double* rd = c->red_host;
+  const double* rm = c->red_host + NACC;
+  const double nd = (double)c->set[0].n, nm = (double)c->set[1].n;
+  const double sm = rm[0] + rm[1];
+  for (int i = 0; i < c->nparams; ++i) grad[i] = NAN;
+  if (rd[2] > 0.0 || !(sm > 0.0)) {
+    *nll = INFINITY;
+    return fail(c, KPSI_E_NONFINITE, "%.0f data events with non-positive density; normalisation %g", rd[2], sm);
+  }
+  *nll = -2.0 * (rd[0] + rd[1]) + 2.0 * nd * std::log(sm / nm);
+  // combined complex sensitivity G = -2 G_data + 2 N_d G_norm / sum(eps S);
+  // dNLL/dr = 2 Re(e^{i phi} G), dNLL/dphi = -2 Im(H G)
+  const double fm = 2.0 * nd / sm;
+  int N[5], NZ;
+  shape_counts(c->shape, N, &NZ);
+  int nkacc = 0;
+  for (int j = 0; j < 5; ++j) nkacc += N[j] * (j == 0 ? 2 : 6);
+  const int ncr = c->nparams - 2 * (int)c->res.size();
+  for (size_t i = 0; i < c->res.size(); ++i) {
+    const kpsi_resonance& r = c->res[i];
+    const int ao = acc_offset(c, i, N);
+    const int nl = ncoup(r);
+    const double* p = params + c->coff[i];
+    for (int l = 0; l < nl; ++l) {
+      // K* spin >= 1 accumulators are lambda = -1, 0, +1; spin 0 has lambda = 0 only; Z has 0, +-1
+      const int a = ao + 2 * l;
+      const double gr = -2.0 * rd[a] + fm * rm[a];
+      const double gi = -2.0 * rd[a + 1] + fm * rm[a + 1];
+      const double mag = p[2 * l], ph = p[2 * l + 1];
+      const double cph = std::cos(ph), sph = std::sin(ph);
+      grad[c->coff[i] + 2 * l] = 2.0 * (cph * gr - sph * gi);
+      grad[c->coff[i] + 2 * l + 1] = -2.0 * mag * (cph * gi + sph * gr);
+    }
+    if (c->fslot[i] >= 0) {
+      const int a = 3 + nkacc + 4 * NZ + 2 * c->fslot[i];
+      grad[ncr + 2 * i] = 2.0 * (-2.0 * rd[a] + fm * rm[a]);
+      grad[ncr + 2 * i + 1] = 2.0 * (-2.0 * rd[a + 1] + fm * rm[a + 1]);
+    }
+  }
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_density(kpsi_ctx* c, kpsi_set set, const double* params, double* out) {
+  if (!c) return KPSI_E_ARG;
+  if (!params || !out) return fail(c, KPSI_E_ARG, "NULL argument");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set");
+  if (set != KPSI_DATA && set != KPSI_NORM) return fail(c, KPSI_E_ARG, "unknown set");
+  const int64_t n = c->set[set].n;
+  if (n <= 0) return fail(c, KPSI_E_STATE, "set not loaded");
+  hipSetDevice(c->device);
+  double* d = nullptr;
+  if (hipMalloc(&d, n * sizeof(double)) != hipSuccess) return fail(c, KPSI_E_OOM, "density output");
+  double* outs[2] = {set == 0 ? d : nullptr, set == 1 ? d : nullptr};
+  kpsi_status st = dispatch(c, MODE_DENSITY, params, (int)set, outs);
+  if (!st) {
+    hipError_t e = hipMemcpyAsync(out, d, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) st = fail(c, KPSI_E_HIP, "density copy: %s", hipGetErrorString(e));
+  }
+  hipFree(d);
+  return st;
+}
+
+kpsi_status kpsi_invariants(kpsi_ctx* c, kpsi_set set, double* out) {
+  if (!c) return KPSI_E_ARG;
+  if (!out) return fail(c, KPSI_E_ARG, "out is NULL");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set");
+  if (set != KPSI_DATA && set != KPSI_NORM) return fail(c, KPSI_E_ARG, "unknown set");
+  DevSet& s = c->set[set];
+  if (s.n <= 0) return fail(c, KPSI_E_STATE, "set not loaded");
+  hipSetDevice(c->device);
+  double *diag = nullptr, *cols = nullptr;
+  const int64_t ld = (s.n + 63) / 64 * 64;
+  if (hipMalloc(&diag, 5 * s.n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&cols, (size_t)ld * NCOL_MAX * sizeof(double)) != hipSuccess) {
+    if (diag) hipFree(diag);
+    return fail(c, KPSI_E_OOM, "diagnostic buffers");
+  }
+  InvArgs<double> a{};
+  for (int j = 0; j < 4; ++j) a.obs[j] = s.obs[j];
+  a.cols = cols;
+  a.ld = ld;
+  a.n = s.n;
+  a.mB = c->kin.m_b; a.mJ = c->kin.m_jpsi; a.mK = c->kin.m_k; a.mPi = c->kin.m_pi;
+  a.rB = c->kin.r_b; a.rR = c->kin.r_r;
+  a.with_z = 1;
+  a.diag = diag;
+  hipError_t e = launch_invariants<double>(a, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, diag, 5 * s.n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(diag);
+  hipFree(cols);
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "invariants: %s", hipGetErrorString(e));
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_generate_phsp(kpsi_ctx* c, uint64_t seed, int64_t n, double wmax, double* m, double* ck,
+                               double* cj, double* phi) {
+  if (!c) return KPSI_E_ARG;
+  if (n <= 0 || !m || !ck || !cj || !phi || !(wmax > 0.0)) return fail(c, KPSI_E_ARG, "bad generator arguments");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set (kinematics needed)");
+  hipSetDevice(c->device);
+  int* flag = nullptr;
+  if (hipMalloc(&flag, n * sizeof(int)) != hipSuccess) return fail(c, KPSI_E_OOM, "generator flags");
+  GenArgs g{};
+  g.seed = seed; g.e0 = 0; g.n = n; g.wmax = wmax;
+  g.mB = c->kin.m_b; g.mJ = c->kin.m_jpsi; g.mK = c->kin.m_k; g.mPi = c->kin.m_pi;
+  g.out[0] = m; g.out[1] = ck; g.out[2] = cj; g.out[3] = phi;
+  g.spare = nullptr;
+  g.flag = flag;
+  hipError_t e = launch_phsp(g, c->stream);
+  // every event must have been produced within the trial budget
+  int* dsum = nullptr;
+  void* tmp = nullptr;
+  size_t tb = 0;
+  int last_pos = 0, last_flag = 0;
+  if (e == hipSuccess) e = hipMalloc(&dsum, n * sizeof(int));
+  if (e == hipSuccess) e = exclusive_scan_int(flag, dsum, n, nullptr, &tb, c->stream);
+  if (e == hipSuccess) e = hipMalloc(&tmp, tb);
+  if (e == hipSuccess) e = exclusive_scan_int(flag, dsum, n, tmp, &tb, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&last_pos, dsum + n - 1, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&last_flag, flag + n - 1, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(flag);
+  if (dsum) hipFree(dsum);
+  if (tmp) hipFree(tmp);
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "phase-space generator: %s", hipGetErrorString(e));
+  if (last_pos + last_flag != n) return fail(c, KPSI_E_ARG, "envelope wmax too small: trial budget exhausted");
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_generate_model(kpsi_ctx* c, const double* params, uint64_t seed, int64_t n, double wmax,
+                                double smax, const double* acc_coef, double* m, double* ck, double* cj,
+                                double* phi, int64_t* n_prop, int64_t* n_over) {
+  if (!c) return KPSI_E_ARG;
+  if (!params || n <= 0 || !m || !ck || !cj || !phi || !(wmax > 0.0) || !(smax > 0.0) || !n_prop || !n_over)
+    return fail(c, KPSI_E_ARG, "bad generator arguments");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set");
+  hipSetDevice(c->device);
+  const int64_t B = 1 << 20;
+  const int64_t ld = B;
+  double *obs = nullptr, *spare = nullptr, *S = nullptr, *cols = nullptr;
+  int *valid = nullptr, *flag = nullptr, *over = nullptr, *pos = nullptr, *opos = nullptr;
+  void* tmp = nullptr;
+  size_t tb = 0;
+  auto cleanup = [&]() {
+    for (void* p : {(void*)obs, (void*)spare, (void*)S, (void*)cols, (void*)valid, (void*)flag, (void*)over,
+                    (void*)pos, (void*)opos, tmp})
+      if (p) hipFree(p);
+  };
+  if (hipMalloc(&obs, 4 * B * sizeof(double)) || hipMalloc(&spare, B * sizeof(double)) ||
+      hipMalloc(&S, B * sizeof(double)) || hipMalloc(&cols, (size_t)ld * NCOL_MAX * sizeof(double)) ||
+      hipMalloc(&valid, B * sizeof(int)) || hipMalloc(&flag, B * sizeof(int)) || hipMalloc(&over, B * sizeof(int)) ||
+      hipMalloc(&pos, B * sizeof(int)) || hipMalloc(&opos, B * sizeof(int))) {
+    cleanup();
+    return fail(c, KPSI_E_OOM, "generator buffers");
+  }
+  exclusive_scan_int(flag, pos, B, nullptr, &tb, c->stream);
+  if (hipMalloc(&tmp, tb)) { cleanup(); return fail(c, KPSI_E_OOM, "scan scratch"); }
+  const double delta = 1.0 - std::pow(3.0, -0.25);
+  int64_t kept = 0, e0 = 0, novr = 0;
+  kpsi_status st = KPSI_OK;
+  std::vector<int> hpos, hflag;
+  while (kept < n) {
+    GenArgs g{};
+    g.seed = seed; g.e0 = e0; g.n = B; g.wmax = wmax;
+    g.mB = c->kin.m_b; g.mJ = c->kin.m_jpsi; g.mK = c->kin.m_k; g.mPi = c->kin.m_pi;
+    for (int j = 0; j < 4; ++j) g.out[j] = obs + j * B;
+    g.spare = spare;
+    g.flag = valid;
+    hipError_t e = launch_phsp(g, c->stream);
+    InvArgs<double> ia{};
+    for (int j = 0; j < 4; ++j) ia.obs[j] = obs + j * B;
+    ia.cols = cols; ia.ld = ld; ia.n = B;
+    ia.mB = c->kin.m_b; ia.mJ = c->kin.m_jpsi; ia.mK = c->kin.m_k; ia.mPi = c->kin.m_pi;
+    ia.rB = c->kin.r_b; ia.rR = c->kin.r_r;
+    ia.with_z = c->has_z ? 1 : 0;
+    if (e == hipSuccess) e = launch_invariants<double>(ia, c->stream);
+    if (e != hipSuccess) { st = fail(c, KPSI_E_HIP, "generator: %s", hipGetErrorString(e)); break; }
+    // density of the proposals through the FP64 amplitude kernel
+    {
+      auto dens = [&](auto shtag) -> hipError_t {
+        using Sh = decltype(shtag);
+        AmpArgs<double, Sh> a{};
+        a.cols[0] = cols; a.ld[0] = ld; a.n[0] = B;
+        a.cols[1] = cols; a.ld[1] = ld; a.n[1] = 0;
+        a.s_out[0] = S; a.s_out[1] = nullptr;
+        a.eps = nullptr;
+        pack<double, Sh>(c, params, a);
+        a.chunk = BLOCK * 4;
+        a.nb_data = (int)((B + a.chunk - 1) / a.chunk);
+        a.partial = nullptr;
+        return launch_amp<double, Sh>(a, MODE_DENSITY, a.nb_data, c->stream);
+      };
+      e = c->shape == 0 ? dens(ShapeSmall{}) : dens(ShapeFull{});
+    }
+    AcceptArgs aa{};
+    for (int j = 0; j < 4; ++j) aa.obs[j] = obs + j * B;
+    aa.S = S; aa.spare = spare; aa.valid = valid;
+    aa.acc_on = acc_coef ? 1 : 0;
+    for (int j = 0; j < 12; ++j) aa.coef[j] = acc_coef ? acc_coef[j] : 0.0;
+    aa.delta = delta;
+    aa.lo = c->kin.m_k + c->kin.m_pi; aa.hi = c->kin.m_b - c->kin.m_jpsi;
+    aa.smax = smax; aa.n = B; aa.flag = flag; aa.over = over;
+    if (e == hipSuccess) e = launch_accept(aa, c->stream);
+    if (e == hipSuccess) e = exclusive_scan_int(flag, pos, B, tmp, &tb, c->stream);
+    if (e == hipSuccess) e = exclusive_scan_int(over, opos, B, tmp, &tb, c->stream);
+    CompactArgs ca{};
+    for (int j = 0; j < 4; ++j) { ca.obs[j] = obs + j * B; }
+    ca.out[0] = m; ca.out[1] = ck; ca.out[2] = cj; ca.out[3] = phi;
+    ca.flag = flag; ca.pos = pos; ca.n = B; ca.base = kept; ca.limit = n;
+    if (e == hipSuccess) e = launch_compact(ca, c->stream);
+    int tail[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(&tail[0], pos + B - 1, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&tail[1], flag + B - 1, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&tail[2], opos + B - 1, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&tail[3], over + B - 1, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { st = fail(c, KPSI_E_HIP, "generator: %s", hipGetErrorString(e)); break; }
+    const int64_t acc = tail[0] + tail[1];
+    novr += tail[2] + tail[3];
+    if (kept + acc >= n) {
+      // locate the proposal that completes the sample
+      hpos.resize(B);
+      hflag.resize(B);
+      e = hipMemcpy(hpos.data(), pos, B * sizeof(int), hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(hflag.data(), flag, B * sizeof(int), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) { st = fail(c, KPSI_E_HIP, "generator: %s", hipGetErrorString(e)); break; }
+      const int64_t need = n - kept;
+      int64_t last = B - 1;
+      for (int64_t i = 0; i < B; ++i)
+        if (hflag[i] && hpos[i] == need - 1) { last = i; break; }
+      e0 += last + 1;
+      kept = n;
+      break;
+    }
+    kept += acc;
+    e0 += B;
+    if (e0 > ((int64_t)1 << 40)) { st = fail(c, KPSI_E_ARG, "proposal budget exhausted"); break; }
+  }
+  cleanup();
+  *n_prop = e0;
+  *n_over = novr;
+  return st;
+}
+
+kpsi_status kpsi_set_timing(kpsi_ctx* c, int enable) {
+  if (!c) return KPSI_E_ARG;
+  c->timing = enable != 0;
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_timing(kpsi_ctx* c, double* ms, int64_t* n, int reset) {
+  if (!c) return KPSI_E_ARG;
+  if (ms) *ms = c->t_ms;
+  if (n) *n = c->t_n;
+  if (reset) { c->t_ms = 0.0; c->t_n = 0; }
+  return KPSI_OK;
+}
+
+const char* kpsi_last_error(const kpsi_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+kpsi_status kpsi_set_events_per_thread(kpsi_ctx* c, int ept) {
+  if (!c || ept < 0 || ept > 1024) return KPSI_E_ARG;
+  c->ept_override = ept;
+  return KPSI_OK;
+}
+
+}  // extern "C"
+
+namespace kpsi {
+hipError_t exclusive_scan_int(const int* in, int* out, int64_t n, void* tmp, size_t* tmp_bytes, hipStream_t st) {
+  return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, in, out, (int)n, st);
+}
+}  // namespace kpsi

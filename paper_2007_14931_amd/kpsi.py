@@ -1,0 +1,276 @@
+"""Python binding of libkpsi (include/kpsi.h): argument marshalling only.
+
+Every step of the likelihood runs in the HIP library; this module converts numpy
+arrays and torch tensors to pointers, checks status codes and raises on errors.
+PyTorch is used for device memory (generator outputs, borrowed event columns) and
+streams.  There is no CPU fallback: if libkpsi.so is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkpsi.so")
+
+KPSI_OK, KPSI_E_ARG, KPSI_E_STATE, KPSI_E_HIP, KPSI_E_OOM, KPSI_E_NONFINITE, KPSI_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32 = 0, 1
+DATA, NORM = 0, 1
+_STATUS = {0: "OK", -1: "E_ARG", -2: "E_STATE", -3: "E_HIP", -4: "E_OOM", -5: "E_NONFINITE", -6: "E_UNSUPPORTED"}
+
+# Every entry point of include/kpsi.h.
+EXPORTS = [
+    "kpsi_create", "kpsi_destroy", "kpsi_set_model", "kpsi_n_params", "kpsi_set_floating", "kpsi_load_events",
+    "kpsi_load_events_device", "kpsi_set_efficiency_flat", "kpsi_set_efficiency_values", "kpsi_set_efficiency_hist",
+    "kpsi_nll", "kpsi_nll_and_grad", "kpsi_density", "kpsi_invariants", "kpsi_generate_phsp", "kpsi_generate_model",
+    "kpsi_set_timing", "kpsi_timing", "kpsi_set_events_per_thread", "kpsi_last_error",
+]
+
+
+class KpsiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Kinematics(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("m_b", "m_jpsi", "m_k", "m_pi", "r_b", "r_r")]
+
+
+class Resonance(C.Structure):
+    _fields_ = [("chain", C.c_int), ("spin", C.c_int), ("parity", C.c_int), ("lb", C.c_int), ("lr", C.c_int),
+                ("mass", C.c_double), ("width", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libkpsi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2007_14931_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+        L.kpsi_create.argtypes = [C.c_int, vp, C.c_int, C.POINTER(vp)]
+        L.kpsi_destroy.argtypes = [vp]
+        L.kpsi_set_model.argtypes = [vp, C.POINTER(Kinematics), C.POINTER(Resonance), C.c_int]
+        L.kpsi_n_params.argtypes = [vp, C.POINTER(C.c_int)]
+        L.kpsi_set_floating.argtypes = [vp, C.POINTER(C.c_int), C.c_int]
+        L.kpsi_load_events.argtypes = [vp, C.c_int, i64, dp, dp, dp, dp]
+        L.kpsi_load_events_device.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp]
+        L.kpsi_set_efficiency_flat.argtypes = [vp]
+        L.kpsi_set_efficiency_values.argtypes = [vp, dp, i64]
+        L.kpsi_set_efficiency_hist.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int), dp, dp]
+        L.kpsi_nll.argtypes = [vp, dp, dp]
+        L.kpsi_nll_and_grad.argtypes = [vp, dp, dp, dp]
+        L.kpsi_density.argtypes = [vp, C.c_int, dp, dp]
+        L.kpsi_invariants.argtypes = [vp, C.c_int, dp]
+        L.kpsi_generate_phsp.argtypes = [vp, C.c_uint64, i64, C.c_double, vp, vp, vp, vp]
+        L.kpsi_generate_model.argtypes = [vp, dp, C.c_uint64, i64, C.c_double, C.c_double, dp, vp, vp, vp, vp,
+                                          C.POINTER(i64), C.POINTER(i64)]
+        L.kpsi_set_timing.argtypes = [vp, C.c_int]
+        L.kpsi_timing.argtypes = [vp, dp, C.POINTER(i64), C.c_int]
+        L.kpsi_set_events_per_thread.argtypes = [vp, C.c_int]
+        L.kpsi_last_error.argtypes = [vp]
+        L.kpsi_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name != "kpsi_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def kinematics(d: dict) -> Kinematics:
+    return Kinematics(d["mB"], d["mJ"], d["mK"], d["mPi"], d["rB"], d["rR"])
+
+
+def resonances(res) -> C.Array:
+    arr = (Resonance * len(res))()
+    for i, r in enumerate(res):
+        arr[i] = Resonance(r.chain, r.spin, r.parity, r.lb, r.lr, r.mass, r.width)
+    return arr
+
+
+def create_status(device: int = 0, precision: int = FP64) -> tuple[int, str]:
+    """Try kpsi_create and return (status, message) without raising (for error-path checks)."""
+    L = lib()
+    h = C.c_void_p()
+    st = L.kpsi_create(device, None, precision, C.byref(h))
+    msg = L.kpsi_last_error(None).decode()
+    if st == KPSI_OK:
+        L.kpsi_destroy(h)
+    return st, msg
+
+
+class Engine:
+    """One kpsi context: model, loaded event sets and the NLL entry points."""
+
+    def __init__(self, device: int = 0, precision: str | int = "fp64", stream=None):
+        self.L = lib()
+        prec = {"fp64": FP64, "fp32": FP32}.get(precision, precision)
+        self.precision = prec
+        self.device = device
+        h = C.c_void_p()
+        st = self.L.kpsi_create(device, C.c_void_p(stream) if stream else None, prec, C.byref(h))
+        if st != KPSI_OK:
+            raise KpsiError(st, self.L.kpsi_last_error(None).decode())
+        self.h = h
+        self._keep = {}
+        self.n_params = 0
+        self.n = [0, 0]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.kpsi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st: int):
+        if st != KPSI_OK:
+            raise KpsiError(st, self.L.kpsi_last_error(self.h).decode())
+
+    def set_model(self, kin: dict, res) -> None:
+        k = kinematics(kin)
+        r = resonances(res)
+        self._chk(self.L.kpsi_set_model(self.h, C.byref(k), r, len(res)))
+        n = C.c_int()
+        self._chk(self.L.kpsi_n_params(self.h, C.byref(n)))
+        self.n_params = n.value
+        self.n_res = len(res)
+
+    def set_floating(self, flags) -> None:
+        f = np.ascontiguousarray(flags, dtype=np.int32)
+        self._chk(self.L.kpsi_set_floating(self.h, f.ctypes.data_as(C.POINTER(C.c_int)), len(f)))
+
+    def load(self, which: int, events) -> None:
+        """events: numpy (4, n) float64 (copied) or a CUDA float64 torch tensor (4, n) (borrowed)."""
+        if hasattr(events, "is_cuda") and events.is_cuda:
+            import torch
+            ev = events.contiguous()
+            assert ev.dtype == torch.float64 and ev.dim() == 2 and ev.shape[0] == 4
+            self._keep[which] = ev
+            n = ev.shape[1]
+            ptrs = [C.c_void_p(ev[i].data_ptr()) for i in range(4)]
+            self._chk(self.L.kpsi_load_events_device(self.h, which, n, *ptrs))
+        else:
+            ev = _f64(events)
+            n = ev.shape[1]
+            cols = [_f64(ev[i]) for i in range(4)]
+            self._chk(self.L.kpsi_load_events(self.h, which, n, *(_dp(c) for c in cols)))
+            self._keep.pop(which, None)
+        self.n[which] = n
+
+    def set_efficiency_flat(self) -> None:
+        self._chk(self.L.kpsi_set_efficiency_flat(self.h))
+
+    def set_efficiency_values(self, eps) -> None:
+        e = _f64(eps)
+        self._chk(self.L.kpsi_set_efficiency_values(self.h, _dp(e), e.size))
+
+    def set_efficiency_hist(self, table, lo, hi) -> None:
+        t = np.ascontiguousarray(table, dtype=np.float32)
+        nb = np.ascontiguousarray(t.shape, dtype=np.int32)
+        lo, hi = _f64(lo), _f64(hi)
+        self._chk(self.L.kpsi_set_efficiency_hist(self.h, t.ctypes.data_as(C.POINTER(C.c_float)),
+                                                  nb.ctypes.data_as(C.POINTER(C.c_int)), _dp(lo), _dp(hi)))
+
+    def nll(self, params) -> float:
+        p = _f64(params)
+        out = C.c_double()
+        self._chk(self.L.kpsi_nll(self.h, _dp(p), C.byref(out)))
+        return out.value
+
+    def nll_and_grad(self, params) -> tuple[float, np.ndarray]:
+        p = _f64(params)
+        out = C.c_double()
+        g = np.empty(self.n_params)
+        self._chk(self.L.kpsi_nll_and_grad(self.h, _dp(p), C.byref(out), _dp(g)))
+        return out.value, g
+
+    def nll_status(self, params, grad: bool = False) -> tuple[int, float]:
+        """Raw status and value (for error-path tests)."""
+        p = _f64(params)
+        out = C.c_double()
+        if grad:
+            g = np.empty(self.n_params)
+            st = self.L.kpsi_nll_and_grad(self.h, _dp(p), C.byref(out), _dp(g))
+        else:
+            st = self.L.kpsi_nll(self.h, _dp(p), C.byref(out))
+        return st, out.value
+
+    def density(self, which: int, params) -> np.ndarray:
+        p = _f64(params)
+        out = np.empty(self.n[which])
+        self._chk(self.L.kpsi_density(self.h, which, _dp(p), _dp(out)))
+        return out
+
+    def invariants(self, which: int) -> np.ndarray:
+        out = np.empty((self.n[which], 5))
+        self._chk(self.L.kpsi_invariants(self.h, which, _dp(out)))
+        return out
+
+    def generate_phsp(self, seed: int, n: int, wmax: float):
+        import torch
+        ev = torch.empty((4, n), dtype=torch.float64, device=f"cuda:{self.device}")
+        ptrs = [C.c_void_p(ev[i].data_ptr()) for i in range(4)]
+        self._chk(self.L.kpsi_generate_phsp(self.h, seed, n, wmax, *ptrs))
+        return ev
+
+    def generate_model(self, params, seed: int, n: int, wmax: float, smax: float, acc_coef=None):
+        import torch
+        p = _f64(params)
+        ev = torch.empty((4, n), dtype=torch.float64, device=f"cuda:{self.device}")
+        ptrs = [C.c_void_p(ev[i].data_ptr()) for i in range(4)]
+        npr, nov = C.c_int64(), C.c_int64()
+        co = _f64(acc_coef).reshape(-1) if acc_coef is not None else None
+        self._chk(self.L.kpsi_generate_model(self.h, _dp(p), seed, n, wmax, smax, _dp(co) if co is not None else None,
+                                             *ptrs, C.byref(npr), C.byref(nov)))
+        return ev, npr.value, nov.value
+
+    def set_timing(self, on: bool) -> None:
+        self._chk(self.L.kpsi_set_timing(self.h, 1 if on else 0))
+
+    def timing(self, reset: bool = False) -> tuple[float, int]:
+        ms, n = C.c_double(), C.c_int64()
+        self._chk(self.L.kpsi_timing(self.h, C.byref(ms), C.byref(n), 1 if reset else 0))
+        return ms.value, n.value
+
+    def set_events_per_thread(self, ept: int) -> None:
+        self._chk(self.L.kpsi_set_events_per_thread(self.h, ept))
+
+
+def make_nll_function(engine: Engine):
+    """torch.autograd.Function over the engine: forward runs nll_and_grad once and keeps the
+    gradient; backward scales it by the incoming gradient."""
+    import torch
+
+    class NLL(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, params):
+            v, g = engine.nll_and_grad(params.detach().cpu().numpy())
+            ctx.save_for_backward(torch.from_numpy(g).to(params.device, params.dtype))
+            return params.new_tensor(v)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            return grad_out * g
+
+    return NLL
