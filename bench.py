@@ -33,6 +33,21 @@ PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}        # MI355X published vector peaks
 PEAK_TFLOPS_UNPACKED = {"f32": 78.6, "f64": 78.6}  # without packed-FP32 instructions
 
 
+def measured_traffic(kernel_source: str) -> float | None:
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None
+    when the kernel source has changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "amp_kernel_traffic.json")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(os.path.join(ROOT, kernel_source), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if not sha.startswith(rec["source_sha256_prefix"]):
+        return None
+    return float(rec["traffic_bytes"])
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -70,6 +85,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ept", type=int, default=0, help="events per thread (0 = automatic)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain 512 MiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported on this build "
@@ -113,6 +130,13 @@ def main() -> int:
         if args.ept:
             e.set_events_per_thread(args.ept)
         return e
+
+    if args.copy_calib:
+        a = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)   # reads and writes 512 MiB once
+        torch.cuda.synchronize()
+        del a, b
 
     par = truth + 0.05 * np.where(W.free_mask(res, floating), 1.0, 0.0)
     eng = make(args.precision)
@@ -176,7 +200,8 @@ def main() -> int:
         "other_precision": {"precision": other, "ms_per_step": ms2, "kernel_ms": k2 / max(kn2, 1),
                             "evals_per_s": 1e3 / ms2, "nll": v2, "rel_nll_diff": abs(v2 - v) / abs(v)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS[dt], "traffic": None,
+                     "frac": achieved / PEAK_TFLOPS[dt],
+                     "traffic": measured_traffic("paper_2007_14931_amd/csrc/kpsi_device.hip") if dt == "f32" else None,
                      "peak_unpacked": PEAK_TFLOPS_UNPACKED[dt],
                      "frac_unpacked": achieved / PEAK_TFLOPS_UNPACKED[dt],
                      "flop_per_event": FLOP_PER_EVENT["full_grad"], "events_per_launch": n_ev,

@@ -38,6 +38,8 @@ __device__ __forceinline__ double rsq_(double x) {
   e = __builtin_fma(-h * r, r, 0.5);
   return __builtin_fma(r, e, r);
 }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float log_(float x) { return __logf(x); }
 __device__ __forceinline__ double log_(double x) { return log(x); }
 
@@ -184,8 +186,8 @@ __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
 // ------------------------------------------------------------------ per-event amplitude
 template <typename T> struct Cx { T re, im; };
 template <typename T> __device__ __forceinline__ void cmac(Cx<T>& acc, T ar, T ai, T br, T bi) {
-  acc.re = __builtin_fma(ar, br, __builtin_fma(-ai, bi, acc.re));
-  acc.im = __builtin_fma(ar, bi, __builtin_fma(ai, br, acc.im));
+  acc.re = fma_(ar, br, fma_(-ai, bi, acc.re));
+  acc.im = fma_(ar, bi, fma_(ai, br, acc.im));
 }
 
 // Blatt-Weisskopf polynomial B_L(z) (Horner form)
@@ -260,14 +262,13 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
   double nbad = 0.0;
   A_t gk[Sh::NKACC > 0 ? Sh::NKACC : 1];
   A_t gz[NZ > 0 ? 4 * NZ : 1];
-  A_t gf[2 * NFL];
+  static_assert(NFL == 2, "floating accumulators are named registers for two slots");
+  A_t gM0 = 0, gG0 = 0, gM1 = 0, gG1 = 0;   // d/dM, d/dGamma0 of floating slots 0 and 1
   if constexpr (GRAD) {
 #pragma unroll
     for (int i = 0; i < Sh::NKACC; ++i) gk[i] = 0;
 #pragma unroll
     for (int i = 0; i < 4 * NZ; ++i) gz[i] = 0;
-#pragma unroll
-    for (int i = 0; i < 2 * NFL; ++i) gf[i] = 0;
   }
 
   for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
               const auto& rc = ka.ks[sb + j];
               const T dre = rc.M2 - m2;
               const T dim = -rc.P * gJ;
-              const T inv = rcp_(__builtin_fma(dre, dre, dim * dim));
+              const T inv = rcp_(fma_(dre, dre, dim * dim));
               const T sc = rc.K * nJ * inv;
               const T Ar = sc * dre, Ai = -sc * dim;
               Amp[sb + j] = Cx<T>{Ar, Ai};
@@ -343,13 +344,13 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
 #pragma unroll
     for (int J = 0; J < 5; ++J) {
       if (Sh::N[J] == 0) continue;
-      U0.re = __builtin_fma(dd0[J], Tl[J][1].re, U0.re);
-      U0.im = __builtin_fma(dd0[J], Tl[J][1].im, U0.im);
+      U0.re = fma_(dd0[J], Tl[J][1].re, U0.re);
+      U0.im = fma_(dd0[J], Tl[J][1].im, U0.im);
       if (J > 0) {
-        Up.re = __builtin_fma(dd1[J], Tl[J][2].re, Up.re);
-        Up.im = __builtin_fma(dd1[J], Tl[J][2].im, Up.im);
-        Um.re = __builtin_fma(-dd1[J], Tl[J][0].re, Um.re);
-        Um.im = __builtin_fma(-dd1[J], Tl[J][0].im, Um.im);
+        Up.re = fma_(dd1[J], Tl[J][2].re, Up.re);
+        Up.im = fma_(dd1[J], Tl[J][2].im, Up.im);
+        Um.re = fma_(-dd1[J], Tl[J][0].re, Um.re);
+        Um.im = fma_(-dd1[J], Tl[J][0].im, Um.im);
       }
     }
     // e^{i lambda phi} d^1_{lambda xi}(theta_J):  lambda=+1: (1+c)/2, (1-c)/2;  0: s/sqrt2, -s/sqrt2;
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
             const auto& rc = ka.zs[z];
             const T dre = rc.M2 - mz2;
             const T dim = -rc.P * gzv;
-            const T inv = rcp_(__builtin_fma(dre, dre, dim * dim));
+            const T inv = rcp_(fma_(dre, dre, dim * dim));
             const T sc = rc.K * nz * inv;
             AZ[z] = Cx<T>{sc * dre, -sc * dim};
             dzr[z] = dre; dzi[z] = dim; zinv[z] = inv;
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
                   const T Xr = A.re * Q.re - A.im * Q.im, Xi = A.re * Q.im + A.im * Q.re;
                   const T g_ = gJv[J];
                   const T dre = rc.M2 - m2, dim = -rc.P * g_;
-                  const T inv = rcp_(__builtin_fma(dre, dre, dim * dim));
+                  const T inv = rcp_(fma_(dre, dre, dim * dim));
                   // Y = (2M - i P' g)(dre - i dim) inv
                   const T pr = rc.twoM, pim = -rc.dP * g_;
                   const T Yr = (pr * dre + pim * dim) * inv;
@@ -477,9 +478,12 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
                   const T dM = rc.kap * Xr - (Xr * Yr - Xi * Yi);
                   const T zf = rc.PoG * g_ * inv;
                   const T dG = zf * (Xr * dim - Xi * dre);
-#pragma unroll
-                  for (int f = 0; f < NFL; ++f)
-                    if (rc.flt == f) { gf[2 * f] += (A_t)dM; gf[2 * f + 1] += (A_t)dG; }
+                  // uniform selects into named registers (no indexed private array)
+                  const bool f0 = rc.flt == 0;
+                  gM0 += f0 ? (A_t)dM : A_t(0);
+                  gG0 += f0 ? (A_t)dG : A_t(0);
+                  gM1 += f0 ? A_t(0) : (A_t)dM;
+                  gG1 += f0 ? A_t(0) : (A_t)dG;
                 }
               }
             }
@@ -521,9 +525,11 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
                 const T dM = rc.kap * Xr - (Xr * Yr - Xi * Yi);
                 const T zf = rc.PoG * gzv * inv;
                 const T dG = zf * (Xr * dim - Xi * dre);
-#pragma unroll
-                for (int f = 0; f < NFL; ++f)
-                  if (rc.flt == f) { gf[2 * f] += (A_t)dM; gf[2 * f + 1] += (A_t)dG; }
+                const bool f0 = rc.flt == 0;
+                gM0 += f0 ? (A_t)dM : A_t(0);
+                gG0 += f0 ? (A_t)dG : A_t(0);
+                gM1 += f0 ? A_t(0) : (A_t)dM;
+                gG1 += f0 ? A_t(0) : (A_t)dG;
               }
             }
           }
@@ -545,7 +551,11 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
       if (i == 2) return nbad;
       if (i < 3 + Sh::NKACC) return (double)gk[i - 3];
       if (i < 3 + Sh::NKACC + 4 * NZ) return (double)gz[i - 3 - Sh::NKACC];
-      if (i < 3 + Sh::NKACC + 4 * NZ + 2 * NFL) return (double)gf[i - 3 - Sh::NKACC - 4 * NZ];
+      const int f = i - 3 - Sh::NKACC - 4 * NZ;
+      if (f == 0) return (double)gM0;
+      if (f == 1) return (double)gG0;
+      if (f == 2) return (double)gM1;
+      if (f == 3) return (double)gG1;
       return 0.0;
     };
     // Transpose butterfly: after the step of width h, lane l keeps h values, each summed
@@ -588,40 +598,51 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
   __syncthreads();
   if (wave == 0) {
     const double t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-    a.partial[(int64_t)blockIdx.x * NACC + lane] = t;
+    // value-major layout: value v of block b at partial[v * gridDim.x + b]
+    if (GRAD || lane < 3) a.partial[(int64_t)lane * gridDim.x + blockIdx.x] = t;
   }
 }
 
-// Fixed-order Neumaier sum of the block partials: block 0 reduces the data blocks,
-// block 1 the normalisation blocks; thread t sums value t%64 over blocks t/64, t/64+4, ...
+// Fixed-order compensated sum of the block partials.  Block (set, v) sums value v over
+// the blocks of one set: each thread runs a Neumaier sum over a strided subset, then the
+// 256 partial pairs are merged pairwise in a fixed tree.  Output goes to out[set*NACC + v]
+// (mapped pinned host memory).
+__device__ __forceinline__ void two_sum_merge(double& s, double& c, double s2, double c2) {
+  const double t = s + s2;
+  const double bp = t - s;
+  const double err = (s - (t - bp)) + (s2 - bp);
+  s = t;
+  c = c + c2 + err;
+}
+
 __global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ partial, int nb_data, int nb_mc,
-                                                    double* __restrict__ out) {
-  const int set = blockIdx.x;
-  const int v = threadIdx.x & 63, sub = threadIdx.x >> 6;
+                                                    int nv, double* __restrict__ out) {
+  const int set = blockIdx.x / nv, v = blockIdx.x % nv;
+  const int nbt = nb_data + nb_mc;
   const int b0 = set ? nb_data : 0;
   const int nb = set ? nb_mc : nb_data;
+  const double* __restrict__ p = partial + (int64_t)v * nbt + b0;
   double s = 0.0, c = 0.0;
-  for (int b = sub; b < nb; b += 4) {
-    const double x = partial[(int64_t)(b0 + b) * NACC + v];
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    const double x = p[b];
     const double t = s + x;
     c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
     s = t;
   }
-  __shared__ double S[4][NACC], C[4][NACC];
-  S[sub][v] = s;
-  C[sub][v] = c;
+  __shared__ double S[256], Cc[256];
+  S[threadIdx.x] = s;
+  Cc[threadIdx.x] = c;
   __syncthreads();
-  if (sub == 0) {
-    double ts = 0.0, tc = 0.0;
-    for (int k = 0; k < 4; ++k) {
-      const double x = S[k][v];
-      const double t = ts + x;
-      tc += (fabs(ts) >= fabs(x)) ? (ts - t) + x : (x - t) + ts;
-      ts = t;
-      tc += C[k][v];
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) {
+      double a = S[threadIdx.x], ca = Cc[threadIdx.x];
+      two_sum_merge(a, ca, S[threadIdx.x + w], Cc[threadIdx.x + w]);
+      S[threadIdx.x] = a;
+      Cc[threadIdx.x] = ca;
     }
-    out[set * NACC + v] = ts + tc;
+    __syncthreads();
   }
+  if (threadIdx.x == 0) out[set * NACC + v] = S[0] + Cc[0];
 }
 
 // ------------------------------------------------------------------ efficiency histogram
@@ -777,8 +798,8 @@ template hipError_t launch_amp<double, ShapeSmall>(const AmpArgs<double, ShapeSm
 template hipError_t launch_amp<float, ShapeFull>(const AmpArgs<float, ShapeFull>&, int, int, hipStream_t);
 template hipError_t launch_amp<double, ShapeFull>(const AmpArgs<double, ShapeFull>&, int, int, hipStream_t);
 
-hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_final, dim3(2), dim3(256), 0, st, partial, nb_data, nb_mc, out);
+hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int nv, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_final, dim3(2 * nv), dim3(256), 0, st, partial, nb_data, nb_mc, nv, out);
   return hipGetLastError();
 }
 hipError_t launch_hist_lookup(const HistArgs& a, hipStream_t st) {

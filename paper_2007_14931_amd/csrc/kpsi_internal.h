@@ -42,7 +42,7 @@ template <typename T, class Sh> struct AmpArgs {
   int64_t ld[2];        // column strides (elements)
   int64_t n[2];         // events per set
   const T* eps;         // per-normalisation-event efficiency, or null (flat)
-  double* partial;      // [blocks][NACC]
+  double* partial;      // value-major: value v of block b at [v * blocks + b]
   double* s_out[2];     // density mode: per-event S of each set
   int nb_data;          // blocks of the data set; the rest cover the normalisation set
   int chunk;            // events per block
@@ -102,7 +102,7 @@ struct CompactArgs {
 
 template <typename T> hipError_t launch_invariants(const InvArgs<T>& a, hipStream_t st);
 template <typename T, class Sh> hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st);
-hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, double* out, hipStream_t st);
+hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int nv, double* out, hipStream_t st);
 hipError_t launch_hist_lookup(const HistArgs& a, hipStream_t st);
 hipError_t launch_phsp(const GenArgs& a, hipStream_t st);
 hipError_t launch_accept(const AcceptArgs& a, hipStream_t st);

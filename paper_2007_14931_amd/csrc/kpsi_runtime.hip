@@ -53,8 +53,8 @@ struct kpsi_ctx {
   void* eps = nullptr;          // T array over the normalisation set, or null (flat)
   double* partial = nullptr;
   size_t partial_cap = 0;       // in doubles
-  double* red = nullptr;        // [2][NACC]
-  double* red_host = nullptr;   // pinned
+  double* red = nullptr;        // device view of red_host
+  double* red_host = nullptr;   // [2][NACC], mapped pinned host memory
   std::string err;
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -316,9 +316,9 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   if (e != hipSuccess) return fail(c, KPSI_E_HIP, "amplitude kernel: %s", hipGetErrorString(e));
   if (c->timing && mode != MODE_DENSITY) hipEventRecord(c->ev1, c->stream);
   if (mode == MODE_DENSITY) return KPSI_OK;
-  e = launch_reduce_final(c->partial, nbd, nbm, c->red, c->stream);
+  // the final sums are written by the GPU straight into mapped pinned host memory
+  e = launch_reduce_final(c->partial, nbd, nbm, mode == MODE_GRAD ? NACC : 3, c->red, c->stream);
   if (e != hipSuccess) return fail(c, KPSI_E_HIP, "reduction kernel: %s", hipGetErrorString(e));
-  HIPCHECK(c, hipMemcpyAsync(c->red_host, c->red, 2 * NACC * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   if (c->timing) {
     float ms = 0.f;
@@ -381,8 +381,8 @@ kpsi_status kpsi_create(int device, void* stream, kpsi_precision prec, kpsi_ctx*
     }
     c->own_stream = true;
   }
-  if (hipMalloc(&c->red, 2 * NACC * sizeof(double)) != hipSuccess ||
-      hipHostMalloc(&c->red_host, 2 * NACC * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&c->red_host, 2 * NACC * sizeof(double), hipHostMallocMapped) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&c->red, c->red_host, 0) != hipSuccess) {
     kpsi_destroy(c);
     return fail(nullptr, KPSI_E_OOM, "result buffers");
   }
@@ -402,7 +402,6 @@ kpsi_status kpsi_destroy(kpsi_ctx* c) {
   }
   if (c->eps) hipFree(c->eps);
   if (c->partial) hipFree(c->partial);
-  if (c->red) hipFree(c->red);
   if (c->red_host) hipHostFree(c->red_host);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
