@@ -76,6 +76,44 @@ def cpu_baseline(res, par, floating, n_data: int, n_mc: int, seconds: float = 15
                       f"{reps} evaluations in {dt * reps:.1f} s, scaled by {scale:.0f} to the full workload"}
 
 
+def fit_comparison(make, truth, mask, canonical_fn) -> dict:
+    """Full MIGRAD + HESSE fit of the benchmark workload twice from the same start point:
+    FP32 amplitudes with the device adjoint gradient, and the plain FP64 likelihood with
+    central finite-difference gradients.  Reports wall time, likelihood calls and how far
+    apart the two minima are in units of the FP64 HESSE errors (couplings compared as
+    magnitude >= 0, phase in (-pi, pi])."""
+    rng = np.random.default_rng(7)
+    x0 = truth + 0.01 * rng.standard_normal(truth.size) * mask
+    free = np.flatnonzero(mask)
+    runs = {}
+    for name, prec, grad in (("fp32_analytic", "fp32", 1), ("fp64_finite_difference", "fp64", 0)):
+        e = make(prec)
+        x, cov, r = e.migrad(x0, mask, gradient=grad)
+        e.close()
+        runs[name] = (x, cov, r)
+        log(f"fit {name}: status {r.status} fmin {r.fmin:.4f} edm {r.edm:.2e} wall {r.wall_seconds:.3f} s "
+            f"nll calls {r.n_nll} grad calls {r.n_grad}")
+    xa, ca, ra = runs["fp32_analytic"]
+    xf, cf, rf = runs["fp64_finite_difference"]
+    xa, xf = canonical_fn(xa), canonical_fn(xf)
+    sig = np.sqrt(np.abs(np.diag(cf)))
+    sig_a = np.sqrt(np.abs(np.diag(ca)))
+    dev = np.abs(xa[free] - xf[free]) / sig
+    worst = [{"index": int(free[k]), "x_fp32_analytic": float(xa[free[k]]), "x_fp64_fd": float(xf[free[k]]),
+              "sigma_fp64_fd": float(sig[k]), "sigma_fp32_analytic": float(sig_a[k])}
+             for k in np.argsort(dev)[-3:][::-1]]
+    return {
+        "largest_differences": worst,
+        "fp32_analytic": ra.as_dict(),
+        "fp64_finite_difference": rf.as_dict(),
+        "wall_ratio_fd_over_analytic": rf.wall_seconds / ra.wall_seconds,
+        "max_param_diff_sigma": float(dev.max()),
+        "median_param_diff_sigma": float(np.median(dev)),
+        "error_ratio_max_dev": float(np.max(np.abs(np.sqrt(np.abs(np.diag(ca))) / sig - 1.0))),
+        "free_params": int(len(free)),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +123,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ept", type=int, default=0, help="events per thread (0 = automatic)")
+    ap.add_argument("--no-fit", action="store_true", help="skip the fit wall-time comparison")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 512 MiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -207,6 +246,8 @@ def main() -> int:
                      "flop_per_event": FLOP_PER_EVENT["full_grad"], "events_per_launch": n_ev,
                      "kernel": "amp_kernel<GRAD>"},
     }
+    if not args.no_fit:
+        out["fit"] = fit_comparison(make, truth, W.free_mask(res, floating), lambda p: W.canonical(res, p))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(res, par, floating, wl.n_data, wl.n_mc, args.cpu_seconds)

@@ -151,6 +151,48 @@ kpsi_status kpsi_generate_model(kpsi_ctx* ctx, const double* params, uint64_t se
 kpsi_status kpsi_set_timing(kpsi_ctx* ctx, int enable);
 kpsi_status kpsi_timing(kpsi_ctx* ctx, double* kernel_ms, int64_t* n_calls, int reset);
 
+/* ---------------------------------------------------------------- fit driver
+ * Variable-metric minimisation (MINUIT MIGRAD style: BFGS update of the inverse Hessian,
+ * parabolic backtracking line search, stop when the expected distance to the minimum
+ * EDM = g^T V g / 2 < 0.002 * tolerance * up) and HESSE covariance, of the context's NLL
+ * over the parameters with free_mask[i] != 0 (length kpsi_n_params; the other entries of
+ * params are held fixed, e.g. H_0 of K*(892) by Eq. 6).  The host steps the parameters
+ * and the device evaluates the NLL (Introduction).  Points where the NLL call reports
+ * KPSI_E_NONFINITE or KPSI_E_ARG (unphysical mass or width) are rejected steps. */
+typedef struct {
+  int64_t max_calls;    /* budget of NLL plus NLL+gradient evaluations */
+  double tolerance;     /* EDM target factor (MINUIT default 0.1) */
+  double up;            /* error definition: 1.0 for -2 ln L */
+  int gradient;         /* 1: analytic gradient (kpsi_nll_and_grad); 0: central finite
+                           differences of kpsi_nll (2 P calls per gradient) */
+  double fd_rel_step;   /* finite-difference step h_i = fd_rel_step * (1 + |x_i|) */
+  int hesse;            /* 1: numerical Hessian at the minimum for the covariance */
+} kpsi_fit_options;
+
+typedef struct {
+  double fmin;          /* NLL at the minimum */
+  double edm;           /* expected distance to the minimum at exit */
+  double wall_seconds;  /* host wall time of the whole call */
+  int64_t n_nll;        /* kpsi_nll evaluations */
+  int64_t n_grad;       /* kpsi_nll_and_grad evaluations */
+  int n_iter;           /* variable-metric iterations */
+  int status;           /* 0 converged; 1 call budget exhausted; 2 line search failed;
+                           3 Hessian not positive definite; 4 device error */
+} kpsi_fit_result;
+
+/* Fill opts with the defaults (analytic gradient, tolerance 0.1, up 1, HESSE on). */
+kpsi_status kpsi_fit_default_options(kpsi_fit_options* opts);
+/* Minimise.  params (length kpsi_n_params) is the start point on entry and the minimum on
+ * exit.  cov (optional, n_free x n_free row-major in the order of the free indices)
+ * receives 2 up H^-1 from HESSE, or the final variable-metric estimate when opts->hesse
+ * is 0. */
+kpsi_status kpsi_migrad(kpsi_ctx* ctx, double* params, const int* free_mask, const kpsi_fit_options* opts,
+                        kpsi_fit_result* result, double* cov);
+/* Covariance 2 up H^-1 at params from a numerical Hessian (gradient differences in the
+ * analytic mode, second differences of the NLL otherwise). */
+kpsi_status kpsi_hesse(kpsi_ctx* ctx, const double* params, const int* free_mask, const kpsi_fit_options* opts,
+                       double* cov, kpsi_fit_result* result);
+
 /* Launch tuning: events handled by each thread of the per-event kernel (1..1024), or 0
  * for the automatic choice (about 2048 blocks over the two sets). */
 kpsi_status kpsi_set_events_per_thread(kpsi_ctx* ctx, int ept);

@@ -26,6 +26,7 @@ EXPORTS = [
     "kpsi_load_events_device", "kpsi_set_efficiency_flat", "kpsi_set_efficiency_values", "kpsi_set_efficiency_hist",
     "kpsi_nll", "kpsi_nll_and_grad", "kpsi_density", "kpsi_invariants", "kpsi_generate_phsp", "kpsi_generate_model",
     "kpsi_set_timing", "kpsi_timing", "kpsi_set_events_per_thread", "kpsi_last_error",
+    "kpsi_fit_default_options", "kpsi_migrad", "kpsi_hesse",
 ]
 
 
@@ -42,6 +43,19 @@ class Kinematics(C.Structure):
 class Resonance(C.Structure):
     _fields_ = [("chain", C.c_int), ("spin", C.c_int), ("parity", C.c_int), ("lb", C.c_int), ("lr", C.c_int),
                 ("mass", C.c_double), ("width", C.c_double)]
+
+
+class FitOptions(C.Structure):
+    _fields_ = [("max_calls", C.c_int64), ("tolerance", C.c_double), ("up", C.c_double), ("gradient", C.c_int),
+                ("fd_rel_step", C.c_double), ("hesse", C.c_int)]
+
+
+class FitResult(C.Structure):
+    _fields_ = [("fmin", C.c_double), ("edm", C.c_double), ("wall_seconds", C.c_double), ("n_nll", C.c_int64),
+                ("n_grad", C.c_int64), ("n_iter", C.c_int), ("status", C.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -75,6 +89,9 @@ def lib() -> C.CDLL:
         L.kpsi_set_timing.argtypes = [vp, C.c_int]
         L.kpsi_timing.argtypes = [vp, dp, C.POINTER(i64), C.c_int]
         L.kpsi_set_events_per_thread.argtypes = [vp, C.c_int]
+        L.kpsi_fit_default_options.argtypes = [C.POINTER(FitOptions)]
+        L.kpsi_migrad.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(FitOptions), C.POINTER(FitResult), dp]
+        L.kpsi_hesse.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(FitOptions), dp, C.POINTER(FitResult)]
         L.kpsi_last_error.argtypes = [vp]
         L.kpsi_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -251,6 +268,37 @@ class Engine:
         ms, n = C.c_double(), C.c_int64()
         self._chk(self.L.kpsi_timing(self.h, C.byref(ms), C.byref(n), 1 if reset else 0))
         return ms.value, n.value
+
+    def fit_options(self, **kw) -> FitOptions:
+        o = FitOptions()
+        self._chk(self.L.kpsi_fit_default_options(C.byref(o)))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def migrad(self, params, free_mask, **kw):
+        """Minimise from params over the free entries.  Returns (params_at_min, covariance of
+        the free parameters, FitResult)."""
+        x = _f64(params).copy()
+        m = np.ascontiguousarray(free_mask, dtype=np.int32)
+        nf = int(m.sum())
+        cov = np.empty((nf, nf))
+        o = self.fit_options(**kw)
+        r = FitResult()
+        self._chk(self.L.kpsi_migrad(self.h, _dp(x), m.ctypes.data_as(C.POINTER(C.c_int)), C.byref(o), C.byref(r),
+                                     _dp(cov)))
+        return x, cov, r
+
+    def hesse(self, params, free_mask, **kw):
+        x = _f64(params)
+        m = np.ascontiguousarray(free_mask, dtype=np.int32)
+        nf = int(m.sum())
+        cov = np.empty((nf, nf))
+        o = self.fit_options(**kw)
+        r = FitResult()
+        self._chk(self.L.kpsi_hesse(self.h, _dp(x), m.ctypes.data_as(C.POINTER(C.c_int)), C.byref(o), _dp(cov),
+                                    C.byref(r)))
+        return cov, r
 
     def set_events_per_thread(self, ept: int) -> None:
         self._chk(self.L.kpsi_set_events_per_thread(self.h, ept))

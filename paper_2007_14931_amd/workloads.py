@@ -199,3 +199,16 @@ def neutral_events(n: int, seed: int, peaked: bool = False, edges: bool = False)
         ]).T
         ev[:, :8] = e
     return np.ascontiguousarray(ev)
+
+
+def canonical(res: list[Resonance], par) -> np.ndarray:
+    """Map every coupling pair to magnitude >= 0 and phase in (-pi, pi]: (r, phi) and
+    (-r, phi + pi), and phases 2 pi apart, are the same point of the likelihood."""
+    p = np.array(par, dtype=np.float64, copy=True)
+    nc = sum(2 * r.n_coup for r in res)
+    for k in range(0, nc, 2):
+        if p[k] < 0:
+            p[k] = -p[k]
+            p[k + 1] += math.pi
+        p[k + 1] = math.remainder(p[k + 1], 2 * math.pi)
+    return p

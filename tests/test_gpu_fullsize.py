@@ -1,0 +1,75 @@
+"""Parity at the benchmark's full size and launch configuration: 1,000,000 data events and
+2,000,000 normalisation events, ten K* + Z(4430), K*(1410) and Z(4430) lineshapes floating.
+
+The oracle evaluates the full NLL over all 3e6 events, the gradient along a subset of
+directions (dual numbers over all events), and per-event densities on a sample.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2007_14931_amd import kpsi
+from paper_2007_14931_amd import workloads as W
+
+K = W.KIN
+pytestmark = pytest.mark.gpu
+FLOATING = ("K*(1410)", "Z(4430)")
+
+
+@pytest.fixture(scope="module")
+def full():
+    wl = W.WORKLOADS["full_grad_1m"]
+    res = W.model(wl.model)
+    data = W.neutral_events(wl.n_data, 777, peaked=True)
+    mc = O.gen_phsp(K, 778, wl.n_mc, W.PHSP_WMAX)
+    par = W.params(res, seed=wl.coup_seed)
+    par = par + 0.05 * W.free_mask(res, FLOATING)
+    st, ref, _ = O.nll(K, res, par, data, mc)
+    assert st == 0
+    return res, data, mc, par, ref
+
+
+def _engine(res, prec, data, mc):
+    e = kpsi.Engine(0, prec)
+    e.set_model(K, res)
+    e.set_floating([1 if r.name in FLOATING else 0 for r in res])
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    return e
+
+
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-10), ("fp32", 1e-6)])
+def test_full_size_nll(full, prec, rtol):
+    res, data, mc, par, ref = full
+    e = _engine(res, prec, data, mc)
+    assert e.nll(par) == pytest.approx(ref, rel=rtol)
+    v, g = e.nll_and_grad(par)
+    assert v == pytest.approx(ref, rel=rtol)
+
+
+def test_full_size_gradient_subset(full):
+    res, data, mc, par, ref = full
+    nc = sum(2 * r.n_coup for r in res)
+    i1410 = [r.name for r in res].index("K*(1410)")
+    iz = [r.name for r in res].index("Z(4430)")
+    dirs = [0, 5, W.coupling_offset(res, iz) + 3, nc + 2 * i1410, nc + 2 * i1410 + 1, nc + 2 * iz + 1]
+    st, v, gref = O.nll(K, res, par, data, mc, dirs=dirs)
+    for prec, tol in (("fp64", 1e-8), ("fp32", 3e-4)):
+        v, g = _engine(res, prec, data, mc).nll_and_grad(par)
+        err = np.abs(g[dirs] - gref) / np.max(np.abs(gref))
+        assert np.all(err < tol), (prec, err)
+
+
+def test_full_size_sampled_densities(full):
+    res, data, mc, par, ref = full
+    rng = np.random.default_rng(3)
+    idx_d = np.concatenate([np.arange(2000), rng.choice(data.shape[1], 3000, replace=False)])
+    idx_m = np.concatenate([np.arange(mc.shape[1] - 2000, mc.shape[1]), rng.choice(mc.shape[1], 3000, replace=False)])
+    for prec, rtol in (("fp64", 1e-11), ("fp32", 2e-5)):
+        e = _engine(res, prec, data, mc)
+        sd = e.density(kpsi.DATA, par)[idx_d]
+        sm = e.density(kpsi.NORM, par)[idx_m]
+        od = O.density(K, res, par, data[:, idx_d])
+        om = O.density(K, res, par, mc[:, idx_m])
+        np.testing.assert_allclose(sd, od, rtol=rtol, atol=rtol * 0.1 * od.max())
+        np.testing.assert_allclose(sm, om, rtol=rtol, atol=rtol * 0.1 * om.max())
