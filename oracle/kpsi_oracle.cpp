@@ -717,3 +717,109 @@ extern "C" {
 double oracle_barrier(int L, double p, double p0, double r) { return barrier<double>(L, p, p0, r); }
 double oracle_bw_poly(int L, double z) { return bw_poly<double>(L, z); }
 }
+
+// ================================================================== learned efficiency
+// Reference of the efficiency network: inputs u = (2 (m - lo)/(hi - lo) - 1, cos theta_K*,
+// cos theta_J/psi, phi/pi); z1 = W1 u + b1, h1 = silu(z1); z2 = W2 h1 + b2, h2 = silu(z2);
+// p = sigmoid(w3 . h2 + b3); loss = mean binary cross-entropy against accept labels.
+// The network is defined with BF16 weights and BF16 operands of the 64x64 layer (its
+// matrix-core form): W1, W2, w3, h1 and the 64x64 layer's back-propagated z2 gradient
+// (per event, before the 1/n of the mean) are rounded to BF16 (round to nearest even) where the device rounds them; everything
+// else is FP64 (round_bf16 = 0 gives the plain FP64 network, whose gradient is exact).  The
+// gradient treats the roundings as identity, as the device does.  Parameter layout (4545 floats): W1[64][4], b1[64], W2[64][64], b2[64],
+// w3[64], b3.
+namespace {
+double bf16_round(double x) {
+  float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (double)f;   // inf / nan unchanged
+  const uint32_t lsb = (u >> 16) & 1u;
+  u = (u + 0x7fffu + lsb) & 0xffff0000u;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+double silu(double z) { return z / (1.0 + std::exp(-z)); }
+double dsilu(double z) { double s = 1.0 / (1.0 + std::exp(-z)); return s * (1.0 + z * (1.0 - s)); }
+}  // namespace
+
+extern "C" {
+
+double oracle_bf16(double x) { return bf16_round(x); }
+
+// Forward (probabilities) and, when grad != NULL, the gradient of the mean BCE over the n
+// events with respect to the 4545 parameters.  Returns the mean loss.
+double oracle_mlp(const double* par, int64_t n, const double* u, const double* y, double* prob, double* grad,
+                  int round_bf16) {
+  auto bf16_round = [round_bf16](double x) { return round_bf16 ? ::bf16_round(x) : x; };
+  const double* W1 = par;
+  const double* b1 = par + 256;
+  const double* W2 = par + 320;
+  const double* b2 = par + 4416;
+  const double* w3 = par + 4480;
+  const double b3 = par[4544];
+  std::vector<double> W1r(256), W2r(4096), w3r(64);
+  for (int i = 0; i < 256; ++i) W1r[i] = bf16_round(W1[i]);
+  for (int i = 0; i < 4096; ++i) W2r[i] = bf16_round(W2[i]);
+  for (int i = 0; i < 64; ++i) w3r[i] = bf16_round(w3[i]);
+  if (grad) std::fill(grad, grad + 4545, 0.0);
+  double loss = 0.0;
+  for (int64_t e = 0; e < n; ++e) {
+    double x[4], z1[64], h1[64], z2[64], h2[64];
+    for (int k = 0; k < 4; ++k) x[k] = u[4 * e + k];
+    for (int j = 0; j < 64; ++j) {
+      double s = b1[j];
+      for (int k = 0; k < 4; ++k) s += W1r[4 * j + k] * x[k];
+      z1[j] = s;
+      h1[j] = bf16_round(silu(s));
+    }
+    for (int o = 0; o < 64; ++o) {
+      double s = b2[o];
+      for (int i = 0; i < 64; ++i) s += W2r[64 * o + i] * h1[i];
+      z2[o] = s;
+      h2[o] = silu(s);
+    }
+    double z3 = b3;
+    for (int o = 0; o < 64; ++o) z3 += w3r[o] * h2[o];
+    const double p = 1.0 / (1.0 + std::exp(-z3));
+    if (prob) prob[e] = p;
+    if (y) {
+      const double pc = std::min(std::max(p, 1e-12), 1.0 - 1e-12);
+      loss += -(y[e] * std::log(pc) + (1.0 - y[e]) * std::log(1.0 - pc));
+    }
+    if (!grad) continue;
+    const double dz3 = (p - y[e]) / (double)n;
+    grad[4544] += dz3;
+    double dz2[64];
+    for (int o = 0; o < 64; ++o) {
+      grad[4480 + o] += dz3 * h2[o];
+      dz2[o] = dz3 * w3r[o] * dsilu(z2[o]);
+      grad[4416 + o] += dz2[o];
+    }
+    double dz2r[64];
+    for (int o = 0; o < 64; ++o) dz2r[o] = bf16_round(dz2[o] * (double)n) / (double)n;
+    for (int o = 0; o < 64; ++o)
+      for (int i = 0; i < 64; ++i) grad[320 + 64 * o + i] += dz2r[o] * h1[i];
+    for (int i = 0; i < 64; ++i) {
+      double dh1 = 0.0;
+      for (int o = 0; o < 64; ++o) dh1 += dz2r[o] * W2r[64 * o + i];
+      const double dz1 = dh1 * dsilu(z1[i]);
+      grad[256 + i] += dz1;
+      for (int k = 0; k < 4; ++k) grad[4 * i + k] += dz1 * x[k];
+    }
+  }
+  return y ? loss / (double)n : 0.0;
+}
+
+// Network input of an event.
+void oracle_mlp_inputs(double m_lo, double m_hi, int64_t n, const double* m, const double* cK, const double* cJ,
+                       const double* phi, double* u) {
+  for (int64_t e = 0; e < n; ++e) {
+    u[4 * e + 0] = 2.0 * (m[e] - m_lo) / (m_hi - m_lo) - 1.0;
+    u[4 * e + 1] = cK[e];
+    u[4 * e + 2] = cJ[e];
+    u[4 * e + 3] = phi[e] / M_PI;
+  }
+}
+
+}  // extern "C"

@@ -228,3 +228,37 @@ def bw_poly(L: int, z: float) -> float:
     f.argtypes = [C.c_int, C.c_double]
     f.restype = C.c_double
     return f(L, z)
+
+
+def mlp(par, u, y=None, grad: bool = False, round_bf16: bool = True):
+    """Reference network: returns (mean loss, probabilities, gradient or None)."""
+    par = _f64(par)
+    u = _f64(u).reshape(-1, 4)
+    n = u.shape[0]
+    prob = np.zeros(n)
+    g = np.zeros(4545) if grad else None
+    yy = _f64(y) if y is not None else None
+    f = lib().oracle_mlp
+    f.argtypes = [C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int]
+    f.restype = C.c_double
+    loss = f(_dp(par), n, _dp(u), _dp(yy) if yy is not None else None, _dp(prob), _dp(g) if g is not None else None,
+             1 if round_bf16 else 0)
+    return loss, prob, g
+
+
+def mlp_inputs(m_lo: float, m_hi: float, ev) -> np.ndarray:
+    ev = _f64(ev)
+    n = ev.shape[1]
+    u = np.zeros((n, 4))
+    f = lib().oracle_mlp_inputs
+    f.argtypes = [C.c_double, C.c_double, C.c_int64] + [C.POINTER(C.c_double)] * 5
+    f(m_lo, m_hi, n, *(_dp(_f64(ev[i])) for i in range(4)), _dp(u))
+    return u
+
+
+def bf16(x: float) -> float:
+    f = lib().oracle_bf16
+    f.argtypes = [C.c_double]
+    f.restype = C.c_double
+    return f(x)

@@ -212,3 +212,20 @@ def canonical(res: list[Resonance], par) -> np.ndarray:
             p[k + 1] += math.pi
         p[k + 1] = math.remainder(p[k + 1], 2 * math.pi)
     return p
+
+
+# Efficiency network: 4 -> 64 -> 64 -> 1; parameter layout W1[64][4], b1[64], W2[64][64], b2[64], w3[64], b3.
+MLP_NPARAMS = 4545
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Seeded starting point of the efficiency network (uniform Glorot ranges, zero biases,
+    output bias at the logit of 0.6)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = np.zeros(MLP_NPARAMS, dtype=np.float32)
+    a1, a2, a3 = np.sqrt(6 / (4 + 64)), np.sqrt(6 / (64 + 64)), np.sqrt(6 / (64 + 1))
+    p[0:256] = rng.uniform(-a1, a1, 256) * 2.0
+    p[320:4416] = rng.uniform(-a2, a2, 4096)
+    p[4480:4544] = rng.uniform(-a3, a3, 64)
+    p[4544] = np.log(0.6 / 0.4)
+    return p

@@ -539,3 +539,44 @@ def test_acceptance_range():
     hi = O.acceptance(c1, W.M_LO, W.M_HI, np.array([[W.M_HI], [1.0], [1.0], [math.pi]]))
     assert lo[0] == pytest.approx(0.3, rel=1e-12)
     assert hi[0] == pytest.approx(0.9, rel=1e-12)
+
+
+# ---------------------------------------------------------------- efficiency network reference
+def test_network_reference_gradient_matches_central_differences():
+    ev = W.neutral_events(40, 2)
+    u = O.mlp_inputs(W.M_LO, W.M_HI, ev)
+    y = (np.arange(40) % 3 == 0).astype(float)
+    p = W.mlp_init(4).astype(np.float64)
+    p[256:320] = np.linspace(-0.3, 0.3, 64)
+    loss, prob, g = O.mlp(p, u, y, grad=True, round_bf16=False)
+    rng = np.random.default_rng(0)
+    for i in list(rng.choice(4545, 40, replace=False)) + [0, 255, 256, 319, 320, 4415, 4416, 4479, 4480, 4544]:
+        h = 1e-5
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (O.mlp(pp, u, y, round_bf16=False)[0] - O.mlp(pm, u, y, round_bf16=False)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, abs=1e-8 + 1e-6 * abs(fd))
+
+
+def test_network_reference_probability_and_loss_closed_form():
+    # with all weights zero the network outputs sigmoid(b3) and the loss is the BCE of that constant
+    p = np.zeros(4545)
+    p[4544] = 0.3
+    u = O.mlp_inputs(W.M_LO, W.M_HI, W.neutral_events(10, 3))
+    y = np.array([1, 0, 1, 1, 0, 0, 1, 0, 1, 1], dtype=float)
+    loss, prob, g = O.mlp(p, u, y, grad=True)
+    s = 1 / (1 + math.exp(-0.3))
+    np.testing.assert_allclose(prob, s, rtol=1e-15)
+    assert loss == pytest.approx(-(y * math.log(s) + (1 - y) * math.log(1 - s)).mean(), rel=1e-14)
+    assert g[4544] == pytest.approx((s - y).mean(), rel=1e-14)
+
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    # BF16 keeps 8 significant bits: spacing 2^-7 at 1; ties go to the even mantissa
+    assert O.bf16(1.0 + 2 ** -8) == 1.0
+    assert O.bf16(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6
+    assert O.bf16(1.0 + 2 ** -8 + 2 ** -12) == 1.0 + 2 ** -7
+    assert O.bf16(-2.5) == -2.5
+    assert O.bf16(3.0e38) == pytest.approx(3.0e38, rel=2 ** -8)
