@@ -145,10 +145,12 @@ kpsi_status kpsi_generate_model(kpsi_ctx* ctx, const double* params, uint64_t se
                                 double smax, const double* acc_coef, double* m_kpi, double* cos_k, double* cos_j,
                                 double* phi, int64_t* n_prop, int64_t* n_over);
 
-/* Device timing of the per-event kernel: when enabled, each nll / nll_and_grad call
- * records HIP events around it on the context stream.  kpsi_timing returns the summed
- * kernel milliseconds and the number of calls since the last reset. */
-kpsi_status kpsi_set_timing(kpsi_ctx* ctx, int enable);
+/* Device timing of the per-event kernel: with every = k > 0, every k-th nll /
+ * nll_and_grad call (counting from the first after this call) records HIP events around
+ * the kernel on the context stream; every = 0 turns timing off.  kpsi_timing returns the
+ * summed kernel milliseconds and the number of timed calls since the last reset.
+ * KPSI_E_ARG if every < 0. */
+kpsi_status kpsi_set_timing(kpsi_ctx* ctx, int every);
 kpsi_status kpsi_timing(kpsi_ctx* ctx, double* kernel_ms, int64_t* n_calls, int reset);
 
 /* ---------------------------------------------------------------- fit driver
@@ -192,6 +194,69 @@ kpsi_status kpsi_migrad(kpsi_ctx* ctx, double* params, const int* free_mask, con
  * analytic mode, second differences of the NLL otherwise). */
 kpsi_status kpsi_hesse(kpsi_ctx* ctx, const double* params, const int* free_mask, const kpsi_fit_options* opts,
                        double* cov, kpsi_fit_result* result);
+
+/* Normalisation through the interference matrix (the per-resonance-pair form of the MC
+ * normalisation sum): sum_j eps_j S(y_j) = sum_kl c_k conj(c_l) I_kl with
+ * I_kl = sum_j eps_j sum_xi B_k,xi(y_j) conj(B_l,xi(y_j)) over the complex couplings c_k and
+ * per-event component amplitudes B_k,xi of Eq. 4 and Eq. 10, plus the matrices
+ * D^p_kl = sum_j eps_j sum_xi dB_k,xi/dp conj(B_l,xi) for the floating lineshapes.  They are
+ * built with FP64 matrix-core products over the normalisation set and depend only on the
+ * masses and widths, so a call whose masses and widths equal those of the cached build
+ * evaluates only the data events.
+ *   mode 0: off (default; every call evaluates both sets)
+ *   mode 1: on (rebuild whenever masses or widths change)
+ *   mode 2: auto (use the cache when it matches; rebuild only when the same masses and
+ *           widths are seen on two consecutive calls, e.g. coupling-only finite differences)
+ * Loading the normalisation set, changing the efficiency, the model or the floating set
+ * drops the cache. */
+kpsi_status kpsi_set_norm_cache(kpsi_ctx* ctx, int mode);
+/* Cache builds, calls served from the cache, and the device milliseconds of the last build. */
+kpsi_status kpsi_norm_cache_stats(const kpsi_ctx* ctx, int64_t* builds, int64_t* hits, double* last_build_ms);
+
+/* ---------------------------------------------------------------- learned efficiency
+ * The relative efficiency eps(Phi) of Eq. 14 learned by a 4 -> 64 -> 64 -> 1 network
+ * (SiLU, SiLU, sigmoid) from accepted / generated phase-space events: the sigmoid output is
+ * the acceptance probability.  The 64x64 layer runs on BF16 matrix cores with FP32
+ * accumulation (forward, weight gradient and input gradient); FP32 master weights.
+ * Parameters: 4545 floats, W1[64][4], b1[64], W2[64][64] (row = output), b2[64], w3[64], b3.
+ * Input map: (2 (m - lo)/(hi - lo) - 1, cos theta_K*, cos theta_J/psi, phi/pi) with
+ * [lo, hi] the m_Kpi range of the context's kinematics (set the model first).
+ * Event arrays of these calls are device pointers of n doubles (borrowed for the call). */
+typedef struct {
+  int epochs;          /* passes over the training events */
+  int64_t batch;       /* events per Adam step */
+  double lr;           /* Adam step size */
+  double beta1, beta2, eps;
+} kpsi_mlp_options;
+
+kpsi_status kpsi_mlp_default_options(kpsi_mlp_options* opts);
+/* Accept labels of events e0 .. e0+n-1 under the seeded analytic acceptance acc_coef (12
+ * doubles): label = [u < eps_true], u from Philox4x32-10 counter (event, 0, 3) with key seed.
+ * label: device uint8 array of n; eps_true: optional device double array of n. */
+kpsi_status kpsi_accept_labels(kpsi_ctx* ctx, uint64_t seed, int64_t e0, int64_t n, const double* m_kpi,
+                               const double* cos_k, const double* cos_j, const double* phi, const double* acc_coef,
+                               uint8_t* label, double* eps_true);
+/* Binned efficiency from labelled events: table (host, nb[0]*nb[1]*nb[2]*nb[3] floats,
+ * row-major) = accepted / generated per bin; bins without generated events take the overall
+ * accepted fraction. */
+kpsi_status kpsi_hist_efficiency(kpsi_ctx* ctx, int64_t n, const double* m_kpi, const double* cos_k,
+                                 const double* cos_j, const double* phi, const uint8_t* label, const int nb[4],
+                                 const double lo[4], const double hi[4], float* table);
+/* Mean binary cross-entropy of the network over n labelled events and its gradient with
+ * respect to the 4545 parameters (host output). */
+kpsi_status kpsi_mlp_grad(kpsi_ctx* ctx, const float* params, int64_t n, const double* m_kpi, const double* cos_k,
+                          const double* cos_j, const double* phi, const uint8_t* label, double* grad, double* loss);
+/* Adam training over the labelled events; params (host, 4545) is the start point on entry and
+ * the trained network on exit; *loss receives the mean loss of the last epoch. */
+kpsi_status kpsi_mlp_train(kpsi_ctx* ctx, float* params, int64_t n, const double* m_kpi, const double* cos_k,
+                           const double* cos_j, const double* phi, const uint8_t* label,
+                           const kpsi_mlp_options* opts, double* loss);
+/* Network output (probabilities) for n events into the device array out. */
+kpsi_status kpsi_mlp_eval(kpsi_ctx* ctx, const float* params, int64_t n, const double* m_kpi, const double* cos_k,
+                          const double* cos_j, const double* phi, double* out);
+/* Efficiency of every normalisation event from the network, evaluated once on the device and
+ * kept as the per-event efficiency column (it does not depend on the fit parameters). */
+kpsi_status kpsi_set_efficiency_mlp(kpsi_ctx* ctx, const float* params);
 
 /* Launch tuning: events handled by each thread of the per-event kernel (1..1024), or 0
  * for the automatic choice (about 2048 blocks over the two sets). */

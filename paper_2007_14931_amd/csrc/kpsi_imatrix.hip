@@ -1,0 +1,311 @@
+// Interference matrix of the normalisation integral (gfx950, FP64 MFMA).
+//
+// With a_xi = sum_k c_k B_k,xi (complex couplings c_k, per-event component amplitudes
+// B_k,xi = A_R(m) x angular factor of Eq. 4 or Eq. 10), the MC normalisation sum is
+//   sum_j eps_j S(y_j) = sum_kl c_k conj(c_l) I_kl,   I_kl = sum_j eps_j sum_xi B_k,xi conj(B_l,xi),
+// and its derivative with respect to a lineshape parameter p of resonance R needs
+//   D^p_kl = sum_j eps_j sum_xi dB_k,xi/dp conj(B_l,xi)   (k in R).
+// Both are blocks of the real Gram matrix G = X_w^T X of the matrix X whose rows are
+// (event, xi) and whose columns are the real and imaginary parts of the components
+// followed by the derivative components; X_w is X with each row scaled by eps.  G is
+// accumulated with v_mfma_f64_16x16x4f64 over 16x16 tiles of its upper triangle.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "kpsi_internal.h"
+
+namespace kpsi {
+
+namespace im {
+
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq_(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  double e = __builtin_fma(-h * r, r, 0.5);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-h * r, r, 0.5);
+  return __builtin_fma(r, e, r);
+}
+template <int L, typename T> __device__ __forceinline__ T bpoly(T z) {
+  if constexpr (L == 0) return T(1);
+  else if constexpr (L == 1) return T(1) + z;
+  else if constexpr (L == 2) return T(9) + z * (T(3) + z);
+  else if constexpr (L == 3) return T(225) + z * (T(45) + z * (T(6) + z));
+  else return T(11025) + z * (T(1575) + z * (T(135) + z * (T(10) + z)));
+}
+template <typename T, int n> __device__ __forceinline__ T ipow(T x) {
+  T r = T(1);
+#pragma unroll
+  for (int i = 0; i < n; ++i) r *= x;
+  return r;
+}
+template <int J, typename T> __device__ __forceinline__ T d00(T c) {
+  if constexpr (J == 0) return T(1);
+  else if constexpr (J == 1) return c;
+  else if constexpr (J == 2) return T(1.5) * c * c - T(0.5);
+  else if constexpr (J == 3) return c * (T(2.5) * c * c - T(1.5));
+  else { T c2 = c * c; return (T(35) * c2 * c2 - T(30) * c2 + T(3)) * T(0.125); }
+}
+template <int J, typename T> __device__ __forceinline__ T d10(T c, T s) {
+  if constexpr (J == 1) return -s * T(0.70710678118654752440);
+  else if constexpr (J == 2) return -s * c * T(1.22474487139158904910);
+  else if constexpr (J == 3) return -s * (T(15) * c * c - T(3)) * T(0.14433756729740644113);
+  else if constexpr (J == 4) return -s * c * (T(35) * c * c - T(15)) * T(0.11180339887498948482);
+  else return T(0);
+}
+template <class Sh> __host__ __device__ constexpr int slot_base(int J) {
+  int b = 0;
+  for (int j = 0; j < J; ++j) b += Sh::N[j];
+  return b;
+}
+template <class Sh> __host__ __device__ constexpr int comp_base(int J) {   // first component of spin J
+  int b = 0;
+  for (int j = 0; j < J; ++j) b += Sh::N[j] * (j == 0 ? 1 : 3);
+  return b;
+}
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+}  // namespace im
+
+// One wavefront per block.  Each tile holds 32 events (64 rows: xi = +1, -1).
+template <typename T, class Sh, int C>
+__global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
+  using namespace im;
+  constexpr int NT = C / 16;
+  constexpr int NTILE = NT * (NT + 1) / 2;
+  constexpr int LDX = C + 2;
+  constexpr int NZ = Sh::NZ;
+  __shared__ double X[64 * LDX];
+  __shared__ double Wr[64];
+  const int lane = threadIdx.x;
+  d4_t acc[NTILE];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t) acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t ntiles = (a.n + 31) / 32;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // ---- rows of this tile: lane l < 32 fills rows 2l (xi = +1) and 2l + 1 (xi = -1)
+    for (int i = lane; i < 64 * LDX; i += 64) X[i] = 0.0;
+    __syncthreads();
+    const int64_t e = tile * 32 + (lane & 31);
+    if (lane < 32 && e < a.n) {
+      const T* col = a.cols;
+      const int64_t ld = a.ld;
+      const T m = col[e], q = col[ld + e], pB = col[2 * ld + e];
+      const T cK = col[3 * ld + e], sK = col[4 * ld + e];
+      const T cJ = col[5 * ld + e], sJ = col[6 * ld + e];
+      const T cph = col[7 * ld + e], sph = col[8 * ld + e];
+      const T m2 = m * m, im_ = rcp_(m);
+      const T zR = (a.rR * q) * (a.rR * q), zB = (a.rB * pB) * (a.rB * pB);
+      const T qm = q * im_, pbm = pB * a.invMB, qq = q * q;
+      const T hp = T(0.5) * (T(1) + cJ), hm = T(0.5) * (T(1) - cJ), s0 = sJ * T(0.70710678118654752440);
+      double* rp = X + (2 * lane) * LDX;
+      double* rm = X + (2 * lane + 1) * LDX;
+      Wr[2 * lane] = a.eps ? (double)a.eps[e] : 1.0;
+      Wr[2 * lane + 1] = Wr[2 * lane];
+      // write a component (or derivative) column: value A times angular pair (gp, gm)
+      auto put = [&](int c, T Ar, T Ai, T gpr, T gpi, T gmr, T gmi) {
+        rp[2 * c] = (double)(Ar * gpr - Ai * gpi);
+        rp[2 * c + 1] = (double)(Ar * gpi + Ai * gpr);
+        rm[2 * c] = (double)(Ar * gmr - Ai * gmi);
+        rm[2 * c + 1] = (double)(Ar * gmi + Ai * gmr);
+      };
+      // angular pairs of lambda = +1, 0, -1 for d^J_{lambda 0} = 1
+      const T ep_r = cph * hp, ep_i = sph * hp, em_r = cph * hm, em_i = sph * hm;     // e^{+i phi} (hp, hm)
+      const T fp_r = cph * hm, fp_i = -sph * hm, fm_r = cph * hp, fm_i = -sph * hp;   // e^{-i phi} (hm, hp)
+      auto do_spin = [&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        if constexpr (Sh::N[J] > 0) {
+          constexpr int LB = (J == 0) ? 1 : J - 1;
+          const T BR = bpoly<J>(zR), BB = bpoly<LB>(zB);
+          const T nJ = ipow<T, LB>(pbm) * ipow<T, J>(qm) * rsq_(BR * BB);
+          const T gJ = qm * ipow<T, J>(qq) * rcp_(BR);
+          const T a0 = d00<J>(cK), a1 = d10<J>(cK, sK);
+#pragma unroll
+          for (int j = 0; j < Sh::N[J]; ++j) {
+            if (j >= a.cnt[J]) continue;
+            const auto& rc = a.ks[slot_base<Sh>(J) + j];
+            const T dre = rc.M2 - m2, dim = -rc.P * gJ;
+            const T inv = rcp_(dre * dre + dim * dim);
+            const T sc = rc.K * nJ * inv;
+            const T Ar = sc * dre, Ai = -sc * dim;
+            const int c0 = comp_base<Sh>(J) + (J == 0 ? j : 3 * j);
+            // derivative factors: dA/dM = A (kappa - Y), dA/dGamma0 = A i (P/Gamma0) g conj(den)/|den|^2
+            T dMr = 0, dMi = 0, dGr = 0, dGi = 0;
+            if (rc.flt >= 0) {
+              const T pr = rc.twoM, pim = -rc.dP * gJ;
+              const T Yr = (pr * dre + pim * dim) * inv, Yi = (pim * dre - pr * dim) * inv;
+              const T kr = rc.kap - Yr, ki = -Yi;
+              dMr = Ar * kr - Ai * ki;
+              dMi = Ar * ki + Ai * kr;
+              const T zf = rc.PoG * gJ * inv;
+              const T zr = zf * dim, zi = zf * dre;
+              dGr = Ar * zr - Ai * zi;
+              dGi = Ar * zi + Ai * zr;
+            }
+            if constexpr (J == 0) {
+              put(c0, Ar, Ai, s0, T(0), -s0, T(0));
+              if (rc.flt >= 0) {
+                const int dc = a.dcol[rc.flt];
+                put(dc, dMr, dMi, s0, T(0), -s0, T(0));
+                put(dc + 1, dGr, dGi, s0, T(0), -s0, T(0));
+              }
+            } else {
+              // lambda = -1: -d10 e^{-i phi}(hm, hp); 0: d00 (s0, -s0); +1: d10 e^{+i phi}(hp, hm)
+              const T g1r = -a1 * fp_r, g1i = -a1 * fp_i, g2r = -a1 * fm_r, g2i = -a1 * fm_i;
+              const T h1r = a0 * s0, h2r = -a0 * s0;
+              const T k1r = a1 * ep_r, k1i = a1 * ep_i, k2r = a1 * em_r, k2i = a1 * em_i;
+              put(c0, Ar, Ai, g1r, g1i, g2r, g2i);
+              put(c0 + 1, Ar, Ai, h1r, T(0), h2r, T(0));
+              put(c0 + 2, Ar, Ai, k1r, k1i, k2r, k2i);
+              if (rc.flt >= 0) {
+                const int dc = a.dcol[rc.flt];
+                put(dc, dMr, dMi, g1r, g1i, g2r, g2i);
+                put(dc + 1, dMr, dMi, h1r, T(0), h2r, T(0));
+                put(dc + 2, dMr, dMi, k1r, k1i, k2r, k2i);
+                put(dc + 3, dGr, dGi, g1r, g1i, g2r, g2i);
+                put(dc + 4, dGr, dGi, h1r, T(0), h2r, T(0));
+                put(dc + 5, dGr, dGi, k1r, k1i, k2r, k2i);
+              }
+            }
+          }
+        }
+      };
+      do_spin(std::integral_constant<int, 0>{});
+      do_spin(std::integral_constant<int, 1>{});
+      do_spin(std::integral_constant<int, 2>{});
+      do_spin(std::integral_constant<int, 3>{});
+      do_spin(std::integral_constant<int, 4>{});
+      if constexpr (NZ > 0) {
+        if (a.cnt[5] > 0) {
+          const T mz2 = col[9 * ld + e], nz = col[10 * ld + e], gz = col[11 * ld + e];
+          T za[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) za[i] = col[(12 + i) * ld + e];
+          constexpr int zc0 = comp_base<Sh>(5);
+#pragma unroll
+          for (int z = 0; z < NZ; ++z) {
+            if (z >= a.cnt[5]) continue;
+            const auto& rc = a.zs[z];
+            const T dre = rc.M2 - mz2, dim = -rc.P * gz;
+            const T inv = rcp_(dre * dre + dim * dim);
+            const T sc = rc.K * nz * inv;
+            const T Ar = sc * dre, Ai = -sc * dim;
+            put(zc0 + 2 * z, Ar, Ai, za[0], za[1], za[2], za[3]);
+            put(zc0 + 2 * z + 1, Ar, Ai, za[4], za[5], za[6], za[7]);
+            if (rc.flt >= 0) {
+              const T pr = rc.twoM, pim = -rc.dP * gz;
+              const T Yr = (pr * dre + pim * dim) * inv, Yi = (pim * dre - pr * dim) * inv;
+              const T kr = rc.kap - Yr, ki = -Yi;
+              const T dMr = Ar * kr - Ai * ki, dMi = Ar * ki + Ai * kr;
+              const T zf = rc.PoG * gz * inv;
+              const T zr = zf * dim, zi = zf * dre;
+              const T dGr = Ar * zr - Ai * zi, dGi = Ar * zi + Ai * zr;
+              const int dc = a.dcol[rc.flt];
+              put(dc, dMr, dMi, za[0], za[1], za[2], za[3]);
+              put(dc + 1, dMr, dMi, za[4], za[5], za[6], za[7]);
+              put(dc + 2, dGr, dGi, za[0], za[1], za[2], za[3]);
+              put(dc + 3, dGr, dGi, za[4], za[5], za[6], za[7]);
+            }
+          }
+        }
+      }
+    } else if (lane < 32) {
+      Wr[2 * lane] = 0.0;
+      Wr[2 * lane + 1] = 0.0;
+    }
+    __syncthreads();
+    // ---- Gram tiles: A[i][k] = w_row X[row][16 ti + i], B[k][j] = X[row][16 tj + j],
+    //      row = 4 s + k; lane = i + 16 k provides A[i][k] and B[k][j = i].
+    const int r16 = lane & 15, k4 = lane >> 4;
+    int t = 0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti) {
+#pragma unroll
+      for (int tj = ti; tj < NT; ++tj) {
+#pragma unroll 4
+        for (int s = 0; s < 16; ++s) {
+          const int row = 4 * s + k4;
+          const double av = Wr[row] * X[row * LDX + 16 * ti + r16];
+          const double bv = X[row * LDX + 16 * tj + r16];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+        }
+        ++t;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- block partial, value-major: value (t, lane, reg) at partial[((t*64 + lane)*4 + reg) * nb + block]
+  const int nb = gridDim.x;
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a.partial[(((int64_t)t * 64 + lane) * 4 + r) * nb + blockIdx.x] = acc[t][r];
+  }
+}
+
+// Fixed-order compensated sum over blocks of value-major partials: out[v] = sum_b p[v*nb + b].
+__global__ __launch_bounds__(256) void reduce_values(const double* __restrict__ partial, int nb, double* out) {
+  const int v = blockIdx.x;
+  const double* p = partial + (int64_t)v * nb;
+  double s = 0.0, c = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    const double x = p[b];
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  __shared__ double S[256], Cc[256];
+  S[threadIdx.x] = s;
+  Cc[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double a = S[threadIdx.x], b = S[threadIdx.x + w];
+      const double tt = a + b, bp = tt - a;
+      const double err = (a - (tt - bp)) + (b - bp);
+      S[threadIdx.x] = tt;
+      Cc[threadIdx.x] = Cc[threadIdx.x] + Cc[threadIdx.x + w] + err;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = S[0] + Cc[0];
+}
+
+template <typename T, class Sh, int C>
+hipError_t launch_imatrix_c(const ImArgs<T, Sh>& a, int nb, double* out, hipStream_t st) {
+  hipLaunchKernelGGL((imatrix_kernel<T, Sh, C>), dim3(nb), dim3(64), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  constexpr int NT = C / 16;
+  const int nv = NT * (NT + 1) / 2 * 256;
+  hipLaunchKernelGGL(reduce_values, dim3(nv), dim3(256), 0, st, a.partial, nb, out);
+  return hipGetLastError();
+}
+
+template <typename T, class Sh>
+hipError_t launch_imatrix(const ImArgs<T, Sh>& a, int ncols, int nb, double* out, hipStream_t st) {
+  if (ncols <= 16) return launch_imatrix_c<T, Sh, 16>(a, nb, out, st);
+  if (ncols <= 32) return launch_imatrix_c<T, Sh, 32>(a, nb, out, st);
+  if (ncols <= 64) return launch_imatrix_c<T, Sh, 64>(a, nb, out, st);
+  if (ncols <= 80) return launch_imatrix_c<T, Sh, 80>(a, nb, out, st);
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_imatrix<float, ShapeSmall>(const ImArgs<float, ShapeSmall>&, int, int, double*, hipStream_t);
+template hipError_t launch_imatrix<double, ShapeSmall>(const ImArgs<double, ShapeSmall>&, int, int, double*, hipStream_t);
+template hipError_t launch_imatrix<float, ShapeFull>(const ImArgs<float, ShapeFull>&, int, int, double*, hipStream_t);
+template hipError_t launch_imatrix<double, ShapeFull>(const ImArgs<double, ShapeFull>&, int, int, double*, hipStream_t);
+
+}  // namespace kpsi

@@ -100,7 +100,61 @@ struct CompactArgs {
   double* out[4];
 };
 
+// Interference-matrix build: per-event component amplitudes of the normalisation set.
+template <typename T, class Sh> struct ImArgs {
+  const T* cols;
+  int64_t ld, n;
+  const T* eps;         // per-event efficiency or null
+  double* partial;      // value-major block partials of the Gram tiles
+  int cnt[6];
+  int dcol[NFL];        // first derivative component of floating slot f
+  T rR, rB, invMB;
+  RC<T> ks[Sh::NK > 0 ? Sh::NK : 1];
+  RC<T> zs[Sh::NZ > 0 ? Sh::NZ : 1];
+};
+
+struct MlpArgs {
+  const double* obs[4];
+  const uint8_t* label;   // accept labels (training) or null
+  const float* params;    // FP32 master parameters (4545)
+  float* partial;         // value-major block gradients (4546 values x blocks)
+  double* out;            // probabilities (evaluation)
+  double lo, hi;          // m_Kpi range of the input map
+  int64_t n, per_block;
+};
+
+struct LabelArgs {
+  const double* obs[4];
+  uint64_t seed;
+  int64_t e0, n;
+  double coef[12];
+  double delta, lo, hi;
+  uint8_t* label;
+  double* eps_out;        // optional true efficiency per event
+};
+
+struct HistCountArgs {
+  const double* obs[4];
+  const uint8_t* label;
+  int nb[4];
+  double lo[4], hi[4];
+  int64_t n;
+  unsigned int* gen;
+  unsigned int* acc;
+};
+
+size_t mlp_smem_bytes();
+hipError_t launch_mlp_grad(const MlpArgs& a, int nb, hipStream_t st);
+hipError_t launch_mlp_reduce(const float* partial, int nb, int nv, double scale, double* out, hipStream_t st);
+hipError_t launch_adam(float* p, float* m, float* v, const double* g, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, hipStream_t st);
+hipError_t launch_mlp_eval(const MlpArgs& a, int nb, hipStream_t st);
+hipError_t launch_labels(const LabelArgs& a, hipStream_t st);
+hipError_t launch_hist_count(const HistCountArgs& a, hipStream_t st);
+
 template <typename T> hipError_t launch_invariants(const InvArgs<T>& a, hipStream_t st);
+template <typename T, class Sh>
+hipError_t launch_imatrix(const ImArgs<T, Sh>& a, int ncols, int nb, double* out, hipStream_t st);
 template <typename T, class Sh> hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st);
 hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int nv, double* out, hipStream_t st);
 hipError_t launch_hist_lookup(const HistArgs& a, hipStream_t st);

@@ -56,11 +56,28 @@ struct kpsi_ctx {
   double* red = nullptr;        // device view of red_host
   double* red_host = nullptr;   // [2][NACC], mapped pinned host memory
   std::string err;
-  bool timing = false;
+  bool timing = false;           // this call records timing events
+  int timing_every = 0;          // time every k-th call (0: off)
+  int64_t timing_calls = 0;      // calls since timing was set
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double t_ms = 0.0;
   int64_t t_n = 0;
   int ept_override = 0;
+  // interference-matrix cache of the normalisation sum (mode 0 off, 1 on, 2 auto)
+  int cache_mode = 0;
+  bool cache_valid = false;
+  std::vector<double> cache_ls;           // lineshape parameters the cache was built at
+  std::vector<double> last_ls;            // lineshape parameters of the previous call (auto mode)
+  int cache_ncomp = 0, cache_ncols = 0;   // complex components, derivative components
+  std::vector<double> cache_I;            // ncomp x ncomp complex (re, im), sums over the set
+  std::vector<double> cache_D;            // (ncols - ncomp) x ncomp complex
+  int cache_dcol[NFL] = {0, 0};
+  double* cache_partial = nullptr;
+  size_t cache_partial_cap = 0;
+  double* cache_out = nullptr;
+  size_t cache_out_cap = 0;
+  int64_t cache_builds = 0, cache_hits = 0;
+  double cache_build_ms = 0.0;
 };
 
 namespace {
@@ -289,6 +306,219 @@ kpsi_status validate(kpsi_ctx* c, int64_t n, const double* const* obs) {
   return KPSI_OK;
 }
 
+// ---------------------------------------------------------------- interference-matrix cache
+void invalidate_cache(kpsi_ctx* c) { c->cache_valid = false; c->last_ls.clear(); }
+
+// Complex components in accumulator order: K* slots by spin (1 or 3 each), then Z slots (2).
+int n_components(int shape) {
+  int N[5], NZ;
+  shape_counts(shape, N, &NZ);
+  int n = 0;
+  for (int j = 0; j < 5; ++j) n += N[j] * (j == 0 ? 1 : 3);
+  return n + 2 * NZ;
+}
+// First component and component count of table resonance i.
+void components_of(const kpsi_ctx* c, size_t i, int* first, int* count) {
+  int N[5], NZ;
+  shape_counts(c->shape, N, &NZ);
+  const kpsi_resonance& r = c->res[i];
+  if (r.chain == 1) {
+    int nk = 0;
+    for (int j = 0; j < 5; ++j) nk += N[j] * (j == 0 ? 1 : 3);
+    *first = nk + 2 * c->slot[i];
+    *count = 2;
+    return;
+  }
+  int base = 0, slot0 = 0;
+  for (int j = 0; j < r.spin; ++j) { base += N[j] * (j == 0 ? 1 : 3); slot0 += N[j]; }
+  *first = base + (c->slot[i] - slot0) * (r.spin == 0 ? 1 : 3);
+  *count = r.spin == 0 ? 1 : 3;
+}
+// Complex couplings in component order.
+std::vector<double> component_couplings(const kpsi_ctx* c, const double* par) {
+  std::vector<double> cv(2 * n_components(c->shape), 0.0);
+  for (size_t i = 0; i < c->res.size(); ++i) {
+    int k0, nk;
+    components_of(c, i, &k0, &nk);
+    const double* p = par + c->coff[i];
+    for (int l = 0; l < nk; ++l) {
+      cv[2 * (k0 + l)] = p[2 * l] * std::cos(p[2 * l + 1]);
+      cv[2 * (k0 + l) + 1] = p[2 * l] * std::sin(p[2 * l + 1]);
+    }
+  }
+  return cv;
+}
+std::vector<double> lineshape_params(const kpsi_ctx* c, const double* par) {
+  const int ncr = c->nparams - 2 * (int)c->res.size();
+  return std::vector<double>(par + ncr, par + c->nparams);
+}
+
+template <typename T, class Sh> kpsi_status build_cache_t(kpsi_ctx* c, const double* par) {
+  const DevSet& d = c->set[1];
+  const int ncomp = n_components(c->shape);
+  int nderiv = 0;
+  int dcol[NFL] = {0, 0};
+  for (size_t i = 0; i < c->res.size(); ++i) {
+    if (c->fslot[i] < 0) continue;
+    int k0, nk;
+    components_of(c, i, &k0, &nk);
+    dcol[c->fslot[i]] = ncomp + nderiv;
+    nderiv += 2 * nk;
+  }
+  const int ncx = ncomp + nderiv;
+  const int ncols = 2 * ncx;
+  const int C = ncols <= 16 ? 16 : ncols <= 32 ? 32 : ncols <= 64 ? 64 : ncols <= 80 ? 80 : 0;
+  if (!C) return fail(c, KPSI_E_UNSUPPORTED, "interference matrix of %d columns exceeds the compiled 80", ncols);
+  const int NT = C / 16, NTILE = NT * (NT + 1) / 2, nv = NTILE * 256;
+  const int64_t ntiles = (d.n + 31) / 32;
+  const int nb = (int)std::min<int64_t>(ntiles, 1024);
+  const size_t need = (size_t)nv * nb;
+  if (need > c->cache_partial_cap) {
+    if (c->cache_partial) hipFree(c->cache_partial);
+    c->cache_partial = nullptr;
+    c->cache_partial_cap = 0;
+    if (hipMalloc(&c->cache_partial, need * sizeof(double)) != hipSuccess) return fail(c, KPSI_E_OOM, "cache partials");
+    c->cache_partial_cap = need;
+  }
+  if ((size_t)nv > c->cache_out_cap) {
+    if (c->cache_out) hipFree(c->cache_out);
+    c->cache_out = nullptr;
+    c->cache_out_cap = 0;
+    if (hipMalloc(&c->cache_out, nv * sizeof(double)) != hipSuccess) return fail(c, KPSI_E_OOM, "cache output");
+    c->cache_out_cap = nv;
+  }
+  AmpArgs<T, Sh> pa{};
+  pack<T, Sh>(c, par, pa);
+  ImArgs<T, Sh> a{};
+  a.cols = (const T*)d.cols;
+  a.ld = d.ld;
+  a.n = d.n;
+  a.eps = (const T*)c->eps;
+  a.partial = c->cache_partial;
+  for (int j = 0; j < 6; ++j) a.cnt[j] = pa.cnt[j];
+  for (int f = 0; f < NFL; ++f) a.dcol[f] = dcol[f];
+  a.rR = pa.rR; a.rB = pa.rB; a.invMB = pa.invMB;
+  for (int k = 0; k < (Sh::NK > 0 ? Sh::NK : 1); ++k) a.ks[k] = pa.ks[k];
+  for (int k = 0; k < (Sh::NZ > 0 ? Sh::NZ : 1); ++k) a.zs[k] = pa.zs[k];
+  hipEvent_t e0 = c->ev0, e1 = c->ev1;
+  hipEventRecord(e0, c->stream);
+  hipError_t e = launch_imatrix<T, Sh>(a, ncols, nb, c->cache_out, c->stream);
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "interference matrix: %s", hipGetErrorString(e));
+  hipEventRecord(e1, c->stream);
+  std::vector<double> out(nv);
+  HIPCHECK(c, hipMemcpyAsync(out.data(), c->cache_out, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) c->cache_build_ms = ms;
+  // real Gram matrix G from its upper 16x16 tiles.  The FP64 16x16x4 MFMA accumulator holds, in
+  // lane l and register r, row l/16 + 4 r and column l % 16 of the tile (rows interleaved across
+  // the four registers, unlike the 32-bit-accumulator forms): tile t, lane, reg ->
+  // row 16 ti + lane/16 + 4 reg, column 16 tj + lane % 16
+  std::vector<double> G((size_t)C * C, 0.0);
+  int t = 0;
+  for (int ti = 0; ti < NT; ++ti)
+    for (int tj = ti; tj < NT; ++tj, ++t)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * ti + lane / 16 + 4 * r, col = 16 * tj + lane % 16;
+          const double v = out[((size_t)t * 64 + lane) * 4 + r];
+          G[(size_t)row * C + col] = v;
+          G[(size_t)col * C + row] = v;
+        }
+  // complex blocks: sum B_k conj(B_l) = (G[2k][2l] + G[2k+1][2l+1]) + i (G[2k+1][2l] - G[2k][2l+1])
+  auto cre = [&](int k, int l) { return G[(size_t)(2 * k) * C + 2 * l] + G[(size_t)(2 * k + 1) * C + 2 * l + 1]; };
+  auto cim = [&](int k, int l) { return G[(size_t)(2 * k + 1) * C + 2 * l] - G[(size_t)(2 * k) * C + 2 * l + 1]; };
+  c->cache_I.assign(2 * (size_t)ncomp * ncomp, 0.0);
+  for (int k = 0; k < ncomp; ++k)
+    for (int l = 0; l < ncomp; ++l) {
+      c->cache_I[2 * ((size_t)k * ncomp + l)] = cre(k, l);
+      c->cache_I[2 * ((size_t)k * ncomp + l) + 1] = cim(k, l);
+    }
+  c->cache_D.assign(2 * (size_t)nderiv * ncomp, 0.0);
+  for (int dd = 0; dd < nderiv; ++dd)
+    for (int l = 0; l < ncomp; ++l) {
+      c->cache_D[2 * ((size_t)dd * ncomp + l)] = cre(ncomp + dd, l);
+      c->cache_D[2 * ((size_t)dd * ncomp + l) + 1] = cim(ncomp + dd, l);
+    }
+  c->cache_ncomp = ncomp;
+  c->cache_ncols = ncx;
+  for (int f = 0; f < NFL; ++f) c->cache_dcol[f] = dcol[f];
+  c->cache_ls = lineshape_params(c, par);
+  c->cache_valid = true;
+  c->cache_builds++;
+  return KPSI_OK;
+}
+
+kpsi_status build_cache(kpsi_ctx* c, const double* par) {
+  if (c->prec == KPSI_FP32)
+    return c->shape == 0 ? build_cache_t<float, ShapeSmall>(c, par) : build_cache_t<float, ShapeFull>(c, par);
+  return c->shape == 0 ? build_cache_t<double, ShapeSmall>(c, par) : build_cache_t<double, ShapeFull>(c, par);
+}
+
+// Normalisation record (what the per-event kernel accumulates over the normalisation set)
+// from the cached matrices: sum eps S = c^T I conj(c), coupling sensitivities (I conj(c))_k,
+// and Re sum_{k in R} c_k (D^p conj(c))_k for the floating lineshapes.
+void cached_norm_record(const kpsi_ctx* c, const double* par, double* rm) {
+  const int n = c->cache_ncomp;
+  const std::vector<double> cv = component_couplings(c, par);
+  for (int v = 0; v < NACC; ++v) rm[v] = 0.0;
+  double smr = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double gr = 0.0, gi = 0.0;   // (I conj(c))_k
+    for (int l = 0; l < n; ++l) {
+      const double ir = c->cache_I[2 * ((size_t)k * n + l)], ii = c->cache_I[2 * ((size_t)k * n + l) + 1];
+      const double cr = cv[2 * l], ci = -cv[2 * l + 1];
+      gr += ir * cr - ii * ci;
+      gi += ir * ci + ii * cr;
+    }
+    rm[3 + 2 * k] = gr;
+    rm[3 + 2 * k + 1] = gi;
+    smr += cv[2 * k] * gr - cv[2 * k + 1] * gi;   // Re(c_k g_k)
+  }
+  rm[0] = smr;
+  int N[5], NZ;
+  shape_counts(c->shape, N, &NZ);
+  int nkacc = 0;
+  for (int j = 0; j < 5; ++j) nkacc += N[j] * (j == 0 ? 2 : 6);
+  for (size_t i = 0; i < c->res.size(); ++i) {
+    const int f = c->fslot[i];
+    if (f < 0) continue;
+    int k0, nk;
+    components_of(c, i, &k0, &nk);
+    for (int p = 0; p < 2; ++p) {
+      double val = 0.0;
+      for (int q = 0; q < nk; ++q) {
+        const int dd = c->cache_dcol[f] - n + p * nk + q;
+        double gr = 0.0, gi = 0.0;
+        for (int l = 0; l < n; ++l) {
+          const double dr = c->cache_D[2 * ((size_t)dd * n + l)], di = c->cache_D[2 * ((size_t)dd * n + l) + 1];
+          const double cr = cv[2 * l], ci = -cv[2 * l + 1];
+          gr += dr * cr - di * ci;
+          gi += dr * ci + di * cr;
+        }
+        const double ckr = cv[2 * (k0 + q)], cki = cv[2 * (k0 + q) + 1];
+        val += ckr * gr - cki * gi;
+      }
+      rm[3 + nkacc + 4 * NZ + 2 * f + p] = val;
+    }
+  }
+}
+
+// Decide whether this call uses the cache (building it when the policy says so).
+kpsi_status use_cache(kpsi_ctx* c, const double* par, bool* use) {
+  *use = false;
+  if (c->cache_mode == 0) return KPSI_OK;
+  const std::vector<double> ls = lineshape_params(c, par);
+  if (c->cache_valid && ls == c->cache_ls) { *use = true; c->cache_hits++; return KPSI_OK; }
+  const bool build = c->cache_mode == 1 || (c->cache_mode == 2 && ls == c->last_ls);
+  c->last_ls = ls;
+  if (!build) return KPSI_OK;
+  kpsi_status st = build_cache(c, par);
+  if (st) return st;
+  *use = true;
+  return KPSI_OK;
+}
+
 // ---------------------------------------------------------------- per-call driver
 template <typename T, class Sh>
 kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: both*/, double** dens_out) {
@@ -311,10 +541,11 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
     if (st) return st;
   }
   a.partial = c->partial;
-  if (c->timing && mode != MODE_DENSITY) hipEventRecord(c->ev0, c->stream);
+  c->timing = mode != MODE_DENSITY && c->timing_every > 0 && (c->timing_calls++ % c->timing_every) == 0;
+  if (c->timing) hipEventRecord(c->ev0, c->stream);
   hipError_t e = launch_amp<T, Sh>(a, mode, nbd + nbm, c->stream);
   if (e != hipSuccess) return fail(c, KPSI_E_HIP, "amplitude kernel: %s", hipGetErrorString(e));
-  if (c->timing && mode != MODE_DENSITY) hipEventRecord(c->ev1, c->stream);
+  if (c->timing) hipEventRecord(c->ev1, c->stream);
   if (mode == MODE_DENSITY) return KPSI_OK;
   // the final sums are written by the GPU straight into mapped pinned host memory
   e = launch_reduce_final(c->partial, nbd, nbm, mode == MODE_GRAD ? NACC : 3, c->red, c->stream);
@@ -402,6 +633,8 @@ kpsi_status kpsi_destroy(kpsi_ctx* c) {
   }
   if (c->eps) hipFree(c->eps);
   if (c->partial) hipFree(c->partial);
+  if (c->cache_partial) hipFree(c->cache_partial);
+  if (c->cache_out) hipFree(c->cache_out);
   if (c->red_host) hipHostFree(c->red_host);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
@@ -466,6 +699,7 @@ kpsi_status kpsi_set_model(kpsi_ctx* c, const kpsi_kinematics* kin, const kpsi_r
   c->cnt[5] = nz;
   c->nparams = off + 2 * n_res;
   c->has_model = true;
+  invalidate_cache(c);
   hipSetDevice(c->device);
   for (int s = 0; s < 2; ++s) {
     kpsi_status st = derive_columns(c, s);
@@ -494,6 +728,7 @@ kpsi_status kpsi_set_floating(kpsi_ctx* c, const int* flags, int n_res) {
     }
   }
   c->fslot = fs;
+  invalidate_cache(c);
   return KPSI_OK;
 }
 
@@ -525,6 +760,7 @@ kpsi_status kpsi_load_events(kpsi_ctx* c, kpsi_set set, int64_t n, const double*
   if (st) return st;
   d.n = n;
   if (set == KPSI_NORM && c->eps) { hipFree(c->eps); c->eps = nullptr; }
+  if (set == KPSI_NORM) invalidate_cache(c);
   st = derive_columns(c, set);
   if (st) return st;
   HIPCHECK(c, hipStreamSynchronize(c->stream));
@@ -547,6 +783,7 @@ kpsi_status kpsi_load_events_device(kpsi_ctx* c, kpsi_set set, int64_t n, const 
   for (int j = 0; j < 4; ++j) d.obs[j] = src[j];
   d.n = n;
   if (set == KPSI_NORM && c->eps) { hipFree(c->eps); c->eps = nullptr; }
+  if (set == KPSI_NORM) invalidate_cache(c);
   st = derive_columns(c, set);
   if (st) return st;
   HIPCHECK(c, hipStreamSynchronize(c->stream));
@@ -555,6 +792,7 @@ kpsi_status kpsi_load_events_device(kpsi_ctx* c, kpsi_set set, int64_t n, const 
 
 kpsi_status kpsi_set_efficiency_flat(kpsi_ctx* c) {
   if (!c) return KPSI_E_ARG;
+  invalidate_cache(c);
   if (c->eps) hipFree(c->eps);
   c->eps = nullptr;
   return KPSI_OK;
@@ -570,6 +808,7 @@ static kpsi_status eps_from_device_f64(kpsi_ctx* c, const double* d_eps, int64_t
   if (er != hipSuccess) { hipFree(e); return fail(c, KPSI_E_HIP, "efficiency conversion: %s", hipGetErrorString(er)); }
   if (c->eps) hipFree(c->eps);
   c->eps = e;
+  invalidate_cache(c);
   return KPSI_OK;
 }
 
@@ -627,8 +866,12 @@ kpsi_status kpsi_nll(kpsi_ctx* c, const double* params, double* nll) {
   if (st) return st;
   if (!nll) return fail(c, KPSI_E_ARG, "nll is NULL");
   hipSetDevice(c->device);
-  st = dispatch(c, MODE_NLL, params, -1, nullptr);
+  bool cached = false;
+  st = use_cache(c, params, &cached);
   if (st) return st;
+  st = dispatch(c, MODE_NLL, params, cached ? 0 : -1, nullptr);
+  if (st) return st;
+  if (cached) cached_norm_record(c, params, c->red_host + NACC);
   const double* rd = c->red_host;
   const double* rm = c->red_host + NACC;
   const double nd = (double)c->set[0].n, nm = (double)c->set[1].n;
@@ -646,8 +889,12 @@ kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, do
   if (st) return st;
   if (!nll || !grad) return fail(c, KPSI_E_ARG, "nll/grad is NULL");
   hipSetDevice(c->device);
-  st = dispatch(c, MODE_GRAD, params, -1, nullptr);
+  bool cached = false;
+  st = use_cache(c, params, &cached);
   if (st) return st;
+  st = dispatch(c, MODE_GRAD, params, cached ? 0 : -1, nullptr);
+  if (st) return st;
+  if (cached) cached_norm_record(c, params, c->red_host + NACC);
   const double* rd = c->red_host;
   const double* rm = c->red_host + NACC;
   const double nd = (double)c->set[0].n, nm = (double)c->set[1].n;
@@ -894,9 +1141,12 @@ kpsi_status kpsi_generate_model(kpsi_ctx* c, const double* params, uint64_t seed
   return st;
 }
 
-kpsi_status kpsi_set_timing(kpsi_ctx* c, int enable) {
+kpsi_status kpsi_set_timing(kpsi_ctx* c, int every) {
   if (!c) return KPSI_E_ARG;
-  c->timing = enable != 0;
+  if (every < 0) return fail(c, KPSI_E_ARG, "timing interval %d < 0", every);
+  c->timing_every = every;
+  c->timing_calls = 0;
+  c->timing = false;
   return KPSI_OK;
 }
 
@@ -909,6 +1159,248 @@ kpsi_status kpsi_timing(kpsi_ctx* c, double* ms, int64_t* n, int reset) {
 }
 
 const char* kpsi_last_error(const kpsi_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+// ---------------------------------------------------------------- learned efficiency
+static const int MLP_NP = 4545;
+
+kpsi_status kpsi_mlp_default_options(kpsi_mlp_options* o) {
+  if (!o) return KPSI_E_ARG;
+  o->epochs = 20;
+  o->batch = 32768;
+  o->lr = 2e-3;
+  o->beta1 = 0.9;
+  o->beta2 = 0.999;
+  o->eps = 1e-8;
+  return KPSI_OK;
+}
+
+static bool mlp_obs_ok(const double* m, const double* ck, const double* cj, const double* phi) {
+  return m && ck && cj && phi;
+}
+
+static MlpArgs mlp_args(const kpsi_ctx* c, int64_t n, const double* m, const double* ck, const double* cj,
+                        const double* phi) {
+  MlpArgs a{};
+  a.obs[0] = m; a.obs[1] = ck; a.obs[2] = cj; a.obs[3] = phi;
+  a.lo = c->kin.m_k + c->kin.m_pi;
+  a.hi = c->kin.m_b - c->kin.m_jpsi;
+  a.n = n;
+  return a;
+}
+
+kpsi_status kpsi_accept_labels(kpsi_ctx* c, uint64_t seed, int64_t e0, int64_t n, const double* m, const double* ck,
+                               const double* cj, const double* phi, const double* acc_coef, uint8_t* label,
+                               double* eps_true) {
+  if (!c) return KPSI_E_ARG;
+  if (n <= 0 || e0 < 0 || !mlp_obs_ok(m, ck, cj, phi) || !acc_coef || !label) return fail(c, KPSI_E_ARG, "bad arguments");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set (kinematics needed)");
+  hipSetDevice(c->device);
+  LabelArgs a{};
+  a.obs[0] = m; a.obs[1] = ck; a.obs[2] = cj; a.obs[3] = phi;
+  a.seed = seed; a.e0 = e0; a.n = n;
+  for (int j = 0; j < 12; ++j) a.coef[j] = acc_coef[j];
+  a.delta = 1.0 - std::pow(3.0, -0.25);
+  a.lo = c->kin.m_k + c->kin.m_pi;
+  a.hi = c->kin.m_b - c->kin.m_jpsi;
+  a.label = label;
+  a.eps_out = eps_true;
+  hipError_t e = launch_labels(a, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "labels: %s", hipGetErrorString(e));
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_hist_efficiency(kpsi_ctx* c, int64_t n, const double* m, const double* ck, const double* cj,
+                                 const double* phi, const uint8_t* label, const int nb[4], const double lo[4],
+                                 const double hi[4], float* table) {
+  if (!c) return KPSI_E_ARG;
+  if (n <= 0 || !mlp_obs_ok(m, ck, cj, phi) || !label || !nb || !lo || !hi || !table)
+    return fail(c, KPSI_E_ARG, "bad arguments");
+  int64_t nbins = 1;
+  for (int d = 0; d < 4; ++d) {
+    if (nb[d] <= 0 || !(hi[d] > lo[d])) return fail(c, KPSI_E_ARG, "bad histogram axis %d", d);
+    nbins *= nb[d];
+  }
+  hipSetDevice(c->device);
+  unsigned int* cnt = nullptr;
+  if (hipMalloc(&cnt, 2 * nbins * sizeof(unsigned int)) != hipSuccess) return fail(c, KPSI_E_OOM, "histogram counts");
+  HistCountArgs a{};
+  a.obs[0] = m; a.obs[1] = ck; a.obs[2] = cj; a.obs[3] = phi;
+  a.label = label;
+  for (int d = 0; d < 4; ++d) { a.nb[d] = nb[d]; a.lo[d] = lo[d]; a.hi[d] = hi[d]; }
+  a.n = n;
+  a.gen = cnt;
+  a.acc = cnt + nbins;
+  std::vector<unsigned int> h(2 * nbins);
+  hipError_t e = hipMemsetAsync(cnt, 0, 2 * nbins * sizeof(unsigned int), c->stream);
+  if (e == hipSuccess) e = launch_hist_count(a, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), cnt, 2 * nbins * sizeof(unsigned int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(cnt);
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "histogram: %s", hipGetErrorString(e));
+  uint64_t tg = 0, ta = 0;
+  for (int64_t i = 0; i < nbins; ++i) { tg += h[i]; ta += h[nbins + i]; }
+  const float mean = tg ? (float)((double)ta / (double)tg) : 0.0f;
+  for (int64_t i = 0; i < nbins; ++i) table[i] = h[i] ? (float)((double)h[nbins + i] / (double)h[i]) : mean;
+  return KPSI_OK;
+}
+
+// Mean BCE gradient over events [0, n) into the device array g (MLP_NP doubles) and the mean
+// loss into g[MLP_NP].
+static hipError_t mlp_grad_device(kpsi_ctx* c, const float* dparams, int64_t n, const double* m, const double* ck,
+                                  const double* cj, const double* phi, const uint8_t* label, float* partial,
+                                  int nbmax, double* g) {
+  MlpArgs a = mlp_args(c, n, m, ck, cj, phi);
+  a.label = label;
+  a.params = dparams;
+  a.partial = partial;
+  const int64_t tiles = (n + 63) / 64;
+  const int nb = (int)std::min<int64_t>(tiles, nbmax);
+  a.per_block = (tiles + nb - 1) / nb * 64;
+  hipError_t e = launch_mlp_grad(a, nb, c->stream);
+  if (e != hipSuccess) return e;
+  return launch_mlp_reduce(partial, nb, MLP_NP + 1, 1.0 / (double)n, g, c->stream);
+}
+
+kpsi_status kpsi_mlp_grad(kpsi_ctx* c, const float* params, int64_t n, const double* m, const double* ck,
+                          const double* cj, const double* phi, const uint8_t* label, double* grad, double* loss) {
+  if (!c) return KPSI_E_ARG;
+  if (!params || n <= 0 || !mlp_obs_ok(m, ck, cj, phi) || !label || !grad) return fail(c, KPSI_E_ARG, "bad arguments");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set (kinematics needed)");
+  hipSetDevice(c->device);
+  const int nbmax = 512;
+  float *dp = nullptr, *part = nullptr;
+  double* g = nullptr;
+  auto cleanup = [&]() { if (dp) hipFree(dp); if (part) hipFree(part); if (g) hipFree(g); };
+  if (hipMalloc(&dp, MLP_NP * sizeof(float)) || hipMalloc(&part, (size_t)(MLP_NP + 1) * nbmax * sizeof(float)) ||
+      hipMalloc(&g, (MLP_NP + 1) * sizeof(double))) {
+    cleanup();
+    return fail(c, KPSI_E_OOM, "network buffers");
+  }
+  std::vector<double> h(MLP_NP + 1);
+  hipError_t e = hipMemcpyAsync(dp, params, MLP_NP * sizeof(float), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = mlp_grad_device(c, dp, n, m, ck, cj, phi, label, part, nbmax, g);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), g, (MLP_NP + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  cleanup();
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "network gradient: %s", hipGetErrorString(e));
+  for (int i = 0; i < MLP_NP; ++i) grad[i] = h[i];
+  if (loss) *loss = h[MLP_NP];
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_mlp_train(kpsi_ctx* c, float* params, int64_t n, const double* m, const double* ck,
+                           const double* cj, const double* phi, const uint8_t* label, const kpsi_mlp_options* o,
+                           double* loss) {
+  if (!c) return KPSI_E_ARG;
+  if (!params || n <= 0 || !mlp_obs_ok(m, ck, cj, phi) || !label || !o || o->epochs < 0 || o->batch < 64)
+    return fail(c, KPSI_E_ARG, "bad arguments");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set (kinematics needed)");
+  hipSetDevice(c->device);
+  const int nbmax = 512;
+  float *dp = nullptr, *mm = nullptr, *vv = nullptr, *part = nullptr;
+  double* g = nullptr;
+  auto cleanup = [&]() {
+    for (void* p : {(void*)dp, (void*)mm, (void*)vv, (void*)part, (void*)g}) if (p) hipFree(p);
+  };
+  if (hipMalloc(&dp, MLP_NP * sizeof(float)) || hipMalloc(&mm, MLP_NP * sizeof(float)) ||
+      hipMalloc(&vv, MLP_NP * sizeof(float)) || hipMalloc(&part, (size_t)(MLP_NP + 1) * nbmax * sizeof(float)) ||
+      hipMalloc(&g, (MLP_NP + 1) * sizeof(double))) {
+    cleanup();
+    return fail(c, KPSI_E_OOM, "network buffers");
+  }
+  hipError_t e = hipMemcpyAsync(dp, params, MLP_NP * sizeof(float), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(mm, 0, MLP_NP * sizeof(float), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(vv, 0, MLP_NP * sizeof(float), c->stream);
+  const int64_t B = o->batch;
+  const int64_t nbatch = (n + B - 1) / B;
+  int64_t step = 0;
+  double last_loss = 0.0;
+  for (int ep = 0; ep < o->epochs && e == hipSuccess; ++ep) {
+    double eloss = 0.0;
+    for (int64_t b = 0; b < nbatch && e == hipSuccess; ++b) {
+      const int64_t off = b * B, cnt = std::min(B, n - off);
+      e = mlp_grad_device(c, dp, cnt, m + off, ck + off, cj + off, phi + off, label + off, part, nbmax, g);
+      ++step;
+      const float c1 = (float)(1.0 / (1.0 - std::pow(o->beta1, (double)step)));
+      const float c2 = (float)(1.0 / (1.0 - std::pow(o->beta2, (double)step)));
+      if (e == hipSuccess)
+        e = launch_adam(dp, mm, vv, g, MLP_NP, (float)o->lr, (float)o->beta1, (float)o->beta2, (float)o->eps, c1, c2,
+                        c->stream);
+      if (ep == o->epochs - 1 && e == hipSuccess) {
+        double lb = 0.0;
+        e = hipMemcpyAsync(&lb, g + MLP_NP, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        eloss += lb * (double)cnt;
+      }
+    }
+    if (ep == o->epochs - 1) last_loss = eloss / (double)n;
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(params, dp, MLP_NP * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  cleanup();
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "network training: %s", hipGetErrorString(e));
+  if (loss) *loss = last_loss;
+  return KPSI_OK;
+}
+
+static hipError_t mlp_eval_device(kpsi_ctx* c, const float* dparams, int64_t n, const double* m, const double* ck,
+                                  const double* cj, const double* phi, double* out) {
+  MlpArgs a = mlp_args(c, n, m, ck, cj, phi);
+  a.params = dparams;
+  a.out = out;
+  const int64_t tiles = (n + 63) / 64;
+  const int nb = (int)std::min<int64_t>(tiles, 2048);
+  a.per_block = (tiles + nb - 1) / nb * 64;
+  return launch_mlp_eval(a, nb, c->stream);
+}
+
+kpsi_status kpsi_mlp_eval(kpsi_ctx* c, const float* params, int64_t n, const double* m, const double* ck,
+                          const double* cj, const double* phi, double* out) {
+  if (!c) return KPSI_E_ARG;
+  if (!params || n <= 0 || !mlp_obs_ok(m, ck, cj, phi) || !out) return fail(c, KPSI_E_ARG, "bad arguments");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set (kinematics needed)");
+  hipSetDevice(c->device);
+  float* dp = nullptr;
+  if (hipMalloc(&dp, MLP_NP * sizeof(float)) != hipSuccess) return fail(c, KPSI_E_OOM, "network parameters");
+  hipError_t e = hipMemcpyAsync(dp, params, MLP_NP * sizeof(float), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = mlp_eval_device(c, dp, n, m, ck, cj, phi, out);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(dp);
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "network evaluation: %s", hipGetErrorString(e));
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_set_efficiency_mlp(kpsi_ctx* c, const float* params) {
+  if (!c) return KPSI_E_ARG;
+  if (!params) return fail(c, KPSI_E_ARG, "params is NULL");
+  if (c->set[1].n <= 0) return fail(c, KPSI_E_STATE, "load the normalisation set first");
+  hipSetDevice(c->device);
+  const int64_t n = c->set[1].n;
+  double* vals = nullptr;
+  if (hipMalloc(&vals, n * sizeof(double)) != hipSuccess) return fail(c, KPSI_E_OOM, "efficiency values");
+  kpsi_status st = kpsi_mlp_eval(c, params, n, c->set[1].obs[0], c->set[1].obs[1], c->set[1].obs[2],
+                                 c->set[1].obs[3], vals);
+  if (!st) st = eps_from_device_f64(c, vals, n);
+  hipFree(vals);
+  return st;
+}
+
+kpsi_status kpsi_set_norm_cache(kpsi_ctx* c, int mode) {
+  if (!c) return KPSI_E_ARG;
+  if (mode < 0 || mode > 2) return fail(c, KPSI_E_ARG, "cache mode must be 0, 1 or 2");
+  c->cache_mode = mode;
+  invalidate_cache(c);
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_norm_cache_stats(const kpsi_ctx* c, int64_t* builds, int64_t* hits, double* last_build_ms) {
+  if (!c) return KPSI_E_ARG;
+  if (builds) *builds = c->cache_builds;
+  if (hits) *hits = c->cache_hits;
+  if (last_build_ms) *last_build_ms = c->cache_build_ms;
+  return KPSI_OK;
+}
 
 kpsi_status kpsi_set_events_per_thread(kpsi_ctx* c, int ept) {
   if (!c || ept < 0 || ept > 1024) return KPSI_E_ARG;

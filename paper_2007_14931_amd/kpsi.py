@@ -26,8 +26,11 @@ EXPORTS = [
     "kpsi_load_events_device", "kpsi_set_efficiency_flat", "kpsi_set_efficiency_values", "kpsi_set_efficiency_hist",
     "kpsi_nll", "kpsi_nll_and_grad", "kpsi_density", "kpsi_invariants", "kpsi_generate_phsp", "kpsi_generate_model",
     "kpsi_set_timing", "kpsi_timing", "kpsi_set_events_per_thread", "kpsi_last_error",
-    "kpsi_fit_default_options", "kpsi_migrad", "kpsi_hesse",
+    "kpsi_fit_default_options", "kpsi_migrad", "kpsi_hesse", "kpsi_set_norm_cache", "kpsi_norm_cache_stats",
+    "kpsi_mlp_default_options", "kpsi_accept_labels", "kpsi_hist_efficiency", "kpsi_mlp_grad", "kpsi_mlp_train",
+    "kpsi_mlp_eval", "kpsi_set_efficiency_mlp",
 ]
+MLP_NP = 4545
 
 
 class KpsiError(RuntimeError):
@@ -56,6 +59,11 @@ class FitResult(C.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MlpOptions(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int64), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double)]
 
 
 _lib = None
@@ -92,6 +100,16 @@ def lib() -> C.CDLL:
         L.kpsi_fit_default_options.argtypes = [C.POINTER(FitOptions)]
         L.kpsi_migrad.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(FitOptions), C.POINTER(FitResult), dp]
         L.kpsi_hesse.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(FitOptions), dp, C.POINTER(FitResult)]
+        L.kpsi_set_norm_cache.argtypes = [vp, C.c_int]
+        L.kpsi_norm_cache_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), dp]
+        fp = C.POINTER(C.c_float)
+        L.kpsi_mlp_default_options.argtypes = [C.POINTER(MlpOptions)]
+        L.kpsi_accept_labels.argtypes = [vp, C.c_uint64, i64, i64, vp, vp, vp, vp, dp, vp, vp]
+        L.kpsi_hist_efficiency.argtypes = [vp, i64, vp, vp, vp, vp, vp, C.POINTER(C.c_int), dp, dp, fp]
+        L.kpsi_mlp_grad.argtypes = [vp, fp, i64, vp, vp, vp, vp, vp, dp, dp]
+        L.kpsi_mlp_train.argtypes = [vp, fp, i64, vp, vp, vp, vp, vp, C.POINTER(MlpOptions), dp]
+        L.kpsi_mlp_eval.argtypes = [vp, fp, i64, vp, vp, vp, vp, vp]
+        L.kpsi_set_efficiency_mlp.argtypes = [vp, fp]
         L.kpsi_last_error.argtypes = [vp]
         L.kpsi_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -261,8 +279,10 @@ class Engine:
                                              *ptrs, C.byref(npr), C.byref(nov)))
         return ev, npr.value, nov.value
 
-    def set_timing(self, on: bool) -> None:
-        self._chk(self.L.kpsi_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, on: bool | int) -> None:
+        """False/0: off; True: every call; an int k > 1: every k-th call."""
+        every = int(on) if not isinstance(on, bool) else (1 if on else 0)
+        self._chk(self.L.kpsi_set_timing(self.h, every))
 
     def timing(self, reset: bool = False) -> tuple[float, int]:
         ms, n = C.c_double(), C.c_int64()
@@ -299,6 +319,79 @@ class Engine:
         self._chk(self.L.kpsi_hesse(self.h, _dp(x), m.ctypes.data_as(C.POINTER(C.c_int)), C.byref(o), _dp(cov),
                                     C.byref(r)))
         return cov, r
+
+    # ---- learned efficiency (event tensors: CUDA float64 (4, n); labels: CUDA uint8 (n,))
+    @staticmethod
+    def _ev_ptrs(ev):
+        import torch
+        assert ev.is_cuda and ev.dtype == torch.float64 and ev.dim() == 2 and ev.shape[0] == 4 and ev.is_contiguous()
+        return [C.c_void_p(ev[i].data_ptr()) for i in range(4)]
+
+    @staticmethod
+    def _f32(params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == MLP_NP
+        return p
+
+    def accept_labels(self, seed: int, events, acc_coef, e0: int = 0):
+        import torch
+        n = events.shape[1]
+        lab = torch.empty(n, dtype=torch.uint8, device=events.device)
+        eps = torch.empty(n, dtype=torch.float64, device=events.device)
+        co = _f64(acc_coef).reshape(-1)
+        self._chk(self.L.kpsi_accept_labels(self.h, seed, e0, n, *self._ev_ptrs(events), _dp(co),
+                                            C.c_void_p(lab.data_ptr()), C.c_void_p(eps.data_ptr())))
+        return lab, eps
+
+    def hist_efficiency(self, events, labels, nb, lo, hi) -> np.ndarray:
+        nbv = np.ascontiguousarray(nb, dtype=np.int32)
+        lo, hi = _f64(lo), _f64(hi)
+        table = np.empty(int(np.prod(nbv)), dtype=np.float32)
+        self._chk(self.L.kpsi_hist_efficiency(self.h, events.shape[1], *self._ev_ptrs(events),
+                                              C.c_void_p(labels.data_ptr()), nbv.ctypes.data_as(C.POINTER(C.c_int)),
+                                              _dp(lo), _dp(hi), table.ctypes.data_as(C.POINTER(C.c_float))))
+        return table.reshape(tuple(nbv))
+
+    def mlp_grad(self, params, events, labels):
+        p = self._f32(params)
+        g = np.empty(MLP_NP)
+        loss = C.c_double()
+        self._chk(self.L.kpsi_mlp_grad(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), events.shape[1],
+                                       *self._ev_ptrs(events), C.c_void_p(labels.data_ptr()), _dp(g), C.byref(loss)))
+        return g, loss.value
+
+    def mlp_train(self, params, events, labels, **kw):
+        p = self._f32(params).copy()
+        o = MlpOptions()
+        self._chk(self.L.kpsi_mlp_default_options(C.byref(o)))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        loss = C.c_double()
+        self._chk(self.L.kpsi_mlp_train(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), events.shape[1],
+                                        *self._ev_ptrs(events), C.c_void_p(labels.data_ptr()), C.byref(o),
+                                        C.byref(loss)))
+        return p, loss.value
+
+    def mlp_eval(self, params, events):
+        import torch
+        p = self._f32(params)
+        out = torch.empty(events.shape[1], dtype=torch.float64, device=events.device)
+        self._chk(self.L.kpsi_mlp_eval(self.h, p.ctypes.data_as(C.POINTER(C.c_float)), events.shape[1],
+                                       *self._ev_ptrs(events), C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_efficiency_mlp(self, params) -> None:
+        p = self._f32(params)
+        self._chk(self.L.kpsi_set_efficiency_mlp(self.h, p.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def set_norm_cache(self, mode: int) -> None:
+        """0 off, 1 on, 2 auto (see kpsi_set_norm_cache)."""
+        self._chk(self.L.kpsi_set_norm_cache(self.h, mode))
+
+    def norm_cache_stats(self) -> tuple[int, int, float]:
+        b, h, ms = C.c_int64(), C.c_int64(), C.c_double()
+        self._chk(self.L.kpsi_norm_cache_stats(self.h, C.byref(b), C.byref(h), C.byref(ms)))
+        return b.value, h.value, ms.value
 
     def set_events_per_thread(self, ept: int) -> None:
         self._chk(self.L.kpsi_set_events_per_thread(self.h, ept))

@@ -1,0 +1,249 @@
+"""Studies of the efficiency model and the large fit, run on one GPU through libkpsi.
+
+    python -m paper_2007_14931_amd.studies learned_eff   # learned efficiency vs 20^4 histogram
+    python -m paper_2007_14931_amd.studies large_fit     # 10M + 20M events, two Z, end-to-end fit
+    python -m paper_2007_14931_amd.studies pulls         # seeded pseudo-experiments of the 1M-event fit
+
+Each prints one JSON line.  All events are synthetic, from the library's seeded generators:
+flat phase space, accept labels under the seeded analytic acceptance (the paper's
+efficiency templates are 2D x 2D histograms of simulated events; here the truth is known
+exactly, so the efficiency models can be judged against it), and accept-reject data from
+the model times the acceptance.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import kpsi
+from . import workloads as W
+
+
+def log(msg: str) -> None:
+    print(f"[study] {msg}", file=sys.stderr, flush=True)
+
+
+def _lohi():
+    lo = np.array([W.M_LO, -1.0, -1.0, -math.pi])
+    hi = np.array([W.M_HI, 1.0, 1.0, math.pi])
+    return lo, hi
+
+
+def _bins(ev: np.ndarray, nb, lo, hi):
+    return tuple(np.clip(np.floor((ev[d] - lo[d]) / (hi[d] - lo[d]) * nb[d]).astype(int), 0, nb[d] - 1)
+                 for d in range(4))
+
+
+def train_efficiency(gen: "kpsi.Engine", coef, n_train: int, seed: int, epochs: int = 20, nb: int = 20):
+    """Generate labelled phase-space events, train the network, fill the histogram."""
+    t0 = time.perf_counter()
+    train = gen.generate_phsp(seed, n_train, W.PHSP_WMAX)
+    lab, _ = gen.accept_labels(seed + 1, train, coef)
+    t1 = time.perf_counter()
+    par, loss = gen.mlp_train(W.mlp_init(seed), train, lab, epochs=epochs, batch=32768, lr=3e-3)
+    t2 = time.perf_counter()
+    lo, hi = _lohi()
+    table = gen.hist_efficiency(train, lab, (nb,) * 4, lo, hi)
+    t3 = time.perf_counter()
+    return par, table, {"train_events": n_train, "epochs": epochs, "final_loss": loss,
+                        "accept_fraction": float(lab.float().mean().item()),
+                        "generate_s": t1 - t0, "train_s": t2 - t1, "histogram_s": t3 - t2}
+
+
+def efficiency_errors(gen, par, table, coef, n_val: int, seed: int):
+    val = gen.generate_phsp(seed, n_val, W.PHSP_WMAX)
+    _, eps_true = gen.accept_labels(seed + 1, val, coef)
+    eps_true = eps_true.cpu().numpy()
+    eps_nn = gen.mlp_eval(par, val).cpu().numpy()
+    lo, hi = _lohi()
+    eps_h = table[_bins(val.cpu().numpy(), table.shape, lo, hi)]
+    return {"validation_events": n_val,
+            "rms_network_minus_truth": float(np.sqrt(np.mean((eps_nn - eps_true) ** 2))),
+            "rms_histogram_minus_truth": float(np.sqrt(np.mean((eps_h - eps_true) ** 2))),
+            "max_abs_network_minus_truth": float(np.max(np.abs(eps_nn - eps_true)))}
+
+
+def learned_eff(args) -> dict:
+    import torch
+    wl = W.WORKLOADS["learned_eff_1m"]
+    res = W.model(wl.model)
+    truth = W.params(res, wl.coup_seed)
+    coef = W.acceptance_coefficients()
+    stream = torch.cuda.current_stream().cuda_stream
+    gen = kpsi.Engine(0, "fp64", stream)
+    gen.set_model(W.KIN, res)
+    par, table, train_info = train_efficiency(gen, coef, args.train, 2041, epochs=args.epochs)
+    log(f"network trained: {train_info}")
+    errs = efficiency_errors(gen, par, table, coef, 1_000_000, 2051)
+    log(f"efficiency errors: {errs}")
+    # data: accept-reject from eps_true x S; normalisation: flat phase space
+    scan = gen.generate_phsp(2061, 1_000_000, W.PHSP_WMAX)
+    gen.load(kpsi.DATA, scan)
+    smax = 1.5 * float(gen.density(kpsi.DATA, truth).max())
+    data, nprop, nover = gen.generate_model(truth, wl.data_seed, wl.n_data, W.PHSP_WMAX, smax, coef)
+    mc = gen.generate_phsp(wl.mc_seed, wl.n_mc, W.PHSP_WMAX)
+    _, eps_mc = gen.accept_labels(2071, mc, coef)
+    gen.close()
+    mask = W.free_mask(res)
+    fits = {}
+    for name in ("true", "histogram", "network"):
+        e = kpsi.Engine(0, "fp32", stream)
+        e.set_model(W.KIN, res)
+        e.load(kpsi.DATA, data)
+        e.load(kpsi.NORM, mc)
+        if name == "true":
+            e.set_efficiency_values(eps_mc.cpu().numpy())
+        elif name == "histogram":
+            lo, hi = _lohi()
+            e.set_efficiency_hist(table, lo, hi)
+        else:
+            e.set_efficiency_mlp(par)
+        x, cov, r = e.migrad(truth, mask)
+        fits[name] = (W.canonical(res, x), np.sqrt(np.abs(np.diag(cov))), r)
+        log(f"fit with {name} efficiency: status {r.status} fmin {r.fmin:.3f} wall {r.wall_seconds:.3f} s")
+        e.close()
+    free = np.flatnonzero(mask)
+    xt, st, _ = fits["true"]
+    shifts = {}
+    for name in ("histogram", "network"):
+        d = np.abs(fits[name][0][free] - xt[free]) / st
+        shifts[name] = {"mean_abs_shift_sigma": float(d.mean()), "max_abs_shift_sigma": float(d.max())}
+    return {"study": "learned_efficiency", "workload": "learned_eff_1m", "data_events": wl.n_data,
+            "data_proposals": nprop, "norm_events": wl.n_mc, "free_params": int(mask.sum()),
+            "training": train_info, "efficiency_errors": errs,
+            "fit_status": {k: v[2].as_dict() for k, v in fits.items()},
+            "fitted_parameter_shift_vs_true_efficiency": shifts}
+
+
+def large_fit(args) -> dict:
+    import torch
+    wl = W.WORKLOADS["large_2z_10m"]
+    res = W.model(wl.model)
+    truth = W.params(res, wl.coup_seed)
+    floating = wl.floating
+    flags = [1 if r.name in floating else 0 for r in res]
+    coef = W.acceptance_coefficients()
+    stream = torch.cuda.current_stream().cuda_stream
+    n_data, n_mc = int(wl.n_data * args.scale), int(wl.n_mc * args.scale)
+    t0 = time.perf_counter()
+    gen = kpsi.Engine(0, "fp64", stream)
+    gen.set_model(W.KIN, res)
+    par, table, train_info = train_efficiency(gen, coef, args.train, 3041, epochs=args.epochs)
+    scan = gen.generate_phsp(3061, 1_000_000, W.PHSP_WMAX)
+    gen.load(kpsi.DATA, scan)
+    smax = 1.5 * float(gen.density(kpsi.DATA, truth).max())
+    data, nprop, nover = gen.generate_model(truth, wl.data_seed, n_data, W.PHSP_WMAX, smax, coef)
+    mc = gen.generate_phsp(wl.mc_seed, n_mc, W.PHSP_WMAX)
+    gen.close()
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    log(f"prepared {n_data} data ({nprop} proposals) + {n_mc} normalisation events in {t_prep:.1f} s")
+    mask = W.free_mask(res, floating)
+    rng = np.random.default_rng(9)
+    x0 = truth + 0.01 * rng.standard_normal(truth.size) * mask
+    out = {}
+    for name, prec, grad in (("fp32_analytic", "fp32", 1), ("fp64_finite_difference", "fp64", 0)):
+        if name == "fp64_finite_difference" and args.skip_fd:
+            continue
+        t1 = time.perf_counter()
+        e = kpsi.Engine(0, prec, stream)
+        e.set_model(W.KIN, res)
+        e.set_floating(flags)
+        e.load(kpsi.DATA, data)
+        e.load(kpsi.NORM, mc)
+        e.set_efficiency_mlp(par)
+        t_setup = time.perf_counter() - t1
+        x, cov, r = e.migrad(x0, mask, gradient=grad)
+        e.close()
+        out[name] = {"setup_s": t_setup, **r.as_dict(), "x": W.canonical(res, x), "sig": np.sqrt(np.abs(np.diag(cov)))}
+        log(f"{name}: status {r.status} fmin {r.fmin:.3f} migrad+hesse {r.wall_seconds:.2f} s "
+            f"(nll {r.n_nll}, grad {r.n_grad})")
+    free = np.flatnonzero(mask)
+    result = {"study": "large_fit", "workload": "large_2z_10m", "data_events": n_data, "norm_events": n_mc,
+              "free_params": int(mask.sum()), "prepare_s": t_prep, "training": train_info}
+    for k, v in out.items():
+        result[k] = {kk: vv for kk, vv in v.items() if kk not in ("x", "sig")}
+    if len(out) == 2:
+        a, f = out["fp32_analytic"], out["fp64_finite_difference"]
+        d = np.abs(a["x"][free] - f["x"][free]) / f["sig"][free]
+        result["wall_ratio_fd_over_analytic"] = f["wall_seconds"] / a["wall_seconds"]
+        result["max_param_diff_sigma"] = float(d.max())
+        result["median_param_diff_sigma"] = float(np.median(d))
+    pulls = (out["fp32_analytic"]["x"][free] - W.canonical(res, truth)[free]) / out["fp32_analytic"]["sig"][free]
+    result["pull_mean"] = float(pulls.mean())
+    result["pull_rms"] = float(np.sqrt(np.mean(pulls ** 2)))
+    return result
+
+
+def pulls(args) -> dict:
+    """Pseudo-experiments of the 1M-event benchmark fit: each seed draws a new data sample at
+    the truth point, fits it (FP32, device adjoint gradient, MIGRAD + HESSE) from a perturbed
+    start, and records (fitted - true) / sigma for every free parameter."""
+    import torch
+    wl = W.WORKLOADS["full_grad_1m"]
+    res = W.model(wl.model)
+    truth = W.params(res, wl.coup_seed)
+    flags = [1 if r.name in wl.floating else 0 for r in res]
+    mask = W.free_mask(res, wl.floating)
+    free = np.flatnonzero(mask)
+    stream = torch.cuda.current_stream().cuda_stream
+    gen = kpsi.Engine(0, "fp64", stream)
+    gen.set_model(W.KIN, res)
+    scan = gen.generate_phsp(4061, 1_000_000, W.PHSP_WMAX)
+    gen.load(kpsi.DATA, scan)
+    smax = 1.5 * float(gen.density(kpsi.DATA, truth).max())
+    mc = gen.generate_phsp(wl.mc_seed, wl.n_mc, W.PHSP_WMAX)
+    e = kpsi.Engine(0, "fp32", stream)
+    e.set_model(W.KIN, res)
+    e.set_floating(flags)
+    e.load(kpsi.NORM, mc)
+    ct = W.canonical(res, truth)
+    P, statuses, walls = [], [], []
+    for s in range(args.seeds):
+        data, _, _ = gen.generate_model(truth, 5000 + s, wl.n_data, W.PHSP_WMAX, smax)
+        e.load(kpsi.DATA, data)
+        rng = np.random.default_rng(100 + s)
+        x0 = truth + 0.02 * rng.standard_normal(truth.size) * mask
+        x, cov, r = e.migrad(x0, mask)
+        sig = np.sqrt(np.abs(np.diag(cov)))
+        d = W.canonical(res, x)[free] - ct[free]
+        nc = W.n_params(res) - 2 * len(res)
+        for k, i in enumerate(free):   # coupling phases are compared modulo 2 pi
+            if i < nc and i % 2 == 1:
+                d[k] = math.remainder(d[k], 2 * math.pi)
+        P.append(d / sig)
+        statuses.append(r.status)
+        walls.append(r.wall_seconds)
+        log(f"seed {s}: status {r.status} wall {r.wall_seconds:.3f} s  rms pull {np.sqrt(np.mean((d / sig) ** 2)):.2f}")
+        del data
+    e.close()
+    gen.close()
+    P = np.array(P)
+    return {"study": "pulls", "workload": "full_grad_1m", "seeds": args.seeds, "free_params": int(mask.sum()),
+            "fit_status": statuses, "median_fit_wall_s": float(np.median(walls)),
+            "pull_mean_over_params": float(P.mean()), "pull_rms_over_params": float(np.sqrt((P ** 2).mean())),
+            "per_param_mean": [float(v) for v in P.mean(0)], "per_param_std": [float(v) for v in P.std(0)],
+            "frac_within_2sigma": float((np.abs(P) < 2).mean())}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("study", choices=["learned_eff", "large_fit", "pulls"])
+    ap.add_argument("--train", type=int, default=5_000_000, help="labelled training events")
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--scale", type=float, default=1.0, help="fraction of the large-fit event counts")
+    ap.add_argument("--skip-fd", action="store_true")
+    ap.add_argument("--seeds", type=int, default=20)
+    args = ap.parse_args()
+    out = {"learned_eff": learned_eff, "large_fit": large_fit, "pulls": pulls}[args.study](args)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

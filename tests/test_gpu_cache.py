@@ -1,0 +1,97 @@
+"""Normalisation through the cached interference matrix (FP64 matrix-core Gram build).
+
+The cached path must give the same NLL and gradient as evaluating every normalisation
+event (and as the FP64 oracle), rebuild when masses or widths change, and serve
+coupling-only changes without touching the normalisation set.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2007_14931_amd import kpsi
+from paper_2007_14931_amd import workloads as W
+
+K = W.KIN
+pytestmark = pytest.mark.gpu
+
+
+def _setup(model, prec, floating, nd=6007, nm=30011, eps=False):
+    res = W.model(model)
+    data = W.neutral_events(nd, 21, peaked=True)
+    data[0] = np.clip(data[0], W.M_LO + 1e-6, W.M_HI - 1e-6)
+    mc = O.gen_phsp(K, 22, nm, W.PHSP_WMAX)
+    e = kpsi.Engine(0, prec)
+    e.set_model(K, res)
+    e.set_floating([1 if r.name in floating else 0 for r in res])
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    ev = None
+    if eps:
+        ev = O.acceptance(W.acceptance_coefficients(), W.M_LO, W.M_HI, mc)
+        e.set_efficiency_values(ev)
+    return res, data, mc, e, ev
+
+
+@pytest.mark.parametrize("model,floating", [("full", ("K*(1410)", "Z(4430)")), ("kstar892", ("K*(892)",)),
+                                            ("full2z", ("K0*(800)", "Z(4240)"))])
+def test_cached_matches_direct_and_oracle_fp64(model, floating):
+    res, data, mc, e, _ = _setup(model, "fp64", floating)
+    par = W.params(res, seed=5) + 0.03 * W.free_mask(res, floating)
+    v0, g0 = e.nll_and_grad(par)
+    e.set_norm_cache(1)
+    v1, g1 = e.nll_and_grad(par)
+    assert e.norm_cache_stats()[0] == 1
+    assert v1 == pytest.approx(v0, rel=1e-12)
+    free = np.flatnonzero(W.free_mask(res, floating))
+    np.testing.assert_allclose(g1[free], g0[free], rtol=1e-9, atol=1e-9 * np.abs(g0[free]).max())
+    st, ref, gref = O.nll(K, res, par, data, mc, dirs=free)
+    assert v1 == pytest.approx(ref, rel=1e-10)
+    assert np.max(np.abs(g1[free] - gref)) / np.max(np.abs(gref)) < 1e-9
+    # couplings only: served from the cache
+    p2 = par.copy()
+    p2[0] += 0.1
+    p2[3] -= 0.2
+    v2 = e.nll(p2)
+    b, h, ms = e.norm_cache_stats()
+    assert b == 1 and h >= 1
+    assert v2 == pytest.approx(O.nll(K, res, p2, data, mc)[1], rel=1e-10)
+    # a mass change rebuilds
+    nc = sum(2 * r.n_coup for r in res)
+    i = [r.name for r in res].index(floating[0])
+    p3 = p2.copy()
+    p3[nc + 2 * i] += 0.004
+    v3 = e.nll(p3)
+    assert e.norm_cache_stats()[0] == 2
+    assert v3 == pytest.approx(O.nll(K, res, p3, data, mc)[1], rel=1e-10)
+
+
+def test_cached_fp32_and_efficiency():
+    floating = ("K*(1410)", "Z(4430)")
+    res, data, mc, e, eps = _setup("full", "fp32", floating, eps=True)
+    par = W.params(res, seed=6)
+    e.set_norm_cache(1)
+    v, g = e.nll_and_grad(par)
+    free = np.flatnonzero(W.free_mask(res, floating))
+    st, ref, gref = O.nll(K, res, par, data, mc, eps=eps, dirs=free)
+    assert v == pytest.approx(ref, rel=1e-6)
+    assert np.max(np.abs(g[free] - gref)) / np.max(np.abs(gref)) < 2e-5
+
+
+def test_auto_mode_builds_on_repeated_lineshape_point():
+    res, data, mc, e, _ = _setup("full", "fp64", ())
+    par = W.params(res, seed=7)
+    e.set_norm_cache(2)
+    e.nll(par)                       # first sight: direct evaluation
+    assert e.norm_cache_stats()[0] == 0
+    p2 = par.copy()
+    p2[4] += 0.01
+    e.nll(p2)                        # same masses and widths again: build
+    assert e.norm_cache_stats()[0] == 1
+    e.nll(par)                       # served from the cache
+    b, h, _ = e.norm_cache_stats()
+    assert b == 1 and h >= 1
+    # reloading the normalisation set drops the cache
+    e.load(kpsi.NORM, mc)
+    e.nll(par)
+    assert e.norm_cache_stats()[0] == 1
+    assert e.nll(par) == pytest.approx(O.nll(K, res, par, data, mc)[1], rel=1e-10)
