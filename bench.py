@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 # Algorithmic floating-point work per event of one NLL+gradient call of this workload
 # (fused multiply-add = 2, reciprocal/rsqrt/log = 1), from the op count of the
 # per-call formulation: forward amplitudes 541, adjoint 418.
+TIMING_EVERY = 10
 FLOP_PER_EVENT = {"full_grad": 959}
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}        # MI355X published vector peaks
 PEAK_TFLOPS_UNPACKED = {"f32": 78.6, "f64": 78.6}  # without packed-FP32 instructions
@@ -77,24 +78,33 @@ def cpu_baseline(res, par, floating, n_data: int, n_mc: int, seconds: float = 15
 
 
 def fit_comparison(make, truth, mask, canonical_fn) -> dict:
-    """Full MIGRAD + HESSE fit of the benchmark workload twice from the same start point:
-    FP32 amplitudes with the device adjoint gradient, and the plain FP64 likelihood with
-    central finite-difference gradients.  Reports wall time, likelihood calls and how far
+    """Full MIGRAD + HESSE fit of the benchmark workload from the same start point: FP32
+    amplitudes with the device adjoint gradient; the plain FP64 likelihood with central
+    finite-difference gradients; and the same FP64 finite-difference fit with the
+    interference-matrix cache in auto mode (coupling-only steps reuse the normalisation).  Reports wall time, likelihood calls and how far
     apart the two minima are in units of the FP64 HESSE errors (couplings compared as
     magnitude >= 0, phase in (-pi, pi])."""
     rng = np.random.default_rng(7)
     x0 = truth + 0.01 * rng.standard_normal(truth.size) * mask
     free = np.flatnonzero(mask)
     runs = {}
-    for name, prec, grad in (("fp32_analytic", "fp32", 1), ("fp64_finite_difference", "fp64", 0)):
+    cache_stats = None
+    for name, prec, grad, cache in (("fp32_analytic", "fp32", 1, 0), ("fp64_finite_difference", "fp64", 0, 0),
+                                    ("fp64_finite_difference_cached", "fp64", 0, 2)):
         e = make(prec)
+        if cache:
+            e.set_norm_cache(cache)   # auto: coupling-only steps reuse the normalisation matrix
         x, cov, r = e.migrad(x0, mask, gradient=grad)
+        if cache:
+            b, h, ms = e.norm_cache_stats()
+            cache_stats = {"builds": b, "hits": h, "last_build_ms": ms}
         e.close()
         runs[name] = (x, cov, r)
         log(f"fit {name}: status {r.status} fmin {r.fmin:.4f} edm {r.edm:.2e} wall {r.wall_seconds:.3f} s "
             f"nll calls {r.n_nll} grad calls {r.n_grad}")
     xa, ca, ra = runs["fp32_analytic"]
     xf, cf, rf = runs["fp64_finite_difference"]
+    xc, cc, rc = runs["fp64_finite_difference_cached"]
     xa, xf = canonical_fn(xa), canonical_fn(xf)
     sig = np.sqrt(np.abs(np.diag(cf)))
     sig_a = np.sqrt(np.abs(np.diag(ca)))
@@ -106,7 +116,11 @@ def fit_comparison(make, truth, mask, canonical_fn) -> dict:
         "largest_differences": worst,
         "fp32_analytic": ra.as_dict(),
         "fp64_finite_difference": rf.as_dict(),
+        "fp64_finite_difference_cached": {**rc.as_dict(), "norm_cache": cache_stats,
+                                          "max_param_diff_sigma_vs_uncached":
+                                              float(np.max(np.abs(canonical_fn(xc)[free] - xf[free]) / sig))},
         "wall_ratio_fd_over_analytic": rf.wall_seconds / ra.wall_seconds,
+        "wall_ratio_fd_over_fd_cached": rf.wall_seconds / rc.wall_seconds,
         "max_param_diff_sigma": float(dev.max()),
         "median_param_diff_sigma": float(np.median(dev)),
         "error_ratio_max_dev": float(np.max(np.abs(np.sqrt(np.abs(np.diag(ca))) / sig - 1.0))),
@@ -117,8 +131,8 @@ def fit_comparison(make, truth, mask, canonical_fn) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=10000)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -129,7 +143,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported on this build "
-              "(the per-call work shards by events with one small all-reduce; see DESIGN.md)", file=sys.stderr)
+              "(the per-call work shards by events with one small all-reduce of the reduced sums)", file=sys.stderr)
         return 2
 
     import torch
@@ -181,7 +195,9 @@ def main() -> int:
     eng = make(args.precision)
     for _ in range(args.warmup):
         eng.nll_and_grad(par)
-    eng.set_timing(True)
+    # HIP events around the kernel on every TIMING_EVERY-th call of the timed region: the
+    # kernel duration is measured live, without event records on every step
+    eng.set_timing(TIMING_EVERY)
     eng.timing(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -202,9 +218,9 @@ def main() -> int:
     # the other precision, for the record (same events, same parameters)
     other = "fp64" if args.precision == "fp32" else "fp32"
     e2 = make(other)
-    for _ in range(5):
+    for _ in range(50):
         e2.nll_and_grad(par)
-    e2.set_timing(True)
+    e2.set_timing(TIMING_EVERY)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n2 = max(20, args.steps // 5)

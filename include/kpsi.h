@@ -205,10 +205,12 @@ kpsi_status kpsi_hesse(kpsi_ctx* ctx, const double* params, const int* free_mask
  * evaluates only the data events.
  *   mode 0: off (default; every call evaluates both sets)
  *   mode 1: on (rebuild whenever masses or widths change)
- *   mode 2: auto (use the cache when it matches; rebuild only when the same masses and
- *           widths are seen on two consecutive calls, e.g. coupling-only finite differences)
+ *   mode 2: auto (use the cache when it matches; build only after KPSI_CACHE_AUTO_STREAK
+ *           consecutive calls at the same masses and widths, e.g. the coupling directions of
+ *           a finite-difference gradient; a build costs about as much as 20-30 direct calls)
  * Loading the normalisation set, changing the efficiency, the model or the floating set
  * drops the cache. */
+#define KPSI_CACHE_AUTO_STREAK 16
 kpsi_status kpsi_set_norm_cache(kpsi_ctx* ctx, int mode);
 /* Cache builds, calls served from the cache, and the device milliseconds of the last build. */
 kpsi_status kpsi_norm_cache_stats(const kpsi_ctx* ctx, int64_t* builds, int64_t* hits, double* last_build_ms);

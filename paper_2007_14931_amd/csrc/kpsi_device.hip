@@ -44,6 +44,11 @@ __device__ __forceinline__ float log_(float x) { return __logf(x); }
 __device__ __forceinline__ double log_(double x) { return log(x); }
 
 template <typename T> __device__ __forceinline__ T ldnt(const T* p) { return __builtin_nontemporal_load(p); }
+// Load at a uniform base plus a 32-bit per-lane byte offset: this maps onto the
+// scalar-base + vector-offset address form, so no per-lane 64-bit address arithmetic.
+template <typename T> __device__ __forceinline__ T ldoff(const T* base, uint32_t off_bytes) {
+  return __builtin_nontemporal_load((const T*)((const char*)base + off_bytes));
+}
 
 // Opaque copy of a pointer to uniform kernel-argument data.  Re-deriving it inside the
 // event loop keeps the compiler from hoisting every per-resonance constant out of the
@@ -271,12 +276,16 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
     for (int i = 0; i < 4 * NZ; ++i) gz[i] = 0;
   }
 
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+  const T* __restrict__ cb = col + e0;   // column 0 at this block's first event
+  const uint32_t n_blk = (uint32_t)(e1 > e0 ? e1 - e0 : 0);
+  for (uint32_t i = threadIdx.x; i < n_blk; i += 256) {
+    const int64_t e = e0 + i;
+    const uint32_t ob = i * (uint32_t)sizeof(T);
     const auto& ka = *kernarg_laundered<AmpArgs<T, Sh>>();
-    const T m = ldnt(col + e), q = ldnt(col + ld + e), pB = ldnt(col + 2 * ld + e);
-    const T cK = ldnt(col + 3 * ld + e), sK = ldnt(col + 4 * ld + e);
-    const T cJ = ldnt(col + 5 * ld + e), sJ = ldnt(col + 6 * ld + e);
-    const T cph = ldnt(col + 7 * ld + e), sph = ldnt(col + 8 * ld + e);
+    const T m = ldoff(cb, ob), q = ldoff(cb + ld, ob), pB = ldoff(cb + 2 * ld, ob);
+    const T cK = ldoff(cb + 3 * ld, ob), sK = ldoff(cb + 4 * ld, ob);
+    const T cJ = ldoff(cb + 5 * ld, ob), sJ = ldoff(cb + 6 * ld, ob);
+    const T cph = ldoff(cb + 7 * ld, ob), sph = ldoff(cb + 8 * ld, ob);
 
     const T m2 = m * m;
     const T im = rcp_(m);
@@ -367,10 +376,10 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
     T gzv = T(0), dzr[NZ > 0 ? NZ : 1], dzi[NZ > 0 ? NZ : 1], zinv[NZ > 0 ? NZ : 1];
     if constexpr (NZ > 0) {
       if (a.cnt[5] > 0) {
-        const T mz2 = ldnt(col + 9 * ld + e), nz = ldnt(col + 10 * ld + e);
-        gzv = ldnt(col + 11 * ld + e);
+        const T mz2 = ldoff(cb + 9 * ld, ob), nz = ldoff(cb + 10 * ld, ob);
+        gzv = ldoff(cb + 11 * ld, ob);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) za[i] = ldnt(col + (12 + i) * ld + e);
+        for (int k = 0; k < 8; ++k) za[k] = ldoff(cb + (12 + k) * ld, ob);
         Cx<T> T0{T(0), T(0)}, T1{T(0), T(0)};
 #pragma unroll
         for (int z = 0; z < NZ; ++z) {
@@ -411,7 +420,7 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
       ms = t;
       w = rcp_(S);
     } else {
-      const T eps = a.eps ? ldnt(a.eps + e) : T(1);
+      const T eps = a.eps ? ldoff(a.eps + e0, ob) : T(1);
       const double x = (double)(eps * S);
       const double y = x - mc;
       const double t = ms + y;
@@ -793,6 +802,22 @@ hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_
   else hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_DENSITY>), dim3(nblocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
+// Blocks of the per-event kernel that can be resident on one compute unit at once (from its
+// register and LDS use), or 0 if the runtime cannot tell.
+template <typename T, class Sh>
+int amp_blocks_per_cu(int mode) {
+  int nb = 0;
+  hipError_t e;
+  if (mode == MODE_GRAD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_GRAD>, 256, 0);
+  else if (mode == MODE_NLL) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_NLL>, 256, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_DENSITY>, 256, 0);
+  return (e == hipSuccess && nb > 0) ? nb : 0;
+}
+template int amp_blocks_per_cu<float, ShapeSmall>(int);
+template int amp_blocks_per_cu<double, ShapeSmall>(int);
+template int amp_blocks_per_cu<float, ShapeFull>(int);
+template int amp_blocks_per_cu<double, ShapeFull>(int);
+
 template hipError_t launch_amp<float, ShapeSmall>(const AmpArgs<float, ShapeSmall>&, int, int, hipStream_t);
 template hipError_t launch_amp<double, ShapeSmall>(const AmpArgs<double, ShapeSmall>&, int, int, hipStream_t);
 template hipError_t launch_amp<float, ShapeFull>(const AmpArgs<float, ShapeFull>&, int, int, hipStream_t);

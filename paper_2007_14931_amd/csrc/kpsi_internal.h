@@ -156,6 +156,7 @@ template <typename T> hipError_t launch_invariants(const InvArgs<T>& a, hipStrea
 template <typename T, class Sh>
 hipError_t launch_imatrix(const ImArgs<T, Sh>& a, int ncols, int nb, double* out, hipStream_t st);
 template <typename T, class Sh> hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st);
+template <typename T, class Sh> int amp_blocks_per_cu(int mode);
 hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int nv, double* out, hipStream_t st);
 hipError_t launch_hist_lookup(const HistArgs& a, hipStream_t st);
 hipError_t launch_phsp(const GenArgs& a, hipStream_t st);

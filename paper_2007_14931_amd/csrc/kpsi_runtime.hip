@@ -63,11 +63,14 @@ struct kpsi_ctx {
   double t_ms = 0.0;
   int64_t t_n = 0;
   int ept_override = 0;
+  int n_cu = 0;                                                   // compute units of the device
+  int blocks_per_cu[2][3] = {{-1, -1, -1}, {-1, -1, -1}};         // [shape][mode], -1: not queried
   // interference-matrix cache of the normalisation sum (mode 0 off, 1 on, 2 auto)
   int cache_mode = 0;
   bool cache_valid = false;
   std::vector<double> cache_ls;           // lineshape parameters the cache was built at
   std::vector<double> last_ls;            // lineshape parameters of the previous call (auto mode)
+  int ls_streak = 0;                      // consecutive calls at last_ls
   int cache_ncomp = 0, cache_ncols = 0;   // complex components, derivative components
   std::vector<double> cache_I;            // ncomp x ncomp complex (re, im), sums over the set
   std::vector<double> cache_D;            // (ncols - ncomp) x ncomp complex
@@ -232,13 +235,25 @@ kpsi_status ensure_partial(kpsi_ctx* c, size_t nblocks) {
 
 // Events per thread: enough blocks to fill 256 compute units several times over while
 // keeping each thread's accumulators busy over many events.
-int pick_ept(const kpsi_ctx* c, int64_t n_total) {
+// Events per thread of the per-event kernel.  The grid is sized to one resident round: the
+// smallest ept whose data and normalisation blocks together fit in the blocks the device can
+// hold at once (compute units x resident blocks per unit for this kernel).  A grid slightly
+// larger than that would run a nearly empty second round; a much larger one pays the
+// per-thread reduction tail more often.  Capped at 64 (then the grid runs several full rounds).
+template <typename T, class Sh>
+int pick_ept(kpsi_ctx* c, int mode, int64_t nd, int64_t nm) {
   if (c->ept_override > 0) return c->ept_override;
-  const int64_t target_blocks = 2048;
-  int64_t ept = (n_total + (int64_t)BLOCK * target_blocks - 1) / ((int64_t)BLOCK * target_blocks);
+  int& bpc = c->blocks_per_cu[c->shape][mode];
+  if (bpc < 0) bpc = amp_blocks_per_cu<T, Sh>(mode);
+  const int64_t cap = (int64_t)(c->n_cu > 0 ? c->n_cu : 256) * (bpc > 0 ? bpc : 3);
+  auto blocks = [&](int64_t ept) {
+    const int64_t ch = (int64_t)BLOCK * ept;
+    return (nd + ch - 1) / ch + (nm + ch - 1) / ch;
+  };
+  int64_t ept = (nd + nm + (int64_t)BLOCK * cap - 1) / ((int64_t)BLOCK * cap);
   if (ept < 1) ept = 1;
-  if (ept > 64) ept = 64;
-  return (int)ept;
+  while (ept < 64 && blocks(ept) > cap) ++ept;
+  return (int)(ept > 64 ? 64 : ept);
 }
 
 kpsi_status derive_columns(kpsi_ctx* c, int s) {
@@ -307,7 +322,7 @@ kpsi_status validate(kpsi_ctx* c, int64_t n, const double* const* obs) {
 }
 
 // ---------------------------------------------------------------- interference-matrix cache
-void invalidate_cache(kpsi_ctx* c) { c->cache_valid = false; c->last_ls.clear(); }
+void invalidate_cache(kpsi_ctx* c) { c->cache_valid = false; c->last_ls.clear(); c->ls_streak = 0; }
 
 // Complex components in accumulator order: K* slots by spin (1 or 3 each), then Z slots (2).
 int n_components(int shape) {
@@ -510,8 +525,13 @@ kpsi_status use_cache(kpsi_ctx* c, const double* par, bool* use) {
   if (c->cache_mode == 0) return KPSI_OK;
   const std::vector<double> ls = lineshape_params(c, par);
   if (c->cache_valid && ls == c->cache_ls) { *use = true; c->cache_hits++; return KPSI_OK; }
-  const bool build = c->cache_mode == 1 || (c->cache_mode == 2 && ls == c->last_ls);
-  c->last_ls = ls;
+  if (ls == c->last_ls) {
+    ++c->ls_streak;
+  } else {
+    c->last_ls = ls;
+    c->ls_streak = 1;
+  }
+  const bool build = c->cache_mode == 1 || (c->cache_mode == 2 && c->ls_streak >= KPSI_CACHE_AUTO_STREAK);
   if (!build) return KPSI_OK;
   kpsi_status st = build_cache(c, par);
   if (st) return st;
@@ -532,7 +552,7 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   a.eps = (const T*)c->eps;
   pack<T, Sh>(c, par, a);
   int64_t nd = (which == 1) ? 0 : c->set[0].n, nm = (which == 0) ? 0 : c->set[1].n;
-  const int ept = pick_ept(c, nd + nm);
+  const int ept = pick_ept<T, Sh>(c, mode, nd, nm);
   a.chunk = BLOCK * ept;
   const int nbd = (int)((nd + a.chunk - 1) / a.chunk), nbm = (int)((nm + a.chunk - 1) / a.chunk);
   a.nb_data = nbd;
@@ -603,6 +623,7 @@ kpsi_status kpsi_create(int device, void* stream, kpsi_precision prec, kpsi_ctx*
   kpsi_ctx* c = new kpsi_ctx();
   c->device = device;
   c->prec = prec;
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) c->n_cu = 0;
   if (stream) {
     c->stream = (hipStream_t)stream;
   } else {

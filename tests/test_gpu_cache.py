@@ -81,17 +81,26 @@ def test_auto_mode_builds_on_repeated_lineshape_point():
     res, data, mc, e, _ = _setup("full", "fp64", ())
     par = W.params(res, seed=7)
     e.set_norm_cache(2)
-    e.nll(par)                       # first sight: direct evaluation
+    streak = 16                      # KPSI_CACHE_AUTO_STREAK
+    for k in range(streak - 1):      # direct evaluations while the streak is short
+        p2 = par.copy()
+        p2[4] += 0.001 * k
+        e.nll(p2)
     assert e.norm_cache_stats()[0] == 0
-    p2 = par.copy()
-    p2[4] += 0.01
-    e.nll(p2)                        # same masses and widths again: build
+    e.nll(par)                       # the streak-th call at these masses and widths: build
     assert e.norm_cache_stats()[0] == 1
     e.nll(par)                       # served from the cache
     b, h, _ = e.norm_cache_stats()
     assert b == 1 and h >= 1
+    # a lineshape change breaks the streak; coming back is served from the still-valid cache
+    p3 = par.copy()
+    p3[-1] += 0.001
+    e.nll(p3)
+    assert e.nll(par) == pytest.approx(O.nll(K, res, par, data, mc)[1], rel=1e-10)
+    assert e.norm_cache_stats()[0] == 1
     # reloading the normalisation set drops the cache
     e.load(kpsi.NORM, mc)
-    e.nll(par)
-    assert e.norm_cache_stats()[0] == 1
+    for _ in range(streak):
+        e.nll(par)
+    assert e.norm_cache_stats()[0] == 2
     assert e.nll(par) == pytest.approx(O.nll(K, res, par, data, mc)[1], rel=1e-10)
