@@ -437,6 +437,56 @@ void oracle_density(const oracle_kin* kin, const oracle_res* res, int n_res, con
   }
 }
 
+// Fit fractions (Eq. 13): FF_j = sum_e w_e S_j(x_e) / sum_e w_e S(x_e), where S_j is the
+// density with every helicity coupling outside resonance j set to zero (masses and widths as
+// given) and the sums run over phase-space events (flat measure; w = NULL means unit weights,
+// otherwise w carries integration weights).  The integral in Eq. 13 is read as the phase-space
+// integral of S.  Returns 0, or -5 when sum w S is not positive.
+int oracle_fit_fractions(const oracle_kin* kin, const oracle_res* res, int n_res, const double* par, int64_t n,
+                         const double* m, const double* cK, const double* cJ, const double* phi, const double* w,
+                         double* ff) {
+  Kin k = to_kin(kin);
+  std::vector<Res> rs = to_res(res, n_res);
+  bool hasZ = false;
+  for (auto& r : rs) hasZ |= (r.chain == 1);
+  const int np = n_full_params(rs);
+  // weighted phase-space sum of the density at parameter vector q
+  auto integral = [&](const std::vector<double>& q) {
+    int nt = omp_get_max_threads();
+    std::vector<KSum> part(nt);
+#pragma omp parallel
+    {
+      int t = omp_get_thread_num();
+#pragma omp for schedule(static)
+      for (int64_t i = 0; i < n; ++i) {
+        Event ev{m[i], cK[i], cJ[i], phi[i]};
+        ZAng za{0, 0, 0, 0, 0};
+        if (hasZ) za = z_angles(k, ev.m, ev.cK, ev.cJ, ev.phi);
+        const double s = density<double>(k, rs, q.data(), ev, za);
+        part[t].add(w ? w[i] * s : s);
+      }
+    }
+    KSum tot;
+    for (int t = 0; t < nt; ++t) { tot.add(part[t].s); tot.add(part[t].c); }
+    return tot.get();
+  };
+  std::vector<double> full(par, par + np);
+  const double den = integral(full);
+  if (!(den > 0.0)) return -5;
+  for (int j = 0; j < n_res; ++j) {
+    std::vector<double> q(full);
+    int o2 = 0;
+    for (int i = 0; i < n_res; ++i) {
+      const int nl = res_ncoup(rs[i]);
+      if (i != j)
+        for (int l = 0; l < nl; ++l) q[o2 + 2 * l] = 0.0;   // magnitude of coupling l of resonance i
+      o2 += 2 * nl;
+    }
+    ff[j] = integral(q) / den;
+  }
+  return 0;
+}
+
 // -2 ln L of the signal PDF eps*S normalised by the phase-space MC sum (Eq. 14 with
 // purity 1):  NLL = -2 sum_i ln S(x_i) + 2 N_d ln( (1/N_MC) sum_j eps_j S(y_j) ).
 // Parameter-independent terms (ln eps(x_i), phase-space factor, volume) are dropped.

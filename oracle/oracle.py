@@ -262,3 +262,20 @@ def bf16(x: float) -> float:
     f.argtypes = [C.c_double]
     f.restype = C.c_double
     return f(x)
+
+
+def fit_fractions(kind: dict, res, par, ev, w=None):
+    """Eq. 13 over the given phase-space events (optional integration weights w):
+    returns (status, FF array of length len(res))."""
+    ev = _f64(ev)
+    par = _f64(par)
+    n = ev.shape[1]
+    ff = np.zeros(len(res))
+    cols = [_f64(ev[i]) for i in range(4)]
+    ww = _f64(w) if w is not None else None
+    k = kin(kind)
+    f = lib().oracle_fit_fractions
+    f.restype = C.c_int
+    st = f(C.byref(k), res_array(res), len(res), _dp(par), n, *(_dp(c) for c in cols),
+           _dp(ww) if ww is not None else None, _dp(ff))
+    return st, ff

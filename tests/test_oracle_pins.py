@@ -580,3 +580,59 @@ def test_bf16_rounding_is_round_to_nearest_even():
     assert O.bf16(1.0 + 2 ** -8 + 2 ** -12) == 1.0 + 2 ** -7
     assert O.bf16(-2.5) == -2.5
     assert O.bf16(3.0e38) == pytest.approx(3.0e38, rel=2 ** -8)
+
+
+# ---------------------------------------------------------------- fit fractions, Eq. (13)
+def test_fit_fractions_on_exact_quadrature_grid_match_spin_orthogonal_form():
+    # Over phase space, int S dcosK dcosJ dphi = (8 pi/3) sum_lambda sum_J 2/(2J+1) |T_{J lambda}(m)|^2, and
+    # the numerator of Eq. 13 keeps only resonance j: (8 pi/3) sum_lambda 2/(2J_j+1) |H_{j lambda} A_j(m)|^2.
+    # On a product grid (Gauss-Legendre in m with weight p_B q, and angular rules exact for these
+    # polynomial/trigonometric integrands) the oracle's fractions must equal the closed form.
+    res = W.model("kstar10")
+    par = W.params(res, seed=23)
+    nc = sum(2 * r.n_coup for r in res)
+    xm, wm = np.polynomial.legendre.leggauss(48)
+    ms = 0.5 * (W.M_HI - W.M_LO) * xm + 0.5 * (W.M_HI + W.M_LO)
+    wms = 0.5 * (W.M_HI - W.M_LO) * wm * np.array([_psw(m) for m in ms])
+    xa, wa = np.polynomial.legendre.leggauss(6)
+    nphi = 6
+    phis = -math.pi + 2 * math.pi * (np.arange(nphi) + 0.5) / nphi
+    M, CK, CJ, PH = np.meshgrid(ms, xa, xa, phis, indexing="ij")
+    WW = (wms[:, None, None, None] * wa[None, :, None, None] * wa[None, None, :, None]
+          * np.full(nphi, 2 * math.pi / nphi)[None, None, None, :])
+    ev = np.stack([M.ravel(), CK.ravel(), CJ.ravel(), PH.ravel()])
+    st, ff = O.fit_fractions(K, res, par, ev, WW.ravel())
+    assert st == 0
+    num = np.zeros(len(res))
+    den = 0.0
+    for m, w in zip(ms, wms):
+        T = {}
+        ip = 0
+        for i, r in enumerate(res):
+            A = O.lineshape(K, r, par[nc + 2 * i], par[nc + 2 * i + 1], m)
+            lams = [0] if r.spin == 0 else [-1, 0, 1]
+            for j, lam in enumerate(lams):
+                hA = par[ip + 2 * j] * np.exp(1j * par[ip + 2 * j + 1]) * A
+                T[(r.spin, lam)] = T.get((r.spin, lam), 0) + hA
+                num[i] += w * 2 / (2 * r.spin + 1) * abs(hA) ** 2
+            ip += 2 * len(lams)
+        den += w * sum(2 / (2 * J + 1) * abs(t) ** 2 for (J, lam), t in T.items())
+    np.testing.assert_allclose(ff, num / den, rtol=1e-11)
+    # same-spin interference makes the sum differ from 1
+    assert abs(ff.sum() - 1) > 1e-3
+
+
+def test_fit_fraction_of_a_lone_resonance_is_one_and_phase_invariant():
+    ev = O.gen_phsp(K, 71, 3000, W.PHSP_WMAX)
+    for res in ([W.KSTAR892], [W.Z4430]):
+        par = W.params(res, seed=3)
+        st, ff = O.fit_fractions(K, res, par, ev)
+        assert st == 0 and ff[0] == pytest.approx(1.0, rel=1e-14)
+    res = W.model("full")
+    par = W.params(res, seed=4)
+    _, ff = O.fit_fractions(K, res, par, ev)
+    rot = par.copy()
+    nc = sum(2 * r.n_coup for r in res)
+    rot[1:nc:2] += 0.7          # a common phase on every coupling leaves every fraction unchanged
+    _, ff2 = O.fit_fractions(K, res, rot, ev)
+    np.testing.assert_allclose(ff2, ff, rtol=1e-11)
