@@ -215,6 +215,35 @@ kpsi_status kpsi_set_norm_cache(kpsi_ctx* ctx, int mode);
 /* Cache builds, calls served from the cache, and the device milliseconds of the last build. */
 kpsi_status kpsi_norm_cache_stats(const kpsi_ctx* ctx, int64_t* builds, int64_t* hits, double* last_build_ms);
 
+/* Fit fractions (Eq. 13): ff[j] = int S_j dPhi / int S dPhi for every resonance j of the
+ * model, where S_j is the density with all helicity couplings outside resonance j set to zero
+ * and the integrals run over phase space without efficiency.  They are estimated on the loaded
+ * normalisation events (flat phase space) through one interference-matrix build at the
+ * masses and widths of params (FP64 matrix-core Gram product, efficiency column not applied;
+ * the normalisation cache is left untouched): ff[j] = c_j^H I_jj c_j / c^H I c.
+ *   params: full parameter vector (kpsi_n_params doubles, host).
+ *   ff:     n_res doubles (host, caller-owned), table order.
+ *   ff_sum: optional (may be NULL), the sum of the fractions (not 1 when resonances interfere).
+ * Errors: KPSI_E_STATE without a model or normalisation set; KPSI_E_ARG for NULL or non-finite
+ * parameters; KPSI_E_NONFINITE when the integral of the density is not positive. */
+kpsi_status kpsi_fit_fractions(kpsi_ctx* ctx, const double* params, double* ff, double* ff_sum);
+
+/* ---------------------------------------------------------------- attainable peaks
+ * Microbenchmarks of the device (no context needed), the ceilings against which the kernels'
+ * rates are read: FP32 and FP64 fused multiply-add issue (one operation per lane per
+ * instruction; packed FP32 instructions are not used by this library), the FP32 reciprocal
+ * unit, and a device-to-device copy of 1 GiB (read + write bytes).  Takes well under a second;
+ * allocates 2 GiB of device memory for the copy and frees it.  Runs on its own stream.
+ * Errors: KPSI_E_ARG for a NULL out; KPSI_E_HIP for a bad device or a failed launch;
+ * KPSI_E_OOM if the buffers cannot be allocated. */
+typedef struct {
+  double fp32_fma_tflops;   /* 2 flop per FMA */
+  double fp64_fma_tflops;
+  double fp32_rcp_tops;     /* reciprocals per second, 1e12 */
+  double copy_gbs;          /* bytes read + written per second, 1e9 */
+} kpsi_peaks;
+kpsi_status kpsi_measure_peaks(int device, kpsi_peaks* out);
+
 /* ---------------------------------------------------------------- learned efficiency
  * The relative efficiency eps(Phi) of Eq. 14 learned by a 4 -> 64 -> 64 -> 1 network
  * (SiLU, SiLU, sigmoid) from accepted / generated phase-space events: the sigmoid output is

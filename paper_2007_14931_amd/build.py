@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkpsi.so")
-SOURCES = ["kpsi_device.hip", "kpsi_imatrix.hip", "kpsi_mlp.hip", "kpsi_runtime.hip", "kpsi_fit.hip"]
+SOURCES = ["kpsi_device.hip", "kpsi_imatrix.hip", "kpsi_mlp.hip", "kpsi_runtime.hip", "kpsi_fit.hip", "kpsi_peaks.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

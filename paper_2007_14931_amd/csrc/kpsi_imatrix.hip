@@ -87,7 +87,9 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
   constexpr int NTILE = NT * (NT + 1) / 2;
   constexpr int LDX = C + 2;
   constexpr int NZ = Sh::NZ;
-  __shared__ double X[64 * LDX];
+  // rows are staged at the context precision: FP32 values take half the LDS, so more blocks
+  // (one wavefront each) fit per compute unit and row building overlaps other waves' MFMA
+  __shared__ T X[64 * LDX];
   __shared__ double Wr[64];
   const int lane = threadIdx.x;
   d4_t acc[NTILE];
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
   const int64_t ntiles = (a.n + 31) / 32;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     // ---- rows of this tile: lane l < 32 fills rows 2l (xi = +1) and 2l + 1 (xi = -1)
-    for (int i = lane; i < 64 * LDX; i += 64) X[i] = 0.0;
+    for (int i = lane; i < 64 * LDX; i += 64) X[i] = T(0);
     __syncthreads();
     const int64_t e = tile * 32 + (lane & 31);
     if (lane < 32 && e < a.n) {
@@ -111,16 +113,16 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
       const T zR = (a.rR * q) * (a.rR * q), zB = (a.rB * pB) * (a.rB * pB);
       const T qm = q * im_, pbm = pB * a.invMB, qq = q * q;
       const T hp = T(0.5) * (T(1) + cJ), hm = T(0.5) * (T(1) - cJ), s0 = sJ * T(0.70710678118654752440);
-      double* rp = X + (2 * lane) * LDX;
-      double* rm = X + (2 * lane + 1) * LDX;
+      T* rp = X + (2 * lane) * LDX;
+      T* rm = X + (2 * lane + 1) * LDX;
       Wr[2 * lane] = a.eps ? (double)a.eps[e] : 1.0;
       Wr[2 * lane + 1] = Wr[2 * lane];
       // write a component (or derivative) column: value A times angular pair (gp, gm)
       auto put = [&](int c, T Ar, T Ai, T gpr, T gpi, T gmr, T gmi) {
-        rp[2 * c] = (double)(Ar * gpr - Ai * gpi);
-        rp[2 * c + 1] = (double)(Ar * gpi + Ai * gpr);
-        rm[2 * c] = (double)(Ar * gmr - Ai * gmi);
-        rm[2 * c + 1] = (double)(Ar * gmi + Ai * gmr);
+        rp[2 * c] = Ar * gpr - Ai * gpi;
+        rp[2 * c + 1] = Ar * gpi + Ai * gpr;
+        rm[2 * c] = Ar * gmr - Ai * gmi;
+        rm[2 * c + 1] = Ar * gmi + Ai * gmr;
       };
       // angular pairs of lambda = +1, 0, -1 for d^J_{lambda 0} = 1
       const T ep_r = cph * hp, ep_i = sph * hp, em_r = cph * hm, em_i = sph * hm;     // e^{+i phi} (hp, hm)
@@ -228,21 +230,26 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
     }
     __syncthreads();
     // ---- Gram tiles: A[i][k] = w_row X[row][16 ti + i], B[k][j] = X[row][16 tj + j],
-    //      row = 4 s + k; lane = i + 16 k provides A[i][k] and B[k][j = i].
+    //      row = 4 s + k; lane = i + 16 k provides A[i][k] and B[k][j = i].  The A and B
+    //      operands of a row group are the same LDS elements (A scaled by the event weight),
+    //      so each group loads NT values per lane and feeds all NT(NT+1)/2 tiles; consecutive
+    //      MFMAs accumulate into different tiles.
     const int r16 = lane & 15, k4 = lane >> 4;
-    int t = 0;
+#pragma unroll 2
+    for (int s = 0; s < 16; ++s) {
+      const int row = 4 * s + k4;
+      const double w = Wr[row];
+      double av[NT], bv[NT];
 #pragma unroll
-    for (int ti = 0; ti < NT; ++ti) {
+      for (int t = 0; t < NT; ++t) {
+        bv[t] = (double)X[row * LDX + 16 * t + r16];
+        av[t] = w * bv[t];
+      }
+      int t = 0;
 #pragma unroll
-      for (int tj = ti; tj < NT; ++tj) {
-#pragma unroll 4
-        for (int s = 0; s < 16; ++s) {
-          const int row = 4 * s + k4;
-          const double av = Wr[row] * X[row * LDX + 16 * ti + r16];
-          const double bv = X[row * LDX + 16 * tj + r16];
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
-        }
-        ++t;
+      for (int ti = 0; ti < NT; ++ti) {
+#pragma unroll
+        for (int tj = ti; tj < NT; ++tj, ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[t], 0, 0, 0);
       }
     }
     __syncthreads();

@@ -293,13 +293,19 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(MlpArgs a) {
 }
 
 // Sum of value-major block partials in FP64, fixed order; out[v] = scale * sum_b p[v][b].
+// out[v] = scale * sum_b partial[v * nb + b]: one wavefront per value (coalesced reads of the
+// value's nb block partials), lane sums in a fixed order, then a fixed butterfly.
 __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ partial, int nb, int nv,
                                                          double scale, double* __restrict__ out) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nv) return;
+  const int lane = threadIdx.x & 63;
+  const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= nv) return;   // whole wavefronts exit together
+  const float* __restrict__ p = partial + (int64_t)v * nb;
   double x = 0.0;
-  for (int b = 0; b < nb; ++b) x += (double)partial[(int64_t)v * nb + b];
-  out[v] = scale * x;
+  for (int b = lane; b < nb; b += 64) x += (double)p[b];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+  if (lane == 0) out[v] = scale * x;
 }
 
 // Adam step on the FP32 master parameters.
@@ -411,7 +417,7 @@ hipError_t launch_mlp_grad(const MlpArgs& a, int nb, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_mlp_reduce(const float* partial, int nb, int nv, double scale, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((nv + 255) / 256), dim3(256), 0, st, partial, nb, nv, scale, out);
+  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((nv + 3) / 4), dim3(256), 0, st, partial, nb, nv, scale, out);
   return hipGetLastError();
 }
 hipError_t launch_adam(float* p, float* m, float* v, const double* g, int n, float lr, float b1, float b2, float eps,

@@ -233,8 +233,6 @@ kpsi_status ensure_partial(kpsi_ctx* c, size_t nblocks) {
   return KPSI_OK;
 }
 
-// Events per thread: enough blocks to fill 256 compute units several times over while
-// keeping each thread's accumulators busy over many events.
 // Events per thread of the per-event kernel.  The grid is sized to one resident round: the
 // smallest ept whose data and normalisation blocks together fit in the blocks the device can
 // hold at once (compute units x resident blocks per unit for this kernel).  A grid slightly
@@ -368,17 +366,30 @@ std::vector<double> lineshape_params(const kpsi_ctx* c, const double* par) {
   return std::vector<double>(par + ncr, par + c->nparams);
 }
 
-template <typename T, class Sh> kpsi_status build_cache_t(kpsi_ctx* c, const double* par) {
+// Gram build over the normalisation set at the lineshape point of par: the complex
+// component matrix I (ncomp x ncomp) and, when with_deriv, the lineshape-derivative rows D
+// (nderiv x ncomp) with dcol[] the first derivative component of each floating slot.
+// with_eps weights each event by the context's efficiency column.
+struct Gram {
+  int ncomp = 0, nderiv = 0;
+  int dcol[NFL] = {0, 0};
+  std::vector<double> I, D;
+  float ms = 0.f;
+};
+template <typename T, class Sh>
+kpsi_status gram_build_t(kpsi_ctx* c, const double* par, bool with_eps, bool with_deriv, Gram& g) {
   const DevSet& d = c->set[1];
   const int ncomp = n_components(c->shape);
   int nderiv = 0;
   int dcol[NFL] = {0, 0};
-  for (size_t i = 0; i < c->res.size(); ++i) {
-    if (c->fslot[i] < 0) continue;
-    int k0, nk;
-    components_of(c, i, &k0, &nk);
-    dcol[c->fslot[i]] = ncomp + nderiv;
-    nderiv += 2 * nk;
+  if (with_deriv) {
+    for (size_t i = 0; i < c->res.size(); ++i) {
+      if (c->fslot[i] < 0) continue;
+      int k0, nk;
+      components_of(c, i, &k0, &nk);
+      dcol[c->fslot[i]] = ncomp + nderiv;
+      nderiv += 2 * nk;
+    }
   }
   const int ncx = ncomp + nderiv;
   const int ncols = 2 * ncx;
@@ -408,13 +419,19 @@ template <typename T, class Sh> kpsi_status build_cache_t(kpsi_ctx* c, const dou
   a.cols = (const T*)d.cols;
   a.ld = d.ld;
   a.n = d.n;
-  a.eps = (const T*)c->eps;
+  a.eps = with_eps ? (const T*)c->eps : nullptr;
   a.partial = c->cache_partial;
   for (int j = 0; j < 6; ++j) a.cnt[j] = pa.cnt[j];
   for (int f = 0; f < NFL; ++f) a.dcol[f] = dcol[f];
   a.rR = pa.rR; a.rB = pa.rB; a.invMB = pa.invMB;
   for (int k = 0; k < (Sh::NK > 0 ? Sh::NK : 1); ++k) a.ks[k] = pa.ks[k];
-  for (int k = 0; k < (Sh::NZ > 0 ? Sh::NZ : 1); ++k) a.zs[k] = pa.zs[k];
+  for (int k = 0; k < (Sh::NZ > 0 ? Sh::NZ : 1); ++k) {
+    a.zs[k] = pa.zs[k];
+  }
+  if (!with_deriv) {   // no derivative columns: mark every lineshape as fixed for this build
+    for (int k = 0; k < (Sh::NK > 0 ? Sh::NK : 1); ++k) a.ks[k].flt = -1;
+    for (int k = 0; k < (Sh::NZ > 0 ? Sh::NZ : 1); ++k) a.zs[k].flt = -1;
+  }
   hipEvent_t e0 = c->ev0, e1 = c->ev1;
   hipEventRecord(e0, c->stream);
   hipError_t e = launch_imatrix<T, Sh>(a, ncols, nb, c->cache_out, c->stream);
@@ -423,8 +440,8 @@ template <typename T, class Sh> kpsi_status build_cache_t(kpsi_ctx* c, const dou
   std::vector<double> out(nv);
   HIPCHECK(c, hipMemcpyAsync(out.data(), c->cache_out, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHECK(c, hipStreamSynchronize(c->stream));
-  float ms = 0.f;
-  if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) c->cache_build_ms = ms;
+  g.ms = 0.f;
+  hipEventElapsedTime(&g.ms, e0, e1);
   // real Gram matrix G from its upper 16x16 tiles.  The FP64 16x16x4 MFMA accumulator holds, in
   // lane l and register r, row l/16 + 4 r and column l % 16 of the tile (rows interleaved across
   // the four registers, unlike the 32-bit-accumulator forms): tile t, lane, reg ->
@@ -443,32 +460,48 @@ template <typename T, class Sh> kpsi_status build_cache_t(kpsi_ctx* c, const dou
   // complex blocks: sum B_k conj(B_l) = (G[2k][2l] + G[2k+1][2l+1]) + i (G[2k+1][2l] - G[2k][2l+1])
   auto cre = [&](int k, int l) { return G[(size_t)(2 * k) * C + 2 * l] + G[(size_t)(2 * k + 1) * C + 2 * l + 1]; };
   auto cim = [&](int k, int l) { return G[(size_t)(2 * k + 1) * C + 2 * l] - G[(size_t)(2 * k) * C + 2 * l + 1]; };
-  c->cache_I.assign(2 * (size_t)ncomp * ncomp, 0.0);
+  g.I.assign(2 * (size_t)ncomp * ncomp, 0.0);
   for (int k = 0; k < ncomp; ++k)
     for (int l = 0; l < ncomp; ++l) {
-      c->cache_I[2 * ((size_t)k * ncomp + l)] = cre(k, l);
-      c->cache_I[2 * ((size_t)k * ncomp + l) + 1] = cim(k, l);
+      g.I[2 * ((size_t)k * ncomp + l)] = cre(k, l);
+      g.I[2 * ((size_t)k * ncomp + l) + 1] = cim(k, l);
     }
-  c->cache_D.assign(2 * (size_t)nderiv * ncomp, 0.0);
+  g.D.assign(2 * (size_t)nderiv * ncomp, 0.0);
   for (int dd = 0; dd < nderiv; ++dd)
     for (int l = 0; l < ncomp; ++l) {
-      c->cache_D[2 * ((size_t)dd * ncomp + l)] = cre(ncomp + dd, l);
-      c->cache_D[2 * ((size_t)dd * ncomp + l) + 1] = cim(ncomp + dd, l);
+      g.D[2 * ((size_t)dd * ncomp + l)] = cre(ncomp + dd, l);
+      g.D[2 * ((size_t)dd * ncomp + l) + 1] = cim(ncomp + dd, l);
     }
-  c->cache_ncomp = ncomp;
-  c->cache_ncols = ncx;
-  for (int f = 0; f < NFL; ++f) c->cache_dcol[f] = dcol[f];
+  g.ncomp = ncomp;
+  g.nderiv = nderiv;
+  for (int f = 0; f < NFL; ++f) g.dcol[f] = dcol[f];
+  return KPSI_OK;
+}
+
+kpsi_status gram_build(kpsi_ctx* c, const double* par, bool with_eps, bool with_deriv, Gram& g) {
+  if (c->prec == KPSI_FP32)
+    return c->shape == 0 ? gram_build_t<float, ShapeSmall>(c, par, with_eps, with_deriv, g)
+                         : gram_build_t<float, ShapeFull>(c, par, with_eps, with_deriv, g);
+  return c->shape == 0 ? gram_build_t<double, ShapeSmall>(c, par, with_eps, with_deriv, g)
+                       : gram_build_t<double, ShapeFull>(c, par, with_eps, with_deriv, g);
+}
+
+kpsi_status build_cache(kpsi_ctx* c, const double* par) {
+  Gram g;
+  kpsi_status st = gram_build(c, par, true, true, g);
+  if (st) return st;
+  c->cache_build_ms = g.ms;
+  c->cache_I = std::move(g.I);
+  c->cache_D = std::move(g.D);
+  c->cache_ncomp = g.ncomp;
+  c->cache_ncols = g.ncomp + g.nderiv;
+  for (int f = 0; f < NFL; ++f) c->cache_dcol[f] = g.dcol[f];
   c->cache_ls = lineshape_params(c, par);
   c->cache_valid = true;
   c->cache_builds++;
   return KPSI_OK;
 }
 
-kpsi_status build_cache(kpsi_ctx* c, const double* par) {
-  if (c->prec == KPSI_FP32)
-    return c->shape == 0 ? build_cache_t<float, ShapeSmall>(c, par) : build_cache_t<float, ShapeFull>(c, par);
-  return c->shape == 0 ? build_cache_t<double, ShapeSmall>(c, par) : build_cache_t<double, ShapeFull>(c, par);
-}
 
 // Normalisation record (what the per-event kernel accumulates over the normalisation set)
 // from the cached matrices: sum eps S = c^T I conj(c), coupling sensitivities (I conj(c))_k,
@@ -1420,6 +1453,44 @@ kpsi_status kpsi_norm_cache_stats(const kpsi_ctx* c, int64_t* builds, int64_t* h
   if (builds) *builds = c->cache_builds;
   if (hits) *hits = c->cache_hits;
   if (last_build_ms) *last_build_ms = c->cache_build_ms;
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_fit_fractions(kpsi_ctx* c, const double* params, double* ff, double* ff_sum) {
+  if (!c) return KPSI_E_ARG;
+  if (!params || !ff) return fail(c, KPSI_E_ARG, "NULL argument");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set");
+  if (c->set[1].n <= 0) return fail(c, KPSI_E_STATE, "no normalisation events loaded");
+  for (int i = 0; i < c->nparams; ++i)
+    if (!std::isfinite(params[i])) return fail(c, KPSI_E_ARG, "parameter %d is not finite", i);
+  hipSetDevice(c->device);
+  Gram g;
+  kpsi_status st = gram_build(c, params, false, false, g);
+  if (st) return st;
+  const std::vector<double> cv = component_couplings(c, params);
+  const int n = g.ncomp;
+  // Re sum_{k,l in K} c_k conj(c_l) I_kl over a component set K
+  auto quad = [&](int k0, int k1) {
+    double v = 0.0;
+    for (int k = k0; k < k1; ++k)
+      for (int l = k0; l < k1; ++l) {
+        const double ir = g.I[2 * ((size_t)k * n + l)], ii = g.I[2 * ((size_t)k * n + l) + 1];
+        const double pr = cv[2 * k] * cv[2 * l] + cv[2 * k + 1] * cv[2 * l + 1];   // c_k conj(c_l)
+        const double pi = cv[2 * k + 1] * cv[2 * l] - cv[2 * k] * cv[2 * l + 1];
+        v += pr * ir - pi * ii;
+      }
+    return v;
+  };
+  const double den = quad(0, n);
+  if (!(den > 0.0)) return fail(c, KPSI_E_NONFINITE, "phase-space integral of the density is %g", den);
+  double tot = 0.0;
+  for (size_t i = 0; i < c->res.size(); ++i) {
+    int k0, nk;
+    components_of(c, i, &k0, &nk);
+    ff[i] = quad(k0, k0 + nk) / den;
+    tot += ff[i];
+  }
+  if (ff_sum) *ff_sum = tot;
   return KPSI_OK;
 }
 

@@ -28,7 +28,7 @@ EXPORTS = [
     "kpsi_set_timing", "kpsi_timing", "kpsi_set_events_per_thread", "kpsi_last_error",
     "kpsi_fit_default_options", "kpsi_migrad", "kpsi_hesse", "kpsi_set_norm_cache", "kpsi_norm_cache_stats",
     "kpsi_mlp_default_options", "kpsi_accept_labels", "kpsi_hist_efficiency", "kpsi_mlp_grad", "kpsi_mlp_train",
-    "kpsi_mlp_eval", "kpsi_set_efficiency_mlp",
+    "kpsi_mlp_eval", "kpsi_set_efficiency_mlp", "kpsi_fit_fractions", "kpsi_measure_peaks",
 ]
 MLP_NP = 4545
 
@@ -59,6 +59,20 @@ class FitResult(C.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Peaks(C.Structure):
+    _fields_ = [("fp32_fma_tflops", C.c_double), ("fp64_fma_tflops", C.c_double), ("fp32_rcp_tops", C.c_double),
+                ("copy_gbs", C.c_double)]
+
+
+def measure_peaks(device: int = 0) -> dict:
+    """Attainable device rates from kpsi_measure_peaks."""
+    p = Peaks()
+    st = lib().kpsi_measure_peaks(device, C.byref(p))
+    if st != KPSI_OK:
+        raise KpsiError(st, "kpsi_measure_peaks failed")
+    return {k: getattr(p, k) for k, _ in Peaks._fields_}
 
 
 class MlpOptions(C.Structure):
@@ -102,6 +116,8 @@ def lib() -> C.CDLL:
         L.kpsi_hesse.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(FitOptions), dp, C.POINTER(FitResult)]
         L.kpsi_set_norm_cache.argtypes = [vp, C.c_int]
         L.kpsi_norm_cache_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), dp]
+        L.kpsi_fit_fractions.argtypes = [vp, dp, dp, dp]
+        L.kpsi_measure_peaks.argtypes = [C.c_int, C.POINTER(Peaks)]
         fp = C.POINTER(C.c_float)
         L.kpsi_mlp_default_options.argtypes = [C.POINTER(MlpOptions)]
         L.kpsi_accept_labels.argtypes = [vp, C.c_uint64, i64, i64, vp, vp, vp, vp, dp, vp, vp]
@@ -392,6 +408,14 @@ class Engine:
         b, h, ms = C.c_int64(), C.c_int64(), C.c_double()
         self._chk(self.L.kpsi_norm_cache_stats(self.h, C.byref(b), C.byref(h), C.byref(ms)))
         return b.value, h.value, ms.value
+
+    def fit_fractions(self, params) -> tuple[np.ndarray, float]:
+        """Eq. 13 on the normalisation events: (fractions in table order, their sum)."""
+        p = _f64(params)
+        ff = np.empty(self.n_res)
+        tot = C.c_double()
+        self._chk(self.L.kpsi_fit_fractions(self.h, _dp(p), _dp(ff), C.byref(tot)))
+        return ff, tot.value
 
     def set_events_per_thread(self, ept: int) -> None:
         self._chk(self.L.kpsi_set_events_per_thread(self.h, ept))
