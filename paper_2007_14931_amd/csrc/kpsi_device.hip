@@ -54,6 +54,7 @@ template <typename T> __device__ __forceinline__ T ldoff(const T* base, uint32_t
 // event loop keeps the compiler from hoisting every per-resonance constant out of the
 // loop into vector registers: the constants are re-read with scalar loads instead.
 template <typename P> using kconst_ptr = __attribute__((address_space(4))) const P*;
+template <typename P> using lds_ptr = __attribute__((address_space(3))) P*;   // LDS (32-bit address)
 template <typename P> __device__ __forceinline__ kconst_ptr<P> kernarg_laundered() {
   kconst_ptr<P> p = (kconst_ptr<P>)__builtin_amdgcn_kernarg_segment_ptr();
   asm volatile("" : "+s"(p));
@@ -248,8 +249,13 @@ template <class Sh> __host__ __device__ constexpr int acc_base(int J) {   // acc
 //   sum w * dS/dH (before the factor 2), then per Z slot 4 values (lambda' = 0, +-1),
 //   then 2 per floating slot (d/dM, d/dGamma0).
 
+// The FP32 gradient kernel of the large shape asks for 4 wavefronts per SIMD (at most 128
+// registers); its spin-1..3 accumulators live in LDS to make room.
+template <typename T, class Sh, int MODE> struct AmpWaves {
+  static constexpr int v = (MODE == MODE_GRAD && std::is_same<T, float>::value && Sh::LDS_HI > Sh::LDS_LO) ? 4 : 1;
+};
 template <typename T, class Sh, int MODE>
-__global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
+__global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(const AmpArgs<T, Sh> a) {
   constexpr int NK = Sh::NK;
   constexpr int NZ = Sh::NZ;
   constexpr bool GRAD = (MODE == MODE_GRAD);
@@ -265,6 +271,14 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
 
   double ms = 0.0, mc = 0.0;   // Kahan pair
   double nbad = 0.0;
+  // accumulators gk[LO, HI) live in this thread's LDS column accl[.][tid] (FP32 gradient only)
+  constexpr bool LDSACC = GRAD && std::is_same<T, float>::value && (Sh::LDS_HI > Sh::LDS_LO);
+  constexpr int LO = LDSACC ? Sh::LDS_LO : 0, HI = LDSACC ? Sh::LDS_HI : 0;
+  __shared__ float accl[HI > LO ? HI - LO : 1][256];
+  if constexpr (LDSACC) {
+#pragma unroll
+    for (int i = 0; i < HI - LO; ++i) accl[i][threadIdx.x] = 0.f;
+  }
   A_t gk[Sh::NKACC > 0 ? Sh::NKACC : 1];
   A_t gz[NZ > 0 ? 4 * NZ : 1];
   static_assert(NFL == 2, "floating accumulators are named registers for two slots");
@@ -282,6 +296,10 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
     const int64_t e = e0 + i;
     const uint32_t ob = i * (uint32_t)sizeof(T);
     const auto& ka = *kernarg_laundered<AmpArgs<T, Sh>>();
+    // this thread's LDS accumulator column, re-derived opaquely each event so the compiler keeps
+    // the accumulators in LDS instead of promoting them back into registers across the loop
+    lds_ptr<float> accb = (lds_ptr<float>)&accl[0][threadIdx.x];
+    if constexpr (LDSACC) asm volatile("" : "+v"(accb));
     const T m = ldoff(cb, ob), q = ldoff(cb + ld, ob), pB = ldoff(cb + 2 * ld, ob);
     const T cK = ldoff(cb + 3 * ld, ob), sK = ldoff(cb + 4 * ld, ob);
     const T cJ = ldoff(cb + 5 * ld, ob), sJ = ldoff(cb + 6 * ld, ob);
@@ -459,6 +477,20 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
                   g[0] += (A_t)(A.re * V0.re - A.im * V0.im);
                   g[1] += (A_t)(A.re * V0.im + A.im * V0.re);
                   if (rc.flt >= 0) cmac(Q, rc.hr[1], rc.hi[1], V0.re, V0.im);
+                } else if constexpr (LDSACC && J >= 1 && J <= 3) {
+                  // ab + 6 j lies in [LO, HI): read-add-write this thread's own LDS slots (no other
+                  // lane touches them, so no atomics)
+                  lds_ptr<float> g = accb + 256 * (ab + 6 * j - LO);
+                  const float v[6] = {(float)(A.re * Vm.re - A.im * Vm.im), (float)(A.re * Vm.im + A.im * Vm.re),
+                                      (float)(A.re * V0.re - A.im * V0.im), (float)(A.re * V0.im + A.im * V0.re),
+                                      (float)(A.re * Vp.re - A.im * Vp.im), (float)(A.re * Vp.im + A.im * Vp.re)};
+#pragma unroll
+                  for (int q = 0; q < 6; ++q) g[256 * q] += v[q];
+                  if (rc.flt >= 0) {
+                    cmac(Q, rc.hr[0], rc.hi[0], Vm.re, Vm.im);
+                    cmac(Q, rc.hr[1], rc.hi[1], V0.re, V0.im);
+                    cmac(Q, rc.hr[2], rc.hi[2], Vp.re, Vp.im);
+                  }
                 } else {
                   A_t* g = gk + ab + 6 * j;
                   g[0] += (A_t)(A.re * Vm.re - A.im * Vm.im);
@@ -558,6 +590,7 @@ __global__ __launch_bounds__(256) void amp_kernel(const AmpArgs<T, Sh> a) {
       if (i == 0) return ms;
       if (i == 1) return -mc;   // Kahan: the running sum exceeds the exact one by mc
       if (i == 2) return nbad;
+      if (LDSACC && i >= 3 + LO && i < 3 + HI) return (double)accl[i - 3 - LO][threadIdx.x];
       if (i < 3 + Sh::NKACC) return (double)gk[i - 3];
       if (i < 3 + Sh::NKACC + 4 * NZ) return (double)gz[i - 3 - Sh::NKACC];
       const int f = i - 3 - Sh::NKACC - 4 * NZ;
