@@ -249,10 +249,11 @@ template <class Sh> __host__ __device__ constexpr int acc_base(int J) {   // acc
 //   sum w * dS/dH (before the factor 2), then per Z slot 4 values (lambda' = 0, +-1),
 //   then 2 per floating slot (d/dM, d/dGamma0).
 
-// The FP32 gradient kernel of the large shape asks for 4 wavefronts per SIMD (at most 128
-// registers); its spin-1..3 accumulators live in LDS to make room.
+// The gradient kernel of the large shape asks for 4 (FP32) or 2 (FP64) wavefronts per SIMD, at
+// most 128 or 256 registers; its spin-1..3 accumulators live in LDS to make room (36 values x
+// 256 threads: 36 KB per block in FP32, 4 blocks per compute unit; 72 KB in FP64, 2 blocks).
 template <typename T, class Sh, int MODE> struct AmpWaves {
-  static constexpr int v = (MODE == MODE_GRAD && std::is_same<T, float>::value && Sh::LDS_HI > Sh::LDS_LO) ? 4 : 1;
+  static constexpr int v = (MODE == MODE_GRAD && Sh::LDS_HI > Sh::LDS_LO) ? (std::is_same<T, float>::value ? 4 : 2) : 1;
 };
 template <typename T, class Sh, int MODE>
 __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(const AmpArgs<T, Sh> a) {
@@ -271,13 +272,13 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
 
   double ms = 0.0, mc = 0.0;   // Kahan pair
   double nbad = 0.0;
-  // accumulators gk[LO, HI) live in this thread's LDS column accl[.][tid] (FP32 gradient only)
-  constexpr bool LDSACC = GRAD && std::is_same<T, float>::value && (Sh::LDS_HI > Sh::LDS_LO);
+  // accumulators gk[LO, HI) live in this thread's LDS column accl[.][tid] (gradient kernel)
+  constexpr bool LDSACC = GRAD && (Sh::LDS_HI > Sh::LDS_LO);
   constexpr int LO = LDSACC ? Sh::LDS_LO : 0, HI = LDSACC ? Sh::LDS_HI : 0;
-  __shared__ float accl[HI > LO ? HI - LO : 1][256];
+  __shared__ A_t accl[HI > LO ? HI - LO : 1][256];
   if constexpr (LDSACC) {
 #pragma unroll
-    for (int i = 0; i < HI - LO; ++i) accl[i][threadIdx.x] = 0.f;
+    for (int i = 0; i < HI - LO; ++i) accl[i][threadIdx.x] = A_t(0);
   }
   A_t gk[Sh::NKACC > 0 ? Sh::NKACC : 1];
   A_t gz[NZ > 0 ? 4 * NZ : 1];
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     const auto& ka = *kernarg_laundered<AmpArgs<T, Sh>>();
     // this thread's LDS accumulator column, re-derived opaquely each event so the compiler keeps
     // the accumulators in LDS instead of promoting them back into registers across the loop
-    lds_ptr<float> accb = (lds_ptr<float>)&accl[0][threadIdx.x];
+    lds_ptr<A_t> accb = (lds_ptr<A_t>)&accl[0][threadIdx.x];
     if constexpr (LDSACC) asm volatile("" : "+v"(accb));
     const T m = ldoff(cb, ob), q = ldoff(cb + ld, ob), pB = ldoff(cb + 2 * ld, ob);
     const T cK = ldoff(cb + 3 * ld, ob), sK = ldoff(cb + 4 * ld, ob);
@@ -480,10 +481,10 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
                 } else if constexpr (LDSACC && J >= 1 && J <= 3) {
                   // ab + 6 j lies in [LO, HI): read-add-write this thread's own LDS slots (no other
                   // lane touches them, so no atomics)
-                  lds_ptr<float> g = accb + 256 * (ab + 6 * j - LO);
-                  const float v[6] = {(float)(A.re * Vm.re - A.im * Vm.im), (float)(A.re * Vm.im + A.im * Vm.re),
-                                      (float)(A.re * V0.re - A.im * V0.im), (float)(A.re * V0.im + A.im * V0.re),
-                                      (float)(A.re * Vp.re - A.im * Vp.im), (float)(A.re * Vp.im + A.im * Vp.re)};
+                  lds_ptr<A_t> g = accb + 256 * (ab + 6 * j - LO);
+                  const A_t v[6] = {(A_t)(A.re * Vm.re - A.im * Vm.im), (A_t)(A.re * Vm.im + A.im * Vm.re),
+                                    (A_t)(A.re * V0.re - A.im * V0.im), (A_t)(A.re * V0.im + A.im * V0.re),
+                                    (A_t)(A.re * Vp.re - A.im * Vp.im), (A_t)(A.re * Vp.im + A.im * Vp.re)};
 #pragma unroll
                   for (int q = 0; q < 6; ++q) g[256 * q] += v[q];
                   if (rc.flt >= 0) {

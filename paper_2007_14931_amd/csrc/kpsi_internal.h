@@ -30,10 +30,10 @@ template <int N0, int N1, int N2, int N3, int N4, int NZ_> struct Shape {
   static constexpr int NK = N0 + N1 + N2 + N3 + N4;
   static constexpr int NZ = NZ_;
   static constexpr int NKACC = 2 * N0 + 6 * (N1 + N2 + N3 + N4);
-  // Coupling accumulators [LDS_LO, LDS_HI) (spins 1..3) that the FP32 per-event kernel keeps in
-  // per-thread LDS slots instead of registers, for the large shape only: 36 floats x 256
-  // threads = 36 KB per block, so 4 blocks fit the 160 KB of a compute unit, and the freed
-  // registers allow 4 wavefronts per SIMD.
+  // Coupling accumulators [LDS_LO, LDS_HI) (spins 1..3) that the per-event gradient kernel
+  // keeps in per-thread LDS slots instead of registers, for the large shape only: 36 values x
+  // 256 threads per block (36 KB in FP32, 4 blocks per compute unit; 72 KB in FP64, 2 blocks),
+  // and the freed registers allow 4 (FP32) or 2 (FP64) wavefronts per SIMD.
   static constexpr int LDS_LO = (NK >= 8) ? 2 * N0 : 0;
   static constexpr int LDS_HI = (NK >= 8) ? 2 * N0 + 6 * (N1 + N2 + N3) : 0;
   static_assert(3 + NKACC + 4 * NZ_ + 2 * NFL <= NACC, "accumulators exceed the block record");
