@@ -101,8 +101,10 @@ def lib() -> C.CDLL:
         L.kpsi_set_efficiency_flat.argtypes = [vp]
         L.kpsi_set_efficiency_values.argtypes = [vp, dp, i64]
         L.kpsi_set_efficiency_hist.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int), dp, dp]
-        L.kpsi_nll.argtypes = [vp, dp, dp]
-        L.kpsi_nll_and_grad.argtypes = [vp, dp, dp, dp]
+        # pointer arguments of the per-call entry points are plain addresses (the binding's fast
+        # path passes ndarray.ctypes.data integers; ctypes pointer objects are accepted too)
+        L.kpsi_nll.argtypes = [vp, vp, vp]
+        L.kpsi_nll_and_grad.argtypes = [vp, vp, vp, vp]
         L.kpsi_density.argtypes = [vp, C.c_int, dp, dp]
         L.kpsi_invariants.argtypes = [vp, C.c_int, dp]
         L.kpsi_generate_phsp.argtypes = [vp, C.c_uint64, i64, C.c_double, vp, vp, vp, vp]
@@ -181,6 +183,8 @@ class Engine:
         self._keep = {}
         self.n_params = 0
         self.n = [0, 0]
+        self._out = C.c_double()
+        self._out_addr = C.addressof(self._out)
 
     def close(self):
         if getattr(self, "h", None):
@@ -244,16 +248,18 @@ class Engine:
 
     def nll(self, params) -> float:
         p = _f64(params)
-        out = C.c_double()
-        self._chk(self.L.kpsi_nll(self.h, _dp(p), C.byref(out)))
-        return out.value
+        st = self.L.kpsi_nll(self.h, p.ctypes.data, self._out_addr)
+        if st:
+            self._chk(st)
+        return self._out.value
 
     def nll_and_grad(self, params) -> tuple[float, np.ndarray]:
         p = _f64(params)
-        out = C.c_double()
         g = np.empty(self.n_params)
-        self._chk(self.L.kpsi_nll_and_grad(self.h, _dp(p), C.byref(out), _dp(g)))
-        return out.value, g
+        st = self.L.kpsi_nll_and_grad(self.h, p.ctypes.data, self._out_addr, g.ctypes.data)
+        if st:
+            self._chk(st)
+        return self._out.value, g
 
     def nll_status(self, params, grad: bool = False) -> tuple[int, float]:
         """Raw status and value (for error-path tests)."""

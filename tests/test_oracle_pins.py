@@ -636,3 +636,71 @@ def test_fit_fraction_of_a_lone_resonance_is_one_and_phase_invariant():
     rot[1:nc:2] += 0.7          # a common phase on every coupling leaves every fraction unchanged
     _, ff2 = O.fit_fractions(K, res, rot, ev)
     np.testing.assert_allclose(ff2, ff, rtol=1e-11)
+
+
+# ---------------------------------------------------------------- 50-digit evaluation of S
+def test_density_matches_50_digit_evaluation_of_the_kstar_chain():
+    # Eq. 2-5 re-evaluated at 50 significant digits (breakup momenta, Blatt-Weisskopf factors,
+    # mass-dependent width, Wigner d by the general formula, helicity sum) for the ten-K* model.
+    # This checks the oracle's double-precision evaluation, including events next to the
+    # threshold and the end point of m_Kpi.
+    import mpmath as mp
+    mp.mp.dps = 50
+    res = W.model("kstar10")
+    par = W.params(res, seed=29)
+    nc = sum(2 * r.n_coup for r in res)
+    ev = W.neutral_events(90, 37)
+    edge = np.array([[W.M_LO + 1e-4, W.M_LO + 1e-3, W.M_HI - 1e-4, W.M_HI - 1e-3, 0.9, 1.45, 2.0, 0.7, 1.2, 1.9],
+                     [0.3, -0.7, 0.9, -0.2, 1.0, -1.0, 0.0, 0.5, -0.5, 0.99],
+                     [-0.4, 0.6, -0.95, 0.1, 0.3, 1.0, -1.0, 0.0, 0.8, -0.6],
+                     [1.0, -2.0, 3.0, -3.1, 0.0, math.pi, -math.pi, 0.4, -1.3, 2.2]])
+    ev = np.concatenate([ev, edge], axis=1)
+    mB, mJ, mK, mPi, rB, rR = (mp.mpf(W.KIN[k]) for k in ("mB", "mJ", "mK", "mPi", "rB", "rR"))
+
+    def p2(M, m1, m2):
+        return mp.sqrt((M * M - (m1 + m2) ** 2) * (M * M - (m1 - m2) ** 2)) / (2 * M)
+
+    def bl(L, z):
+        return [1, 1 + z, 9 + 3 * z + z ** 2, 225 + 45 * z + 6 * z ** 2 + z ** 3,
+                11025 + 1575 * z + 135 * z ** 2 + 10 * z ** 3 + z ** 4][L]
+
+    def wd(j, mp_, m, th):
+        c, s = mp.cos(th / 2), mp.sin(th / 2)
+        tot = mp.mpf(0)
+        for k in range(0, 2 * j + 1):
+            a, b, cc, d = j + m - k, k, j - k - mp_, k - m + mp_
+            if min(a, b, cc, d) < 0:
+                continue
+            tot += ((-1) ** (k - m + mp_) * mp.sqrt(mp.factorial(j + mp_) * mp.factorial(j - mp_) * mp.factorial(j + m)
+                                                     * mp.factorial(j - m))
+                    / (mp.factorial(a) * mp.factorial(b) * mp.factorial(cc) * mp.factorial(d))
+                    * c ** (2 * j - 2 * k + m - mp_) * s ** (2 * k - m + mp_))
+        return tot
+
+    def lineshape(r, M, G0, m):
+        LR = r.spin
+        LB = 1 if r.spin == 0 else r.spin - 1
+        q, q0 = p2(m, mK, mPi), p2(M, mK, mPi)
+        pB, pB0 = p2(mB, mJ, m), p2(mB, mJ, M)
+        FR = mp.sqrt(bl(LR, (rR * q0) ** 2) / bl(LR, (rR * q) ** 2))
+        FB = mp.sqrt(bl(LB, (rB * pB0) ** 2) / bl(LB, (rB * pB) ** 2))
+        G = G0 * (q / q0) ** (2 * LR + 1) * (M / m) * FR ** 2
+        return FB * (pB / mB) ** LB * FR * (q / m) ** LR / (M * M - m * m - 1j * M * G)
+
+    got = O.density(K, res, par, ev)
+    for e in range(ev.shape[1]):
+        m, cK, cJ, ph = (mp.mpf(float(x)) for x in ev[:, e])
+        thK, thJ = mp.acos(cK), mp.acos(cJ)
+        a = {1: mp.mpc(0), -1: mp.mpc(0)}
+        ip = 0
+        for i, r in enumerate(res):
+            A = lineshape(r, mp.mpf(par[nc + 2 * i]), mp.mpf(par[nc + 2 * i + 1]), m)
+            lams = [0] if r.spin == 0 else [-1, 0, 1]
+            for k, lam in enumerate(lams):
+                H = mp.mpf(par[ip + 2 * k]) * mp.expj(mp.mpf(par[ip + 2 * k + 1]))
+                for xi in (1, -1):
+                    a[xi] += H * A * wd(r.spin, lam, 0, thK) * mp.expj(lam * ph) * wd(1, lam, xi, thJ)
+            ip += 2 * len(lams)
+        S = abs(a[1]) ** 2 + abs(a[-1]) ** 2
+        tol = 1e-10 if (ev[0, e] - W.M_LO < 2e-3 or W.M_HI - ev[0, e] < 2e-3) else 1e-12
+        assert got[e] == pytest.approx(float(S), rel=tol), (e, ev[:, e])
