@@ -487,6 +487,69 @@ int oracle_fit_fractions(const oracle_kin* kin, const oracle_res* res, int n_res
   return 0;
 }
 
+// -2 ln L of the mixture PDF of Eq. 14,  f = p eps S / N_S + (1 - p) b / N_b,  where
+// N_S = (1/N_MC) sum_j eps_j S(y_j) and N_b = (1/N_MC) sum_j b_j over the phase-space
+// normalisation events, so that both terms are normalised over phase space (the constant
+// phase-space volume is dropped).  NLL = -2 sum_i ln f(x_i).  eps_d / eps_m may be NULL
+// (efficiency 1); b_d, b_m are the background density at the data and normalisation events;
+// 0 < purity <= 1.  Gradient (forward-mode duals) along dirs[] when n_dir > 0.  Returns 0, -1
+// for bad arguments, or -5 when some f(x_i) <= 0 or a normalisation is not positive.
+int oracle_nll_mix(const oracle_kin* kin, const oracle_res* res, int n_res, const double* par, int64_t nd,
+                   const double* dm, const double* dck, const double* dcj, const double* dphi, int64_t nm,
+                   const double* mm, const double* mck, const double* mcj, const double* mphi, const double* eps_d,
+                   const double* b_d, const double* eps_m, const double* b_m, double purity, int n_dir,
+                   const int* dirs, double* nll, double* grad) {
+  Kin k = to_kin(kin);
+  std::vector<Res> rs = to_res(res, n_res);
+  const int np = n_full_params(rs);
+  if (nd <= 0 || nm <= 0 || !b_d || !b_m || !(purity > 0.0 && purity <= 1.0)) return -1;
+  if (n_dir < 0 || n_dir > KD) return -1;
+  for (int d = 0; d < n_dir; ++d) if (dirs[d] < 0 || dirs[d] >= np) return -1;
+  bool hasZ = false;
+  for (auto& r : rs) hasZ |= (r.chain == 1);
+  g_nd = n_dir;
+  std::vector<Dual> P(np);
+  for (int i = 0; i < np; ++i) P[i] = Dual(par[i]);
+  for (int d = 0; d < n_dir; ++d) P[dirs[d]].d[d] = 1.0;
+  auto dens = [&](double m, double cK, double cJ, double ph) {
+    Event ev{m, cK, cJ, ph};
+    ZAng za{0, 0, 0, 0, 0};
+    if (hasZ) za = z_angles(k, ev.m, ev.cK, ev.cJ, ev.phi);
+    return density<Dual>(k, rs, P.data(), ev, za);
+  };
+  // normalisations over the phase-space events
+  KSum sS, sB;
+  std::vector<double> gS(n_dir, 0.0);
+  for (int64_t j = 0; j < nm; ++j) {
+    const Dual s = dens(mm[j], mck[j], mcj[j], mphi[j]);
+    const double e = eps_m ? eps_m[j] : 1.0;
+    sS.add(e * s.v);
+    for (int d = 0; d < n_dir; ++d) gS[d] += e * s.d[d];
+    sB.add(b_m[j]);
+  }
+  const double NS = sS.get() / (double)nm, NB = sB.get() / (double)nm;
+  if (!(NS > 0.0) || !(NB > 0.0)) { *nll = INFINITY; return -5; }
+  std::vector<double> dNS(n_dir);
+  for (int d = 0; d < n_dir; ++d) dNS[d] = gS[d] / (double)nm;
+  // data: f_i = p eps_i S_i / N_S + (1 - p) b_i / N_b
+  KSum L;
+  std::vector<double> gL(n_dir, 0.0);
+  for (int64_t i = 0; i < nd; ++i) {
+    const Dual s = dens(dm[i], dck[i], dcj[i], dphi[i]);
+    const double e = eps_d ? eps_d[i] : 1.0;
+    const double f = purity * e * s.v / NS + (1.0 - purity) * b_d[i] / NB;
+    if (!(f > 0.0) || !std::isfinite(f)) { *nll = INFINITY; return -5; }
+    L.add(std::log(f));
+    for (int d = 0; d < n_dir; ++d) {
+      const double df = purity * e * (s.d[d] / NS - s.v * dNS[d] / (NS * NS));
+      gL[d] += df / f;
+    }
+  }
+  *nll = -2.0 * L.get();
+  for (int d = 0; d < n_dir; ++d) grad[d] = -2.0 * gL[d];
+  return 0;
+}
+
 // -2 ln L of the signal PDF eps*S normalised by the phase-space MC sum (Eq. 14 with
 // purity 1):  NLL = -2 sum_i ln S(x_i) + 2 N_d ln( (1/N_MC) sum_j eps_j S(y_j) ).
 // Parameter-independent terms (ln eps(x_i), phase-space factor, volume) are dropped.

@@ -704,3 +704,58 @@ def test_density_matches_50_digit_evaluation_of_the_kstar_chain():
         S = abs(a[1]) ** 2 + abs(a[-1]) ** 2
         tol = 1e-10 if (ev[0, e] - W.M_LO < 2e-3 or W.M_HI - ev[0, e] < 2e-3) else 1e-12
         assert got[e] == pytest.approx(float(S), rel=tol), (e, ev[:, e])
+
+
+# ---------------------------------------------------------------- signal + background mixture, Eq. (14)
+def _mix_inputs(n_d=400, n_m=2000):
+    res = W.model("full")
+    par = W.params(res, seed=41)
+    data = W.neutral_events(n_d, 43, peaked=True)
+    mc = O.gen_phsp(K, 44, n_m, W.PHSP_WMAX)
+    coef = W.acceptance_coefficients()
+    eps_d = O.acceptance(coef, W.M_LO, W.M_HI, data)
+    eps_m = O.acceptance(coef, W.M_LO, W.M_HI, mc)
+    rng = np.random.default_rng(45)
+    b_d = rng.uniform(0.2, 1.5, n_d)
+    b_m = rng.uniform(0.2, 1.5, n_m)
+    return res, par, data, mc, eps_d, eps_m, b_d, b_m
+
+
+def test_mixture_at_full_purity_is_the_signal_likelihood():
+    # p = 1: -2 sum ln(eps_i S_i / N_S) = signal NLL - 2 sum ln eps_i, same gradient
+    res, par, data, mc, eps_d, eps_m, b_d, b_m = _mix_inputs()
+    dirs = np.flatnonzero(W.free_mask(res, ("K*(1410)",)))
+    st, v, g = O.nll_mix(K, res, par, data, mc, b_d, b_m, 1.0, eps_d, eps_m, dirs)
+    st2, v2, g2 = O.nll(K, res, par, data, mc, eps=eps_m, dirs=dirs)
+    assert st == 0 and st2 == 0
+    assert v == pytest.approx(v2 - 2 * np.log(eps_d).sum(), rel=1e-13)
+    np.testing.assert_allclose(g, g2, rtol=1e-11, atol=1e-11 * np.abs(g2).max())
+
+
+@pytest.mark.parametrize("purity", [0.15, 0.5, 0.85])
+def test_mixture_with_signal_shaped_background_is_purity_independent(purity):
+    # b = eps S(theta0) on both sets makes f = eps S(theta0)/N_S(theta0) at theta0 for every p,
+    # and df/dtheta = p d(eps S/N_S)/dtheta there
+    res, par, data, mc, eps_d, eps_m, _, _ = _mix_inputs()
+    b_d = eps_d * O.density(K, res, par, data)
+    b_m = eps_m * O.density(K, res, par, mc)
+    dirs = np.flatnonzero(W.free_mask(res, ("Z(4430)",)))
+    _, v1, g1 = O.nll_mix(K, res, par, data, mc, b_d, b_m, 1.0, eps_d, eps_m, dirs)
+    st, v, g = O.nll_mix(K, res, par, data, mc, b_d, b_m, purity, eps_d, eps_m, dirs)
+    assert st == 0
+    assert v == pytest.approx(v1, rel=1e-13)
+    np.testing.assert_allclose(g, purity * g1, rtol=1e-10, atol=1e-10 * np.abs(g1).max())
+
+
+def test_mixture_gradient_matches_central_differences():
+    res, par, data, mc, eps_d, eps_m, b_d, b_m = _mix_inputs(200, 1000)
+    dirs = np.flatnonzero(W.free_mask(res, ("K*(1410)", "Z(4430)")))
+    _, v, g = O.nll_mix(K, res, par, data, mc, b_d, b_m, 0.85, eps_d, eps_m, dirs)
+    for k, i in enumerate(dirs[::5]):
+        h = 1e-6 * max(1.0, abs(par[i]))
+        pp, pm = par.copy(), par.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (O.nll_mix(K, res, pp, data, mc, b_d, b_m, 0.85, eps_d, eps_m)[1]
+              - O.nll_mix(K, res, pm, data, mc, b_d, b_m, 0.85, eps_d, eps_m)[1]) / (2 * h)
+        assert g[5 * k] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(g).max())
