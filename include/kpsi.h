@@ -228,6 +228,39 @@ kpsi_status kpsi_norm_cache_stats(const kpsi_ctx* ctx, int64_t* builds, int64_t*
  * parameters; KPSI_E_NONFINITE when the integral of the density is not positive. */
 kpsi_status kpsi_fit_fractions(kpsi_ctx* ctx, const double* params, double* ff, double* ff_sum);
 
+/* ---------------------------------------------------------------- signal + background (Eq. 14)
+ * The mixture PDF f = p eps S / N_S + (1 - p) b / N_b of Eq. 14 (Results: applicability to
+ * real-life use cases): p the signal purity, eps the relative signal efficiency, b the
+ * background density, N_S and N_b the normalisation-event means of eps S and of b, so that
+ * both terms are normalised over phase space.  Once set, kpsi_nll / kpsi_nll_and_grad return
+ *   -2 ln L = -2 sum_i ln(p eps_i S_i + (1 - p)(N_S / N_b) b_i) + 2 N_d ln N_S
+ * (equal to -2 sum_i ln f(x_i) up to the dropped phase-space volume).  The normalisation
+ * events keep the efficiency of kpsi_set_efficiency_*.  The data terms need N_S, so each call
+ * evaluates the normalisation events first (or takes them from the interference matrix).
+ *   purity:   0 < p <= 1.
+ *   eps_data: efficiency at each loaded data event (n_data doubles, host; NULL = 1).
+ *   b_data:   background density at each data event (n_data doubles, host; NULL switches the
+ *             mixture off and restores the signal-only likelihood).
+ *   b_norm:   background density at each normalisation event (n_norm doubles, host).
+ * Values are copied (and rounded to the context precision).  Loading either event set drops
+ * the mixture.  Errors: KPSI_E_ARG for a purity outside (0, 1], negative or non-finite values,
+ * or a non-positive background integral; KPSI_E_STATE unless both sets are loaded. */
+kpsi_status kpsi_set_background(kpsi_ctx* ctx, double purity, const double* eps_data, const double* b_data,
+                                const double* b_norm);
+
+/* Per-event values of a 2D (mass variables) x 2D (angular variables) template, the form in
+ * which the paper passes efficiency and background shapes to the fit: t_mass over
+ * (m_Kpi in [m_K + m_pi, M_B - M_J/psi], cos theta_K* in [-1, 1]) with n_mass[0] x n_mass[1]
+ * bins (row-major, m_Kpi slowest), t_ang over (cos theta_J/psi in [-1, 1], phi in [-pi, pi])
+ * with n_ang[0] x n_ang[1] bins.  (m_Kpi, cos theta_K*) maps one-to-one onto
+ * (m_Kpi, m_J/psi pi) at fixed m_Kpi and has a rectangular domain.  out[e] =
+ * t_mass[bin] * t_ang[bin] for every event of the set (host, n doubles); bins are [lo, hi),
+ * values outside are clamped into the edge bins.  Tables are host arrays, copied.
+ * Errors: KPSI_E_ARG for NULL arguments or non-positive bin counts; KPSI_E_STATE if the set is
+ * not loaded. */
+kpsi_status kpsi_template_values(kpsi_ctx* ctx, kpsi_set set, const float* t_mass, const int n_mass[2],
+                                 const float* t_ang, const int n_ang[2], double* out);
+
 /* ---------------------------------------------------------------- attainable peaks
  * Microbenchmarks of the device (no context needed), the ceilings against which the kernels'
  * rates are read: FP32 and FP64 fused multiply-add issue (one operation per lane per

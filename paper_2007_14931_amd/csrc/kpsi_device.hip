@@ -271,7 +271,11 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
   const int64_t e1 = (e0 + a.chunk < n) ? e0 + a.chunk : n;
 
   double ms = 0.0, mc = 0.0;   // Kahan pair
-  double nbad = 0.0;
+  float nbad = 0.f;   // events with a non-positive or non-finite density (exact count)
+  // Eq. 14 mixture on the data set: background weight k from the reduced normalisation total
+  const bool mix = (set == 0) && a.bkg_data != nullptr;
+  const T kb = mix ? (T)(a.bkg_coef * (a.norm_total[0] + a.norm_total[1])) : T(0);
+  A_t ws = A_t(0);   // sum_i w_i S_i (mixture, gradient mode)
   // accumulators gk[LO, HI) live in this thread's LDS column accl[.][tid] (gradient kernel)
   constexpr bool LDSACC = GRAD && (Sh::LDS_HI > Sh::LDS_LO);
   constexpr int LO = LDSACC ? Sh::LDS_LO : 0, HI = LDSACC ? Sh::LDS_HI : 0;
@@ -431,13 +435,23 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     // ---- likelihood terms
     T w;
     if (set == 0) {
-      if (!(S > T(0)) || !(S < T(INFINITY))) { nbad += 1.0; continue; }
-      const double x = (double)log_(S);
+      T arg = S;   // the quantity whose logarithm is summed
+      if (mix) {
+        // Eq. 14: t = p eps S + k b; d ln t / dS = p eps / t
+        const T pe = a.purity * (a.eps_data ? ldoff(a.eps_data + e0, ob) : T(1));
+        arg = fma_(pe, S, kb * ldoff(a.bkg_data + e0, ob));
+        if (!(arg > T(0)) || !(arg < T(INFINITY))) { nbad += 1.f; continue; }
+        w = pe * rcp_(arg);
+        ws += (A_t)(w * S);
+      } else {
+        if (!(S > T(0)) || !(S < T(INFINITY))) { nbad += 1.f; continue; }
+        w = rcp_(S);
+      }
+      const double x = (double)log_(arg);
       const double y = x - mc;
       const double t = ms + y;
       mc = (t - ms) - y;
       ms = t;
-      w = rcp_(S);
     } else {
       const T eps = a.eps ? ldoff(a.eps + e0, ob) : T(1);
       const double x = (double)(eps * S);
@@ -590,7 +604,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     auto accv = [&](int i) -> double {
       if (i == 0) return ms;
       if (i == 1) return -mc;   // Kahan: the running sum exceeds the exact one by mc
-      if (i == 2) return nbad;
+      if (i == 2) return (double)nbad;
       if (LDSACC && i >= 3 + LO && i < 3 + HI) return (double)accl[i - 3 - LO][threadIdx.x];
       if (i < 3 + Sh::NKACC) return (double)gk[i - 3];
       if (i < 3 + Sh::NKACC + 4 * NZ) return (double)gz[i - 3 - Sh::NKACC];
@@ -599,6 +613,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
       if (f == 1) return (double)gG0;
       if (f == 2) return (double)gM1;
       if (f == 3) return (double)gG1;
+      if (f == 4) return (double)ws;
       return 0.0;
     };
     // Transpose butterfly: after the step of width h, lane l keeps h values, each summed
@@ -629,7 +644,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     }
     red[wave][lane] = v[0];
   } else {
-    double v0 = ms, v1 = -mc, v2 = nbad;
+    double v0 = ms, v1 = -mc, v2 = (double)nbad;
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) {
       v0 += __shfl_xor(v0, s, 64);
@@ -659,8 +674,9 @@ __device__ __forceinline__ void two_sum_merge(double& s, double& c, double s2, d
 }
 
 __global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ partial, int nb_data, int nb_mc,
-                                                    int nv, double* __restrict__ out) {
-  const int set = blockIdx.x / nv, v = blockIdx.x % nv;
+                                                    int nv, double* __restrict__ out, double* __restrict__ out_dev,
+                                                    int first_set) {
+  const int set = first_set + (int)blockIdx.x / nv, v = blockIdx.x % nv;
   const int nbt = nb_data + nb_mc;
   const int b0 = set ? nb_data : 0;
   const int nb = set ? nb_mc : nb_data;
@@ -685,7 +701,11 @@ __global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ p
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[set * NACC + v] = S[0] + Cc[0];
+  if (threadIdx.x == 0) {
+    const double r = S[0] + Cc[0];
+    out[set * NACC + v] = r;
+    if (out_dev) out_dev[set * NACC + v] = r;
+  }
 }
 
 // ------------------------------------------------------------------ efficiency histogram
@@ -701,6 +721,20 @@ __global__ __launch_bounds__(256) void hist_lookup_kernel(HistArgs a) {
     idx = idx * a.nb[d] + b;
   }
   a.out_f64[e] = (double)a.table[idx];
+}
+
+// ------------------------------------------------------------------ 2D x 2D templates
+__global__ __launch_bounds__(256) void template_kernel(TplArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.n) return;
+  int b[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const double x = a.obs[d][e];
+    int k = (int)floor((x - a.lo[d]) / (a.hi[d] - a.lo[d]) * a.nb[d]);
+    b[d] = k < 0 ? 0 : (k >= a.nb[d] ? a.nb[d] - 1 : k);
+  }
+  a.out[e] = (double)a.t1[b[0] * a.nb[1] + b[1]] * (double)a.t2[b[2] * a.nb[3] + b[3]];
 }
 
 // ------------------------------------------------------------------ generators
@@ -857,13 +891,21 @@ template hipError_t launch_amp<double, ShapeSmall>(const AmpArgs<double, ShapeSm
 template hipError_t launch_amp<float, ShapeFull>(const AmpArgs<float, ShapeFull>&, int, int, hipStream_t);
 template hipError_t launch_amp<double, ShapeFull>(const AmpArgs<double, ShapeFull>&, int, int, hipStream_t);
 
-hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int nv, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_final, dim3(2 * nv), dim3(256), 0, st, partial, nb_data, nb_mc, nv, out);
+hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int nv, double* out, double* out_dev,
+                               int first_set, int n_sets, hipStream_t st) {
+  if (first_set < 0 || n_sets < 1 || first_set + n_sets > 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(reduce_final, dim3(n_sets * nv), dim3(256), 0, st, partial, nb_data, nb_mc, nv, out, out_dev,
+                     first_set);
   return hipGetLastError();
 }
 hipError_t launch_hist_lookup(const HistArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(hist_lookup_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_template(const TplArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(template_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 hipError_t launch_phsp(const GenArgs& a, hipStream_t st) {

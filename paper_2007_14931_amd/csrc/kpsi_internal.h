@@ -36,7 +36,7 @@ template <int N0, int N1, int N2, int N3, int N4, int NZ_> struct Shape {
   // and the freed registers allow 4 (FP32) or 2 (FP64) wavefronts per SIMD.
   static constexpr int LDS_LO = (NK >= 8) ? 2 * N0 : 0;
   static constexpr int LDS_HI = (NK >= 8) ? 2 * N0 + 6 * (N1 + N2 + N3) : 0;
-  static_assert(3 + NKACC + 4 * NZ_ + 2 * NFL <= NACC, "accumulators exceed the block record");
+  static_assert(3 + NKACC + 4 * NZ_ + 2 * NFL + 1 <= NACC, "accumulators exceed the block record");
 };
 using ShapeSmall = Shape<0, 1, 0, 0, 0, 0>;   // one spin-1 K*
 using ShapeFull = Shape<3, 3, 2, 1, 1, 2>;    // the ten K* of the paper and two Z
@@ -56,7 +56,18 @@ template <typename T, class Sh> struct AmpArgs {
   T rR, rB, invMB;
   RC<T> ks[Sh::NK > 0 ? Sh::NK : 1];
   RC<T> zs[Sh::NZ > 0 ? Sh::NZ : 1];
+  // Signal + background mixture (Eq. 14) on the data set, active when bkg_data != null:
+  // each data event contributes ln t with t = purity eps_i S_i + k b_i, where
+  // k = bkg_coef * (norm_total[0] + norm_total[1]) (bkg_coef = (1 - p) / (N_b N_MC), and
+  // norm_total the reduced normalisation record in device memory).
+  const T* eps_data;    // per-data-event efficiency, or null (1)
+  const T* bkg_data;    // per-data-event background density, or null (signal only)
+  const double* norm_total;
+  double bkg_coef;
+  T purity;
 };
+// Record slot of sum_i w_i S_i over the data events of the mixture (gradient mode).
+template <class Sh> constexpr int ws_slot() { return 3 + Sh::NKACC + 4 * Sh::NZ + 2 * NFL; }
 
 template <typename T> struct InvArgs {
   const double* obs[4];   // m_Kpi, cos theta_K*, cos theta_J/psi, phi
@@ -74,6 +85,18 @@ struct HistArgs {
   double lo[4], hi[4];
   int64_t n;
   double* out_f64;
+};
+
+// Product of a 2D table over (m_Kpi, cos theta_K*) and a 2D table over (cos theta_J/psi, phi),
+// looked up per event (bins [lo, hi), clamped into the edge bins), written as FP64.
+struct TplArgs {
+  const double* obs[4];
+  const float* t1;      // nb[0] x nb[1], row-major
+  const float* t2;      // nb[2] x nb[3], row-major
+  int nb[4];
+  double lo[4], hi[4];
+  int64_t n;
+  double* out;
 };
 
 struct GenArgs {
@@ -163,8 +186,12 @@ template <typename T, class Sh>
 hipError_t launch_imatrix(const ImArgs<T, Sh>& a, int ncols, int nb, double* out, hipStream_t st);
 template <typename T, class Sh> hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st);
 template <typename T, class Sh> int amp_blocks_per_cu(int mode);
-hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int nv, double* out, hipStream_t st);
+// Fixed-order sums of the block partials of sets first_set .. first_set + n_sets - 1 into
+// out[set * NACC + v] (and, when out_dev != null, also into out_dev[set * NACC + v]).
+hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int nv, double* out, double* out_dev,
+                               int first_set, int n_sets, hipStream_t st);
 hipError_t launch_hist_lookup(const HistArgs& a, hipStream_t st);
+hipError_t launch_template(const TplArgs& a, hipStream_t st);
 hipError_t launch_phsp(const GenArgs& a, hipStream_t st);
 hipError_t launch_accept(const AcceptArgs& a, hipStream_t st);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t st);

@@ -55,6 +55,13 @@ struct kpsi_ctx {
   size_t partial_cap = 0;       // in doubles
   double* red = nullptr;        // device view of red_host
   double* red_host = nullptr;   // [2][NACC], mapped pinned host memory
+  double* red_dev = nullptr;    // [2][NACC] device copy of the normalisation record (mixture)
+  // signal + background mixture of Eq. 14 (kpsi_set_background)
+  bool bkg_on = false;
+  double purity = 1.0;
+  double bkg_coef = 0.0;        // (1 - p) / (N_b N_MC)
+  void* eps_data = nullptr;     // T per data event, or null (efficiency 1)
+  void* bkg_data = nullptr;     // T per data event
   std::string err;
   bool timing = false;           // this call records timing events
   int timing_every = 0;          // time every k-th call (0: off)
@@ -572,6 +579,16 @@ kpsi_status use_cache(kpsi_ctx* c, const double* par, bool* use) {
   return KPSI_OK;
 }
 
+// Normalisation record from the interference matrix into the host record; with the Eq. 14
+// mixture also into the device copy that the data pass reads.
+kpsi_status put_cached_record(kpsi_ctx* c, const double* params) {
+  cached_norm_record(c, params, c->red_host + NACC);
+  if (c->bkg_on)
+    HIPCHECK(c, hipMemcpyAsync(c->red_dev + NACC, c->red_host + NACC, 2 * sizeof(double), hipMemcpyHostToDevice,
+                               c->stream));
+  return KPSI_OK;
+}
+
 // ---------------------------------------------------------------- per-call driver
 template <typename T, class Sh>
 kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: both*/, double** dens_out) {
@@ -584,25 +601,51 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   }
   a.eps = (const T*)c->eps;
   pack<T, Sh>(c, par, a);
-  int64_t nd = (which == 1) ? 0 : c->set[0].n, nm = (which == 0) ? 0 : c->set[1].n;
-  const int ept = pick_ept<T, Sh>(c, mode, nd, nm);
-  a.chunk = BLOCK * ept;
-  const int nbd = (int)((nd + a.chunk - 1) / a.chunk), nbm = (int)((nm + a.chunk - 1) / a.chunk);
-  a.nb_data = nbd;
-  if (mode != MODE_DENSITY) {
-    kpsi_status st = ensure_partial(c, (size_t)(nbd + nbm));
-    if (st) return st;
+  const int nv = mode == MODE_GRAD ? NACC : 3;
+  const bool mix = c->bkg_on && mode != MODE_DENSITY;
+  if (mix) {
+    a.eps_data = (const T*)c->eps_data;
+    a.bkg_data = (const T*)c->bkg_data;
+    a.norm_total = c->red_dev + NACC;
+    a.bkg_coef = c->bkg_coef;
+    a.purity = (T)c->purity;
   }
-  a.partial = c->partial;
   c->timing = mode != MODE_DENSITY && c->timing_every > 0 && (c->timing_calls++ % c->timing_every) == 0;
   if (c->timing) hipEventRecord(c->ev0, c->stream);
-  hipError_t e = launch_amp<T, Sh>(a, mode, nbd + nbm, c->stream);
-  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "amplitude kernel: %s", hipGetErrorString(e));
-  if (c->timing) hipEventRecord(c->ev1, c->stream);
+  // one launch over the events of [nd data, nm normalisation], block partials reduced into the
+  // record slots of sets first..first+nsets-1 (written by the GPU straight into mapped pinned
+  // host memory, and into the device copy when out_dev is given)
+  auto pass = [&](int64_t nd, int64_t nm, int first, int nsets, double* out_dev, bool last) -> kpsi_status {
+    AmpArgs<T, Sh> b = a;
+    const int ept = pick_ept<T, Sh>(c, mode, nd, nm);
+    b.chunk = BLOCK * ept;
+    const int nbd = (int)((nd + b.chunk - 1) / b.chunk), nbm = (int)((nm + b.chunk - 1) / b.chunk);
+    b.nb_data = nbd;
+    if (mode != MODE_DENSITY) {
+      kpsi_status st = ensure_partial(c, (size_t)(nbd + nbm));
+      if (st) return st;
+    }
+    b.partial = c->partial;
+    hipError_t e = launch_amp<T, Sh>(b, mode, nbd + nbm, c->stream);
+    if (e != hipSuccess) return fail(c, KPSI_E_HIP, "amplitude kernel: %s", hipGetErrorString(e));
+    if (last && c->timing) hipEventRecord(c->ev1, c->stream);   // end of the per-event work
+    if (mode == MODE_DENSITY) return KPSI_OK;
+    e = launch_reduce_final(c->partial, nbd, nbm, nv, c->red, out_dev, first, nsets, c->stream);
+    if (e != hipSuccess) return fail(c, KPSI_E_HIP, "reduction kernel: %s", hipGetErrorString(e));
+    return KPSI_OK;
+  };
+  const int64_t nd = (which == 1) ? 0 : c->set[0].n, nm = (which == 0) ? 0 : c->set[1].n;
+  kpsi_status st = KPSI_OK;
+  if (!mix) {
+    st = pass(nd, nm, which == 1 ? 1 : 0, which < 0 ? 2 : 1, nullptr, true);
+  } else {
+    // Eq. 14: the data terms need the normalisation total, so the normalisation events go
+    // first (unless their record comes from the interference matrix and is already in red_dev)
+    if (nm > 0) st = pass(0, nm, 1, 1, c->red_dev, nd == 0);
+    if (!st && nd > 0) st = pass(nd, 0, 0, 1, nullptr, true);
+  }
+  if (st) return st;
   if (mode == MODE_DENSITY) return KPSI_OK;
-  // the final sums are written by the GPU straight into mapped pinned host memory
-  e = launch_reduce_final(c->partial, nbd, nbm, mode == MODE_GRAD ? NACC : 3, c->red, c->stream);
-  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "reduction kernel: %s", hipGetErrorString(e));
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   if (c->timing) {
     float ms = 0.f;
@@ -667,7 +710,8 @@ kpsi_status kpsi_create(int device, void* stream, kpsi_precision prec, kpsi_ctx*
     c->own_stream = true;
   }
   if (hipHostMalloc(&c->red_host, 2 * NACC * sizeof(double), hipHostMallocMapped) != hipSuccess ||
-      hipHostGetDevicePointer((void**)&c->red, c->red_host, 0) != hipSuccess) {
+      hipHostGetDevicePointer((void**)&c->red, c->red_host, 0) != hipSuccess ||
+      hipMalloc(&c->red_dev, 2 * NACC * sizeof(double)) != hipSuccess) {
     kpsi_destroy(c);
     return fail(nullptr, KPSI_E_OOM, "result buffers");
   }
@@ -690,6 +734,9 @@ kpsi_status kpsi_destroy(kpsi_ctx* c) {
   if (c->cache_partial) hipFree(c->cache_partial);
   if (c->cache_out) hipFree(c->cache_out);
   if (c->red_host) hipHostFree(c->red_host);
+  if (c->red_dev) hipFree(c->red_dev);
+  if (c->eps_data) hipFree(c->eps_data);
+  if (c->bkg_data) hipFree(c->bkg_data);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -786,11 +833,108 @@ kpsi_status kpsi_set_floating(kpsi_ctx* c, const int* flags, int n_res) {
   return KPSI_OK;
 }
 
+static void drop_background(kpsi_ctx* c) {
+  if (c->eps_data) hipFree(c->eps_data);
+  if (c->bkg_data) hipFree(c->bkg_data);
+  c->eps_data = c->bkg_data = nullptr;
+  c->bkg_on = false;
+}
+
 static kpsi_status load_common(kpsi_ctx* c, kpsi_set set, int64_t n) {
   if (!c) return KPSI_E_ARG;
   if (set != KPSI_DATA && set != KPSI_NORM) return fail(c, KPSI_E_ARG, "unknown set");
   if (n <= 0) return fail(c, KPSI_E_ARG, "n must be positive");
   if (!c->has_model) return fail(c, KPSI_E_STATE, "set the model before loading events");
+  drop_background(c);   // its per-event values belong to the previous events
+  return KPSI_OK;
+}
+
+// Per-event values of a host array into a new device array of the context precision.
+static kpsi_status upload_values(kpsi_ctx* c, const double* v, int64_t n, void** out) {
+  const size_t ts = tsize(c);
+  if (hipMalloc(out, (size_t)n * ts) != hipSuccess) return fail(c, KPSI_E_OOM, "per-event values");
+  std::vector<unsigned char> buf((size_t)n * ts);
+  if (c->prec == KPSI_FP32) {
+    float* f = reinterpret_cast<float*>(buf.data());
+    for (int64_t i = 0; i < n; ++i) f[i] = (float)v[i];
+  } else {
+    std::memcpy(buf.data(), v, (size_t)n * sizeof(double));
+  }
+  HIPCHECK(c, hipMemcpy(*out, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_set_background(kpsi_ctx* c, double purity, const double* eps_data, const double* b_data,
+                                const double* b_norm) {
+  if (!c) return KPSI_E_ARG;
+  hipSetDevice(c->device);
+  drop_background(c);
+  if (!b_data) return KPSI_OK;   // signal-only likelihood
+  if (!b_norm) return fail(c, KPSI_E_ARG, "b_norm is NULL");
+  if (!(purity > 0.0 && purity <= 1.0)) return fail(c, KPSI_E_ARG, "purity %g outside (0, 1]", purity);
+  const int64_t nd = c->set[0].n, nm = c->set[1].n;
+  if (nd <= 0 || nm <= 0) return fail(c, KPSI_E_STATE, "load both event sets before the background");
+  for (int64_t i = 0; i < nd; ++i) {
+    if (!(b_data[i] >= 0.0) || !std::isfinite(b_data[i])) return fail(c, KPSI_E_ARG, "b_data[%lld] invalid", (long long)i);
+    if (eps_data && (!(eps_data[i] >= 0.0) || !std::isfinite(eps_data[i])))
+      return fail(c, KPSI_E_ARG, "eps_data[%lld] invalid", (long long)i);
+  }
+  double s = 0.0, comp = 0.0;   // Neumaier sum of b over the normalisation events
+  for (int64_t j = 0; j < nm; ++j) {
+    const double x = b_norm[j];
+    if (!(x >= 0.0) || !std::isfinite(x)) return fail(c, KPSI_E_ARG, "b_norm[%lld] invalid", (long long)j);
+    const double t = s + x;
+    comp += (std::fabs(s) >= std::fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  const double nb = (s + comp) / (double)nm;
+  if (!(nb > 0.0)) return fail(c, KPSI_E_ARG, "background integral over the normalisation events is %g", nb);
+  kpsi_status st = upload_values(c, b_data, nd, &c->bkg_data);
+  if (!st && eps_data) st = upload_values(c, eps_data, nd, &c->eps_data);
+  if (st) { drop_background(c); return st; }
+  c->purity = purity;
+  c->bkg_coef = (1.0 - purity) / (nb * (double)nm);
+  c->bkg_on = true;
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_template_values(kpsi_ctx* c, kpsi_set set, const float* t_mass, const int n_mass[2],
+                                 const float* t_ang, const int n_ang[2], double* out) {
+  if (!c) return KPSI_E_ARG;
+  if (set != KPSI_DATA && set != KPSI_NORM) return fail(c, KPSI_E_ARG, "unknown set");
+  if (!t_mass || !n_mass || !t_ang || !n_ang || !out) return fail(c, KPSI_E_ARG, "NULL argument");
+  if (n_mass[0] <= 0 || n_mass[1] <= 0 || n_ang[0] <= 0 || n_ang[1] <= 0) return fail(c, KPSI_E_ARG, "bad bin counts");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set (kinematics needed)");
+  const DevSet& d = c->set[set];
+  if (d.n <= 0) return fail(c, KPSI_E_STATE, "set not loaded");
+  hipSetDevice(c->device);
+  const size_t n1 = (size_t)n_mass[0] * n_mass[1], n2 = (size_t)n_ang[0] * n_ang[1];
+  float *d1 = nullptr, *d2 = nullptr;
+  double* dout = nullptr;
+  auto cleanup = [&]() { if (d1) hipFree(d1); if (d2) hipFree(d2); if (dout) hipFree(dout); };
+  if (hipMalloc(&d1, n1 * sizeof(float)) || hipMalloc(&d2, n2 * sizeof(float)) ||
+      hipMalloc(&dout, (size_t)d.n * sizeof(double))) {
+    cleanup();
+    return fail(c, KPSI_E_OOM, "template buffers");
+  }
+  TplArgs a{};
+  for (int j = 0; j < 4; ++j) a.obs[j] = d.obs[j];
+  a.t1 = d1;
+  a.t2 = d2;
+  a.nb[0] = n_mass[0]; a.nb[1] = n_mass[1]; a.nb[2] = n_ang[0]; a.nb[3] = n_ang[1];
+  a.lo[0] = c->kin.m_k + c->kin.m_pi; a.hi[0] = c->kin.m_b - c->kin.m_jpsi;
+  a.lo[1] = -1.0; a.hi[1] = 1.0;
+  a.lo[2] = -1.0; a.hi[2] = 1.0;
+  a.lo[3] = -M_PI; a.hi[3] = M_PI;
+  a.n = d.n;
+  a.out = dout;
+  hipError_t e = hipMemcpyAsync(d1, t_mass, n1 * sizeof(float), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d2, t_ang, n2 * sizeof(float), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_template(a, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, (size_t)d.n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  cleanup();
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "template lookup: %s", hipGetErrorString(e));
   return KPSI_OK;
 }
 
@@ -923,9 +1067,12 @@ kpsi_status kpsi_nll(kpsi_ctx* c, const double* params, double* nll) {
   bool cached = false;
   st = use_cache(c, params, &cached);
   if (st) return st;
+  if (cached) {
+    st = put_cached_record(c, params);
+    if (st) return st;
+  }
   st = dispatch(c, MODE_NLL, params, cached ? 0 : -1, nullptr);
   if (st) return st;
-  if (cached) cached_norm_record(c, params, c->red_host + NACC);
   const double* rd = c->red_host;
   const double* rm = c->red_host + NACC;
   const double nd = (double)c->set[0].n, nm = (double)c->set[1].n;
@@ -946,9 +1093,12 @@ kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, do
   bool cached = false;
   st = use_cache(c, params, &cached);
   if (st) return st;
+  if (cached) {
+    st = put_cached_record(c, params);
+    if (st) return st;
+  }
   st = dispatch(c, MODE_GRAD, params, cached ? 0 : -1, nullptr);
   if (st) return st;
-  if (cached) cached_norm_record(c, params, c->red_host + NACC);
   const double* rd = c->red_host;
   const double* rm = c->red_host + NACC;
   const double nd = (double)c->set[0].n, nm = (double)c->set[1].n;
@@ -959,13 +1109,15 @@ kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, do
     return fail(c, KPSI_E_NONFINITE, "%.0f data events with non-positive density; normalisation %g", rd[2], sm);
   }
   *nll = -2.0 * (rd[0] + rd[1]) + 2.0 * nd * std::log(sm / nm);
-  // combined complex sensitivity G = -2 G_data + 2 N_d G_norm / sum(eps S);
+  // combined complex sensitivity G = -2 G_data + 2 W G_norm / sum(eps S), W = N_d (signal
+  // only) or sum_i w_i S_i (Eq. 14 mixture, w_i = p eps_i / t_i);
   // dNLL/dr = 2 Re(e^{i phi} G), dNLL/dphi = -2 Im(H G)
-  const double fm = 2.0 * nd / sm;
   int N[5], NZ;
   shape_counts(c->shape, N, &NZ);
   int nkacc = 0;
   for (int j = 0; j < 5; ++j) nkacc += N[j] * (j == 0 ? 2 : 6);
+  const double wsum = c->bkg_on ? rd[3 + nkacc + 4 * NZ + 2 * NFL] : nd;
+  const double fm = 2.0 * wsum / sm;
   const int ncr = c->nparams - 2 * (int)c->res.size();
   for (size_t i = 0; i < c->res.size(); ++i) {
     const kpsi_resonance& r = c->res[i];

@@ -28,7 +28,8 @@ EXPORTS = [
     "kpsi_set_timing", "kpsi_timing", "kpsi_set_events_per_thread", "kpsi_last_error",
     "kpsi_fit_default_options", "kpsi_migrad", "kpsi_hesse", "kpsi_set_norm_cache", "kpsi_norm_cache_stats",
     "kpsi_mlp_default_options", "kpsi_accept_labels", "kpsi_hist_efficiency", "kpsi_mlp_grad", "kpsi_mlp_train",
-    "kpsi_mlp_eval", "kpsi_set_efficiency_mlp", "kpsi_fit_fractions", "kpsi_measure_peaks",
+    "kpsi_mlp_eval", "kpsi_set_efficiency_mlp", "kpsi_fit_fractions", "kpsi_measure_peaks", "kpsi_set_background",
+    "kpsi_template_values",
 ]
 MLP_NP = 4545
 
@@ -120,6 +121,9 @@ def lib() -> C.CDLL:
         L.kpsi_norm_cache_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), dp]
         L.kpsi_fit_fractions.argtypes = [vp, dp, dp, dp]
         L.kpsi_measure_peaks.argtypes = [C.c_int, C.POINTER(Peaks)]
+        L.kpsi_set_background.argtypes = [vp, C.c_double, dp, dp, dp]
+        L.kpsi_template_values.argtypes = [vp, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_int),
+                                           C.POINTER(C.c_float), C.POINTER(C.c_int), dp]
         fp = C.POINTER(C.c_float)
         L.kpsi_mlp_default_options.argtypes = [C.POINTER(MlpOptions)]
         L.kpsi_accept_labels.argtypes = [vp, C.c_uint64, i64, i64, vp, vp, vp, vp, dp, vp, vp]
@@ -422,6 +426,23 @@ class Engine:
         tot = C.c_double()
         self._chk(self.L.kpsi_fit_fractions(self.h, _dp(p), _dp(ff), C.byref(tot)))
         return ff, tot.value
+
+    def set_background(self, purity: float, eps_data, b_data, b_norm) -> None:
+        """Eq. 14 mixture (kpsi_set_background); b_data None switches it off."""
+        arrs = [None if a is None else _f64(a) for a in (eps_data, b_data, b_norm)]
+        self._chk(self.L.kpsi_set_background(self.h, purity, *(None if a is None else _dp(a) for a in arrs)))
+
+    def template_values(self, which: int, t_mass, t_ang) -> np.ndarray:
+        """Per-event product of a (m_Kpi, cos theta_K*) table and a (cos theta_J/psi, phi) table."""
+        t1 = np.ascontiguousarray(t_mass, dtype=np.float32)
+        t2 = np.ascontiguousarray(t_ang, dtype=np.float32)
+        n1 = np.array(t1.shape, dtype=np.int32)
+        n2 = np.array(t2.shape, dtype=np.int32)
+        out = np.empty(self.n[which])
+        fp, ip = C.POINTER(C.c_float), C.POINTER(C.c_int)
+        self._chk(self.L.kpsi_template_values(self.h, which, t1.ctypes.data_as(fp), n1.ctypes.data_as(ip),
+                                              t2.ctypes.data_as(fp), n2.ctypes.data_as(ip), _dp(out)))
+        return out
 
     def set_events_per_thread(self, ept: int) -> None:
         self._chk(self.L.kpsi_set_events_per_thread(self.h, ept))

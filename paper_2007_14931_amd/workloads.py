@@ -229,3 +229,30 @@ def mlp_init(seed: int = 0) -> np.ndarray:
     p[4480:4544] = rng.uniform(-a3, a3, 64)
     p[4544] = np.log(0.6 / 0.4)
     return p
+
+
+# Background shape of the signal + background study: a product of two 2D Bernstein
+# polynomials of degree 3, over (m_Kpi, cos theta_K*) and (cos theta_J/psi, phi), with seeded
+# positive coefficients (the paper's generic background shapes are 2D Bernstein polynomials
+# passed to the fit as 2D x 2D histograms).
+def background_coefficients(seed: int = 400) -> tuple[np.ndarray, np.ndarray]:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(0.2, 1.0, size=(4, 4)), rng.uniform(0.2, 1.0, size=(4, 4))
+
+
+def _bernstein2(c: np.ndarray, u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """sum_ij c[i, j] B_i^3(u) B_j^3(v) for u, v in [0, 1]."""
+    def basis(t):
+        return np.stack([(1 - t) ** 3, 3 * t * (1 - t) ** 2, 3 * t ** 2 * (1 - t), t ** 3])
+    return np.einsum("ij,i...,j...->...", c, basis(u), basis(v))
+
+
+def background_templates(nbins=(40, 40, 40, 40), seed: int = 400) -> tuple[np.ndarray, np.ndarray]:
+    """The background shape at the bin centres of a (m_Kpi, cos theta_K*) table and a
+    (cos theta_J/psi, phi) table, float32, row-major."""
+    cm, ca = background_coefficients(seed)
+    u = [(np.arange(n) + 0.5) / n for n in nbins]
+    t1 = _bernstein2(cm, u[0][:, None], u[1][None, :])
+    t2 = _bernstein2(ca, u[2][:, None], u[3][None, :])
+    return t1.astype(np.float32), t2.astype(np.float32)
+

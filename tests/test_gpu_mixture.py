@@ -1,0 +1,91 @@
+"""Signal + background mixture of Eq. 14 on the GPU against the FP64 oracle, with and without
+the interference-matrix normalisation, and the 2D x 2D template lookup."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2007_14931_amd import kpsi
+from paper_2007_14931_amd import workloads as W
+
+K = W.KIN
+pytestmark = pytest.mark.gpu
+FLOAT = ("K*(1410)", "Z(4430)")
+
+
+def _inputs(nd=5003, nm=20011):
+    res = W.model("full")
+    data = W.neutral_events(nd, 51, peaked=True)
+    data[0] = np.clip(data[0], W.M_LO + 1e-6, W.M_HI - 1e-6)
+    mc = O.gen_phsp(K, 52, nm, W.PHSP_WMAX)
+    coef = W.acceptance_coefficients()
+    eps_d = O.acceptance(coef, W.M_LO, W.M_HI, data)
+    eps_m = O.acceptance(coef, W.M_LO, W.M_HI, mc)
+    rng = np.random.default_rng(53)
+    b_d = rng.uniform(0.2, 1.5, nd)
+    b_m = rng.uniform(0.2, 1.5, nm)
+    return res, data, mc, eps_d, eps_m, b_d, b_m
+
+
+def _engine(prec, res, data, mc, eps_m):
+    e = kpsi.Engine(0, prec)
+    e.set_model(K, res)
+    e.set_floating([1 if r.name in FLOAT else 0 for r in res])
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    e.set_efficiency_values(eps_m)
+    return e
+
+
+@pytest.mark.parametrize("prec,tv,tg,cache", [("fp64", 1e-10, 1e-9, 0), ("fp64", 1e-10, 1e-9, 1),
+                                              ("fp32", 1e-6, 2e-5, 0), ("fp32", 1e-6, 2e-5, 1)])
+def test_mixture_matches_oracle(prec, tv, tg, cache):
+    res, data, mc, eps_d, eps_m, b_d, b_m = _inputs()
+    e = _engine(prec, res, data, mc, eps_m)
+    e.set_background(0.85, eps_d, b_d, b_m)
+    e.set_norm_cache(cache)
+    par = W.params(res, seed=14) + 0.03 * W.free_mask(res, FLOAT)
+    free = np.flatnonzero(W.free_mask(res, FLOAT))
+    st, ref, gref = O.nll_mix(K, res, par, data, mc, b_d, b_m, 0.85, eps_d, eps_m, dirs=free)
+    assert st == 0
+    v, g = e.nll_and_grad(par)
+    assert v == pytest.approx(ref, rel=tv)
+    assert np.max(np.abs(g[free] - gref)) / np.max(np.abs(gref)) < tg
+    assert e.nll(par) == pytest.approx(ref, rel=tv)
+    if cache:
+        assert e.norm_cache_stats()[0] >= 1
+
+
+def test_mixture_off_and_reload_restore_the_signal_likelihood():
+    res, data, mc, eps_d, eps_m, b_d, b_m = _inputs(2001, 6007)
+    e = _engine("fp64", res, data, mc, eps_m)
+    par = W.params(res, seed=15)
+    v_sig = e.nll(par)
+    e.set_background(0.7, eps_d, b_d, b_m)
+    assert abs(e.nll(par) - v_sig) > 1.0
+    e.set_background(0.7, None, None, None)
+    assert e.nll(par) == v_sig
+    e.set_background(0.7, eps_d, b_d, b_m)
+    e.load(kpsi.DATA, data)            # reloading drops the mixture
+    assert e.nll(par) == pytest.approx(v_sig, rel=1e-14)
+    with pytest.raises(kpsi.KpsiError):
+        e.set_background(1.5, eps_d, b_d, b_m)
+
+
+def test_template_values_match_lookup():
+    res = W.model("full")
+    ev = W.neutral_events(3001, 54)
+    e = kpsi.Engine(0, "fp32")
+    e.set_model(K, res)
+    e.load(kpsi.DATA, ev)
+    rng = np.random.default_rng(55)
+    t1 = rng.uniform(0.3, 1.0, (17, 9)).astype(np.float32)
+    t2 = rng.uniform(0.3, 1.0, (7, 11)).astype(np.float32)
+    got = e.template_values(kpsi.DATA, t1, t2)
+    lo = [W.M_LO, -1.0, -1.0, -math.pi]
+    hi = [W.M_HI, 1.0, 1.0, math.pi]
+    nb = [17, 9, 7, 11]
+    b = [np.clip(np.floor((ev[d] - lo[d]) / (hi[d] - lo[d]) * nb[d]).astype(int), 0, nb[d] - 1) for d in range(4)]
+    ref = t1[b[0], b[1]].astype(np.float64) * t2[b[2], b[3]].astype(np.float64)
+    np.testing.assert_array_equal(got, ref)
