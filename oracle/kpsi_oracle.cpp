@@ -84,7 +84,9 @@ template <class T> Cx<T> ctoT(const Cx<double>& a) { return {T(a.re), T(a.im)}; 
 // ------------------------------------------------------------------ model
 struct Kin { double mB, mJ, mK, mPi, rB, rR; };
 // chain: 0 = K* (K pi), 1 = Z (J/psi pi); lb/lr < 0 => lowest allowed.
-struct Res { int chain, spin, parity, lb, lr; double mass, width; };
+// shape: 0 relativistic Breit-Wigner (Eq. 2-3); 1 LASS S-wave (Eq. 7-8) with effective-range
+// parameters a, b (GeV^-1) for a spin-0 K*.
+struct Res { int chain, spin, parity, lb, lr; double mass, width; int shape; double lass_a, lass_b; };
 
 // Lowest orbital momenta (text below Eq. 3 for the K*; angular momentum and
 // parity for the Z, which decays strongly to J/psi(1-) pi(0-)).
@@ -159,6 +161,24 @@ template <class T> Cx<T> lineshape(const Kin& k, const Res& r, const T& M, const
   }
   T FR = barrier(LR, p, p0, k.rR);
   T FB = barrier(LB, pB, pB0, k.rB);
+  if (r.shape == 1) {
+    // LASS (Eq. 7-8), written as the unitarised sum of an effective-range phase and the scalar
+    // resonance (reading: the printed factor 2 of the resonant term is dropped, the B-decay
+    // factor F_B (p_B/M_B)^L_B of Eq. 2 is kept):
+    //   A = F_B (p_B/M_B)^L_B [ (m/q) sin dB e^{i dB} + e^{2 i dB} (M^2 G0 / q0) / (M^2 - m^2 - i M G(m)) ]
+    //   cot dB = 1/(a q) + b q / 2,  G(m) = G0 (q/q0) (M/m)
+    // at threshold (q = 0): dB = 0 and (m/q) sin dB e^{i dB} -> m a
+    const double cot = p > 0.0 ? 1.0 / (r.lass_a * p) + 0.5 * r.lass_b * p : INFINITY;
+    const double dB = std::atan2(1.0, cot);
+    const Cx<T> nr = p > 0.0 ? Cx<T>{T((m / p) * std::sin(dB) * std::cos(dB)), T((m / p) * std::sin(dB) * std::sin(dB))}
+                             : Cx<T>{T(m * r.lass_a), T(0.0)};
+    const Cx<T> e2{T(std::cos(2.0 * dB)), T(std::sin(2.0 * dB))};
+    const T Gam = G0 * (T(p) / p0) * (M / m);
+    const Cx<T> res = cdiv(Cx<T>{M * M * G0 / p0, T(0.0)}, Cx<T>{M * M - m * m, -(M * Gam)});
+    const T pre = FB * std::pow(pB / k.mB, LB);
+    const Cx<T> t{nr.re + e2.re * res.re - e2.im * res.im, nr.im + e2.re * res.im + e2.im * res.re};
+    return Cx<T>{pre * t.re, pre * t.im};
+  }
   T ratio = T(p) / p0;
   T Gam = G0 * ipow(ratio, 2 * LR + 1) * (M / m) * FR * FR;
   T num = FB * std::pow(pB / k.mB, LB) * FR * std::pow(p / m, LR);
@@ -372,11 +392,13 @@ using namespace orc;
 extern "C" {
 
 struct oracle_kin { double mB, mJ, mK, mPi, rB, rR; };
-struct oracle_res { int chain, spin, parity, lb, lr; double mass, width; };
+struct oracle_res { int chain, spin, parity, lb, lr; double mass, width; int shape; double lass_a, lass_b; };
 
 static std::vector<Res> to_res(const oracle_res* r, int n) {
   std::vector<Res> v;
-  for (int i = 0; i < n; ++i) v.push_back(Res{r[i].chain, r[i].spin, r[i].parity, r[i].lb, r[i].lr, r[i].mass, r[i].width});
+  for (int i = 0; i < n; ++i)
+    v.push_back(Res{r[i].chain, r[i].spin, r[i].parity, r[i].lb, r[i].lr, r[i].mass, r[i].width, r[i].shape,
+                    r[i].lass_a, r[i].lass_b});
   return v;
 }
 static Kin to_kin(const oracle_kin* k) { return Kin{k->mB, k->mJ, k->mK, k->mPi, k->rB, k->rR}; }
@@ -389,7 +411,8 @@ double oracle_breakup(double M, double m1, double m2) { return breakup(M, m1, m2
 // Lineshape of resonance ir at running mass m (Eq. 2-3); M and Gamma0 given explicitly.
 void oracle_lineshape(const oracle_kin* kin, const oracle_res* res, double M, double G0, double m, double* out_re_im) {
   Kin k = to_kin(kin);
-  Res r{res->chain, res->spin, res->parity, res->lb, res->lr, res->mass, res->width};
+  Res r{res->chain, res->spin, res->parity, res->lb, res->lr, res->mass, res->width, res->shape, res->lass_a,
+        res->lass_b};
   Cx<double> a = lineshape<double>(k, r, M, G0, m);
   out_re_im[0] = a.re; out_re_im[1] = a.im;
 }

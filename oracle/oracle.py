@@ -33,7 +33,8 @@ class Kin(C.Structure):
 
 class Res(C.Structure):
     _fields_ = [("chain", C.c_int), ("spin", C.c_int), ("parity", C.c_int), ("lb", C.c_int), ("lr", C.c_int),
-                ("mass", C.c_double), ("width", C.c_double)]
+                ("mass", C.c_double), ("width", C.c_double), ("shape", C.c_int), ("lass_a", C.c_double),
+                ("lass_b", C.c_double)]
 
 
 _lib = None
@@ -87,7 +88,7 @@ def kin(d: dict) -> Kin:
 def res_array(res) -> C.Array:
     arr = (Res * len(res))()
     for i, r in enumerate(res):
-        arr[i] = Res(r.chain, r.spin, r.parity, r.lb, r.lr, r.mass, r.width)
+        arr[i] = Res(r.chain, r.spin, r.parity, r.lb, r.lr, r.mass, r.width, r.shape, r.lass_a, r.lass_b)
     return arr
 
 

@@ -43,6 +43,9 @@ class Resonance:
     width: float
     lb: int = -1     # < 0: lowest allowed orbital momentum
     lr: int = -1
+    shape: int = 0           # 0 relativistic Breit-Wigner, 1 LASS S-wave (spin-0 K* only)
+    lass_a: float = 1.95     # LASS effective-range parameters (GeV^-1)
+    lass_b: float = 1.76
 
     @property
     def n_coup(self) -> int:
@@ -66,6 +69,9 @@ KSTARS = [
 Z4430 = Resonance("Z(4430)", ZCHAIN, 1, +1, 4.43, 0.18)
 Z4240 = Resonance("Z(4240)", ZCHAIN, 1, +1, 4.24, 0.60)
 KSTAR892 = KSTARS[1]
+# The low-mass K pi S-wave in the LASS form: the effective-range term with the K0*(1430)
+# resonance (mass, width of K0*(1430)); it replaces K0*(800) and K0*(1430).
+LASS = Resonance("LASS", KSTAR, 0, +1, 1.425, 0.270, shape=1)
 
 
 def model(name: str) -> list[Resonance]:
@@ -78,6 +84,9 @@ def model(name: str) -> list[Resonance]:
         return list(KSTARS) + [Z4430]
     if name == "full2z":
         return list(KSTARS) + [Z4430, Z4240]
+    if name in ("kstar_lass", "lass_full2z"):
+        ks = [LASS] + [r for r in KSTARS if r.name not in ("K0*(800)", "K0*(1430)")]
+        return ks if name == "kstar_lass" else ks + [Z4430, Z4240]
     raise KeyError(name)
 
 

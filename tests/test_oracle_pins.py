@@ -759,3 +759,34 @@ def test_mixture_gradient_matches_central_differences():
         fd = (O.nll_mix(K, res, pp, data, mc, b_d, b_m, 0.85, eps_d, eps_m)[1]
               - O.nll_mix(K, res, pm, data, mc, b_d, b_m, 0.85, eps_d, eps_m)[1]) / (2 * h)
         assert g[5 * k] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(g).max())
+
+
+# ---------------------------------------------------------------- LASS S-wave, Eq. (7)-(8)
+@pytest.mark.parametrize("m", [0.70, 0.95, 1.30, 1.42, 1.60, 2.10])
+def test_lass_amplitude_is_the_unitary_sum_of_the_two_phases(m):
+    # (q/m) A / (F_B (p_B/M_B)) = sin dB e^{i dB} + e^{2 i dB} sin dR e^{i dR} = sin d e^{i d},
+    # d = dB + dR, with cot dB = 1/(a q) + b q/2 and tan dR = M G(m) / (M^2 - m^2),
+    # G(m) = G0 (q/q0)(M/m).  The printed extra factor 2 on the resonant term breaks this.
+    r = W.LASS
+    M, G0 = r.mass, r.width
+    A = O.lineshape(K, r, M, G0, m)
+    q, q0 = O.breakup(m, K["mK"], K["mPi"]), O.breakup(M, K["mK"], K["mPi"])
+    pB, pB0 = O.breakup(K["mB"], K["mJ"], m), O.breakup(K["mB"], K["mJ"], M)
+    pre = O.barrier(1, pB, pB0, K["rB"]) * pB / K["mB"]
+    T = A * q / (m * pre)
+    dB = math.atan2(1.0, 1.0 / (r.lass_a * q) + 0.5 * r.lass_b * q)
+    dR = math.atan2(M * G0 * (q / q0) * (M / m), M * M - m * m)
+    d = dB + dR
+    assert abs(T - math.sin(d) * complex(math.cos(d), math.sin(d))) < 1e-13
+    assert abs(T) <= 1.0 + 1e-14
+
+
+def test_lass_without_effective_range_phase_is_the_scaled_scalar_resonance():
+    # a -> 0: cot dB -> infinity, dB -> 0, so A -> (M^2 G0 / q0) x the spin-0 Breit-Wigner of Eq. 2
+    import dataclasses
+    r = dataclasses.replace(W.LASS, lass_a=1e-12)
+    bw = dataclasses.replace(W.LASS, shape=0)
+    M, G0 = r.mass, r.width
+    q0 = O.breakup(M, K["mK"], K["mPi"])
+    for m in (0.8, 1.2, 1.425, 1.9):
+        assert O.lineshape(K, r, M, G0, m) == pytest.approx(M * M * G0 / q0 * O.lineshape(K, bw, M, G0, m), rel=1e-10)
