@@ -75,6 +75,13 @@ typedef struct {
                     allowed value (text below Eq. 3), the only values supported */
   double mass;   /* nominal M (used only as the default entry of the parameter vector) */
   double width;  /* nominal Gamma0 (idem) */
+  int shape;     /* 0: relativistic Breit-Wigner of Eq. 2-3.  1: LASS S-wave of Eq. 7-8 (K* of
+                    spin 0 only; its M and Gamma0 cannot float), read as
+                      A = F_B (p_B/M_B)^L_B [ (m/q) sin d e^{i d}
+                                              + e^{2 i d} (M^2 Gamma0/q0) / (M^2 - m^2 - i M Gamma(m)) ]
+                    with cot d = 1/(a q) + b q/2 and Gamma(m) = Gamma0 (q/q0)(M/m) */
+  double lass_a; /* LASS scattering length a in GeV^-1 (> 0); ignored when shape = 0 */
+  double lass_b; /* LASS effective range b in GeV^-1 (finite); ignored when shape = 0 */
 } kpsi_resonance;
 
 typedef struct {

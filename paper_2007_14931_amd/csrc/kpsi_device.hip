@@ -346,7 +346,23 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
               const T dim = -rc.P * gJ;
               const T inv = rcp_(fma_(dre, dre, dim * dim));
               const T sc = rc.K * nJ * inv;
-              const T Ar = sc * dre, Ai = -sc * dim;
+              const T br = sc * dre, bi = -sc * dim;
+              T Ar = br, Ai = bi;
+              if constexpr (J == 0) {
+                if (rc.lass) {
+                  // LASS (Eq. 7-8): with u = q cot(delta_B) = 1/a + b q^2/2 (finite at threshold),
+                  // (m/q) sin(delta_B) e^{i delta_B} = m (u + i q)/(u^2 + q^2) and
+                  // e^{2 i delta_B} = (u + i q)^2/(u^2 + q^2); the resonant term is the
+                  // Breit-Wigner above times P = M^2 Gamma0/q0 and e^{2 i delta_B}
+                  const T u = fma_(rc.lhb, qq, rc.lai);
+                  const T dn = rcp_(fma_(u, u, qq));
+                  const T er = (u * u - qq) * dn, ei = T(2) * u * q * dn;
+                  const T pre = rc.K * nJ;
+                  const T md = m * dn * pre;
+                  Ar = fma_(md, u, rc.P * (er * br - ei * bi));
+                  Ai = fma_(md, q, rc.P * (er * bi + ei * br));
+                }
+              }
               Amp[sb + j] = Cx<T>{Ar, Ai};
               if constexpr (J == 0) {
                 cmac(Tl[0][1], rc.hr[1], rc.hi[1], Ar, Ai);

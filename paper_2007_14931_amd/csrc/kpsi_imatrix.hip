@@ -142,7 +142,20 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
             const T dre = rc.M2 - m2, dim = -rc.P * gJ;
             const T inv = rcp_(dre * dre + dim * dim);
             const T sc = rc.K * nJ * inv;
-            const T Ar = sc * dre, Ai = -sc * dim;
+            const T br = sc * dre, bi = -sc * dim;
+            T Ar = br, Ai = bi;
+            if constexpr (J == 0) {
+              if (rc.lass) {
+                // LASS (Eq. 7-8): u = q cot(delta_B) = 1/a + b q^2/2; the non-resonant term is
+                // m (u + i q)/(u^2 + q^2), the resonant one P e^{2 i delta_B} times the Breit-Wigner
+                const T u = rc.lhb * qq + rc.lai;
+                const T dn = rcp_(u * u + qq);
+                const T er = (u * u - qq) * dn, ei = T(2) * u * q * dn;
+                const T md = m * dn * (rc.K * nJ);
+                Ar = md * u + rc.P * (er * br - ei * bi);
+                Ai = md * q + rc.P * (er * bi + ei * br);
+              }
+            }
             const int c0 = comp_base<Sh>(J) + (J == 0 ? j : 3 * j);
             // derivative factors: dA/dM = A (kappa - Y), dA/dGamma0 = A i (P/Gamma0) g conj(den)/|den|^2
             T dMr = 0, dMi = 0, dGr = 0, dGi = 0;

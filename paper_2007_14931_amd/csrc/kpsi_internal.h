@@ -22,6 +22,8 @@ template <typename T> struct RC {
   T hr[3], hi[3];     // K*: lambda = -1, 0, +1; Z: [0] lambda' = 0, [1] lambda' = +-1
   T kap, twoM, dP, PoG;   // d ln K/dM, 2M, dP/dM, P/Gamma0
   int flt;            // floating slot or -1
+  int lass;           // 1: LASS S-wave (spin-0 K* only), 0: Breit-Wigner
+  T lai, lhb;         // LASS 1/a and b/2: q cot(delta_B) = lai + lhb q^2
 };
 
 // Compile-time capacity of a kernel instantiation: K* slots per spin 0..4 and Z slots.

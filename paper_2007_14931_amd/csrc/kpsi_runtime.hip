@@ -179,6 +179,8 @@ template <typename T> void fill_rc(RC<T>& rc, const LsConst& c, const double* hr
   for (int l = 0; l < 3; ++l) { rc.hr[l] = (T)(l < nl ? hr[l] : 0.0); rc.hi[l] = (T)(l < nl ? hi[l] : 0.0); }
   rc.kap = (T)c.kap; rc.twoM = (T)c.twoM; rc.dP = (T)c.dP; rc.PoG = (T)c.PoG;
   rc.flt = flt;
+  rc.lass = 0;
+  rc.lai = rc.lhb = T(0);
 }
 
 // Pack the canonical parameter vector into kernel arguments.
@@ -200,6 +202,12 @@ template <typename T, class Sh> void pack(const kpsi_ctx* c, const double* par, 
       }
       nl = 3;
       fill_rc(a.ks[c->slot[i]], lc, hr, hi, nl, c->fslot[i]);
+      if (r.shape == 1) {
+        RC<T>& rc = a.ks[c->slot[i]];
+        rc.lass = 1;
+        rc.lai = (T)(1.0 / r.lass_a);
+        rc.lhb = (T)(0.5 * r.lass_b);
+      }
     } else {
       for (int l = 0; l < 2; ++l) { hr[l] = p[2 * l] * std::cos(p[2 * l + 1]); hi[l] = p[2 * l] * std::sin(p[2 * l + 1]); }
       nl = 2;
@@ -765,6 +773,14 @@ kpsi_status kpsi_set_model(kpsi_ctx* c, const kpsi_kinematics* kin, const kpsi_r
     }
     if ((r.lb >= 0 && r.lb != lowest_lb(r)) || (r.lr >= 0 && r.lr != lowest_lr(r)))
       return fail(c, KPSI_E_UNSUPPORTED, "resonance %d: only the lowest orbital momenta are supported", i);
+    if (r.shape == 1) {
+      if (r.chain != 0 || r.spin != 0)
+        return fail(c, KPSI_E_UNSUPPORTED, "resonance %d: the LASS lineshape is defined for spin-0 K* only", i);
+      if (!(r.lass_a > 0) || !std::isfinite(r.lass_a) || !std::isfinite(r.lass_b))
+        return fail(c, KPSI_E_ARG, "resonance %d: LASS needs a > 0 and a finite b", i);
+    } else if (r.shape != 0) {
+      return fail(c, KPSI_E_ARG, "resonance %d: shape must be 0 (Breit-Wigner) or 1 (LASS)", i);
+    }
   }
   int shape = -1;
   const int small[5] = {0, 1, 0, 0, 0}, full[5] = {3, 3, 2, 1, 1};
@@ -825,6 +841,8 @@ kpsi_status kpsi_set_floating(kpsi_ctx* c, const int* flags, int n_res) {
   for (int i = 0; i < n_res; ++i) {
     if (flags && flags[i]) {
       if (k >= NFL) return fail(c, KPSI_E_UNSUPPORTED, "at most %d floating lineshapes", NFL);
+      if (c->res[i].shape == 1)
+        return fail(c, KPSI_E_UNSUPPORTED, "resonance %d: a LASS lineshape cannot float", i);
       fs[i] = k++;
     }
   }

@@ -46,7 +46,8 @@ class Kinematics(C.Structure):
 
 class Resonance(C.Structure):
     _fields_ = [("chain", C.c_int), ("spin", C.c_int), ("parity", C.c_int), ("lb", C.c_int), ("lr", C.c_int),
-                ("mass", C.c_double), ("width", C.c_double)]
+                ("mass", C.c_double), ("width", C.c_double), ("shape", C.c_int), ("lass_a", C.c_double),
+                ("lass_b", C.c_double)]
 
 
 class FitOptions(C.Structure):
@@ -156,7 +157,7 @@ def kinematics(d: dict) -> Kinematics:
 def resonances(res) -> C.Array:
     arr = (Resonance * len(res))()
     for i, r in enumerate(res):
-        arr[i] = Resonance(r.chain, r.spin, r.parity, r.lb, r.lr, r.mass, r.width)
+        arr[i] = Resonance(r.chain, r.spin, r.parity, r.lb, r.lr, r.mass, r.width, r.shape, r.lass_a, r.lass_b)
     return arr
 
 
