@@ -169,6 +169,56 @@ def norm_cache_leg(eng, par, res, floating) -> dict:
             "cached_ms_per_step": ms, "cached_evals_per_s": 1e3 / ms, "builds": b2, "hits": hits}
 
 
+def extension_legs(stream, data, mc, par, res, floating, steps: int = 1000, warmup: int = 300) -> dict:
+    """Per-call NLL+gradient rate of the extensions at the benchmark sizes (same data and
+    normalisation events, FP32): the signal + background mixture of Eq. 14 with per-event
+    efficiency and background values, and the LASS S-wave model (LASS + 8 K* + two Z, the
+    K*(1410) and Z(4430) lineshapes floating)."""
+    import torch
+    from paper_2007_14931_amd import kpsi
+    from paper_2007_14931_amd import workloads as W
+    rng = np.random.default_rng(11)
+    nd, nm = data.shape[1], mc.shape[1]
+    eps_d, eps_m = rng.uniform(0.3, 0.9, nd), rng.uniform(0.3, 0.9, nm)
+    b_d, b_m = rng.uniform(0.2, 1.5, nd), rng.uniform(0.2, 1.5, nm)
+
+    def timed(e, p):
+        for _ in range(warmup):
+            e.nll_and_grad(p)
+        e.set_timing(TIMING_EVERY)
+        e.timing(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e.nll_and_grad(p)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        kms, kn = e.timing(reset=True)
+        return {"ms_per_step": ms, "evals_per_s": 1e3 / ms, "kernel_ms": kms / max(kn, 1)}
+
+    out = {}
+    e = kpsi.Engine(0, "fp32", stream)
+    e.set_model(W.KIN, res)
+    e.set_floating([1 if r.name in floating else 0 for r in res])
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    e.set_efficiency_values(eps_m)
+    e.set_background(0.85, eps_d, b_d, b_m)
+    out["mixture"] = {"model": "10 K* + Z(4430)", "purity": 0.85, **timed(e, par)}
+    e.close()
+    lres = W.model("lass_full2z")
+    lfl = ("K*(1410)", "Z(4430)")
+    lpar = W.params(lres, 31) + 0.05 * W.free_mask(lres, lfl)
+    e = kpsi.Engine(0, "fp32", stream)
+    e.set_model(W.KIN, lres)
+    e.set_floating([1 if r.name in lfl else 0 for r in lres])
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    out["lass"] = {"model": "LASS + 8 K* + Z(4430) + Z(4240)", **timed(e, lpar)}
+    e.close()
+    return out
+
+
 def W_free(res, floating):
     from paper_2007_14931_amd import workloads as W
     return W.free_mask(res, floating).astype(float)
@@ -314,6 +364,7 @@ def main() -> int:
                                                            else peaks["fp64_fma_tflops"])},
     }
     out["norm_cache"] = norm_cache_leg(eng, par, res, floating)
+    out["extensions"] = extension_legs(stream.cuda_stream, data, mc, par, res, floating)
     if not args.no_fit:
         out["fit"] = fit_comparison(make, truth, W.free_mask(res, floating), lambda p: W.canonical(res, p))
     if not args.no_cpu_baseline:

@@ -196,6 +196,12 @@ template <typename T> __device__ __forceinline__ void cmac(Cx<T>& acc, T ar, T a
   acc.im = fma_(ar, bi, fma_(ai, br, acc.im));
 }
 
+// (gr, gi) += A V: the per-event gradient contribution, fused into the accumulators
+template <typename T> __device__ __forceinline__ void cacc(T& gr, T& gi, const Cx<T>& A, const Cx<T>& V) {
+  gr = fma_(A.re, V.re, fma_(-A.im, V.im, gr));
+  gi = fma_(A.re, V.im, fma_(A.im, V.re, gi));
+}
+
 // Blatt-Weisskopf polynomial B_L(z) (Horner form)
 template <int L, typename T> __device__ __forceinline__ T bpoly(T z) {
   if constexpr (L == 0) return T(1);
@@ -504,19 +510,21 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
                 const auto& rc = ka.ks[sb + j];
                 Cx<T> Q{T(0), T(0)};
                 if constexpr (J == 0) {
-                  A_t* g = gk + ab + 2 * j;
-                  g[0] += (A_t)(A.re * V0.re - A.im * V0.im);
-                  g[1] += (A_t)(A.re * V0.im + A.im * V0.re);
+                  // accumulators += A V as two fused multiply-adds per component
+                  cacc(gk[ab + 2 * j], gk[ab + 2 * j + 1], A, V0);
                   if (rc.flt >= 0) cmac(Q, rc.hr[1], rc.hi[1], V0.re, V0.im);
                 } else if constexpr (LDSACC && J >= 1 && J <= 3) {
                   // ab + 6 j lies in [LO, HI): read-add-write this thread's own LDS slots (no other
                   // lane touches them, so no atomics)
                   lds_ptr<A_t> g = accb + 256 * (ab + 6 * j - LO);
-                  const A_t v[6] = {(A_t)(A.re * Vm.re - A.im * Vm.im), (A_t)(A.re * Vm.im + A.im * Vm.re),
-                                    (A_t)(A.re * V0.re - A.im * V0.im), (A_t)(A.re * V0.im + A.im * V0.re),
-                                    (A_t)(A.re * Vp.re - A.im * Vp.im), (A_t)(A.re * Vp.im + A.im * Vp.re)};
+                  A_t v[6];
 #pragma unroll
-                  for (int q = 0; q < 6; ++q) g[256 * q] += v[q];
+                  for (int q = 0; q < 6; ++q) v[q] = g[256 * q];
+                  cacc(v[0], v[1], A, Vm);
+                  cacc(v[2], v[3], A, V0);
+                  cacc(v[4], v[5], A, Vp);
+#pragma unroll
+                  for (int q = 0; q < 6; ++q) g[256 * q] = v[q];
                   if (rc.flt >= 0) {
                     cmac(Q, rc.hr[0], rc.hi[0], Vm.re, Vm.im);
                     cmac(Q, rc.hr[1], rc.hi[1], V0.re, V0.im);
@@ -524,12 +532,9 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
                   }
                 } else {
                   A_t* g = gk + ab + 6 * j;
-                  g[0] += (A_t)(A.re * Vm.re - A.im * Vm.im);
-                  g[1] += (A_t)(A.re * Vm.im + A.im * Vm.re);
-                  g[2] += (A_t)(A.re * V0.re - A.im * V0.im);
-                  g[3] += (A_t)(A.re * V0.im + A.im * V0.re);
-                  g[4] += (A_t)(A.re * Vp.re - A.im * Vp.im);
-                  g[5] += (A_t)(A.re * Vp.im + A.im * Vp.re);
+                  cacc(g[0], g[1], A, Vm);
+                  cacc(g[2], g[3], A, V0);
+                  cacc(g[4], g[5], A, Vp);
                   if (rc.flt >= 0) {
                     cmac(Q, rc.hr[0], rc.hi[0], Vm.re, Vm.im);
                     cmac(Q, rc.hr[1], rc.hi[1], V0.re, V0.im);
@@ -580,10 +585,8 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
             if (z < a.cnt[5]) {
               const Cx<T> A = AZ[z];
               A_t* g = gz + 4 * z;
-              g[0] += (A_t)(A.re * WZ0.re - A.im * WZ0.im);
-              g[1] += (A_t)(A.re * WZ0.im + A.im * WZ0.re);
-              g[2] += (A_t)(A.re * WZ1.re - A.im * WZ1.im);
-              g[3] += (A_t)(A.re * WZ1.im + A.im * WZ1.re);
+              cacc(g[0], g[1], A, WZ0);
+              cacc(g[2], g[3], A, WZ1);
               const auto& rc = ka.zs[z];
               if (rc.flt >= 0) {
                 Cx<T> Q{T(0), T(0)};

@@ -265,68 +265,75 @@ def pulls(args) -> dict:
 def z_sensitivity(args) -> dict:
     """Sensitivity to Z contributions (Results, sensitivity of the fitter to Z contributions):
     pseudo-data from the ten K* alone are fitted with the ten K* + Z(4430) + Z(4240) model (the
-    Z fit fractions should come out near zero), and, as a positive control, pseudo-data with
-    both Z at seeded couplings are fitted with the same model (the fitted Z fractions should
-    match the generated ones).  Fits: FP32 adjoint MIGRAD, then an FP64 adjoint polish with
-    HESSE; Z masses and widths fixed."""
+    Z fit fractions should come out near zero); the same null test with the LASS S-wave (Eq. 7-8)
+    in place of K0*(800) and K0*(1430) in both generation and fit; and, as a positive control,
+    pseudo-data with both Z at seeded couplings fitted with the same model (the fitted Z
+    fractions should match the generated ones).  Fits: FP32 adjoint MIGRAD, then an FP64 adjoint
+    polish with HESSE; Z masses and widths fixed."""
     import torch
-    res = W.model("full2z")
-    truth = W.params(res, 31)
-    iz = [i for i, r in enumerate(res) if r.chain == 1]
-    zoff = [W.coupling_offset(res, i) for i in iz]
-    null = truth.copy()
-    for o in zoff:
-        null[o] = 0.0
-        null[o + 2] = 0.0
     stream = torch.cuda.current_stream().cuda_stream
     n_data, n_mc = int(args.data_events), int(args.norm_events) if args.norm_events else 2_000_000
-    gen = kpsi.Engine(0, "fp64", stream)
-    gen.set_model(W.KIN, res)
-    mc = gen.generate_phsp(5201, n_mc, W.PHSP_WMAX)
-    scan = gen.generate_phsp(5202, 1_000_000, W.PHSP_WMAX)
-    gen.load(kpsi.DATA, scan)
-    gen.load(kpsi.NORM, mc)
-    # positive control at the few-percent Z fractions the paper quotes for its efficiency and
-    # background study (3.5% and 1.2%): scale each Z's couplings until its fraction matches
-    target = {res[iz[0]].name: 0.035, res[iz[1]].name: 0.012}
-    for _ in range(4):
-        ff, _ = gen.fit_fractions(truth)
-        for i, o in zip(iz, zoff):
-            f = math.sqrt(target[res[i].name] / ff[i])
-            truth[o] *= f
-            truth[o + 2] *= f
-    out = {"study": "z_sensitivity", "data_events": n_data, "norm_events": n_mc, "model": "10 K* + Z(4430) + Z(4240)"}
-    mask = W.free_mask(res)
-    for case, point in (("kstar_only_data", null), ("with_z_data", truth)):
-        smax = 1.5 * float(gen.density(kpsi.DATA, point).max())
-        data, _, _ = gen.generate_model(point, 5300 + len(out), n_data, W.PHSP_WMAX, smax)
-        ff_true, _ = gen.fit_fractions(point)
-        start = point.copy()
-        for o in zoff:   # Z couplings start small but non-zero
-            start[o] = max(start[o], 0.05)
-            start[o + 2] = max(start[o + 2], 0.05)
-        fits = {}
-        for prec in ("fp32", "fp64"):
-            e = kpsi.Engine(0, prec, stream)
-            e.set_model(W.KIN, res)
-            e.load(kpsi.DATA, data)
-            e.load(kpsi.NORM, mc)
-            x, cov, r = e.migrad(start, mask)
-            e.close()
-            fits[prec] = (x, r)
-            start = x
-        x, r = fits["fp64"]
-        ff, tot = gen.fit_fractions(x)
-        rec = {"fit_status": {p: fits[p][1].status for p in fits},
-               "fit_wall_s": {p: fits[p][1].wall_seconds for p in fits},
-               "ff_generated": {res[i].name: float(ff_true[i]) for i in iz},
-               "ff_fitted": {res[i].name: float(ff[i]) for i in iz},
-               "ff_sum_fitted": tot,
-               "kstar_ff_max_abs_diff": float(np.max(np.abs(np.delete(ff - ff_true, iz))))}
-        log(f"{case}: {rec}")
-        out[case] = rec
-        del data
-    gen.close()
+    out = {"study": "z_sensitivity", "data_events": n_data, "norm_events": n_mc}
+    plan = (("full2z", "10 K* + Z(4430) + Z(4240)", ("kstar_only_data", "with_z_data")),
+            ("lass_full2z", "LASS + 8 K* + Z(4430) + Z(4240)", ("lass_kstar_only_data",)))
+    for model, label, cases in plan:
+        res = W.model(model)
+        truth = W.params(res, 31)
+        iz = [i for i, r in enumerate(res) if r.chain == 1]
+        zoff = [W.coupling_offset(res, i) for i in iz]
+        null = truth.copy()
+        for o in zoff:
+            null[o] = 0.0
+            null[o + 2] = 0.0
+        gen = kpsi.Engine(0, "fp64", stream)
+        gen.set_model(W.KIN, res)
+        mc = gen.generate_phsp(5201, n_mc, W.PHSP_WMAX)
+        scan = gen.generate_phsp(5202, 1_000_000, W.PHSP_WMAX)
+        gen.load(kpsi.DATA, scan)
+        gen.load(kpsi.NORM, mc)
+        if "with_z_data" in cases:
+            # positive control at the few-percent Z fractions the paper quotes for its efficiency
+            # and background study (3.5% and 1.2%): scale each Z's couplings until its fraction matches
+            target = {res[iz[0]].name: 0.035, res[iz[1]].name: 0.012}
+            for _ in range(4):
+                ff, _ = gen.fit_fractions(truth)
+                for i, o in zip(iz, zoff):
+                    f = math.sqrt(target[res[i].name] / ff[i])
+                    truth[o] *= f
+                    truth[o + 2] *= f
+        mask = W.free_mask(res)
+        for case in cases:
+            point = truth if case == "with_z_data" else null
+            smax = 1.5 * float(gen.density(kpsi.DATA, point).max())
+            data, _, _ = gen.generate_model(point, 5300 + len(out), n_data, W.PHSP_WMAX, smax)
+            ff_true, _ = gen.fit_fractions(point)
+            start = point.copy()
+            for o in zoff:   # Z couplings start small but non-zero
+                start[o] = max(start[o], 0.05)
+                start[o + 2] = max(start[o + 2], 0.05)
+            fits = {}
+            for prec in ("fp32", "fp64"):
+                e = kpsi.Engine(0, prec, stream)
+                e.set_model(W.KIN, res)
+                e.load(kpsi.DATA, data)
+                e.load(kpsi.NORM, mc)
+                x, cov, r = e.migrad(start, mask)
+                e.close()
+                fits[prec] = (x, r)
+                start = x
+            x, r = fits["fp64"]
+            ff, tot = gen.fit_fractions(x)
+            rec = {"model": label,
+                   "fit_status": {p: fits[p][1].status for p in fits},
+                   "fit_wall_s": {p: fits[p][1].wall_seconds for p in fits},
+                   "ff_generated": {res[i].name: float(ff_true[i]) for i in iz},
+                   "ff_fitted": {res[i].name: float(ff[i]) for i in iz},
+                   "ff_sum_fitted": tot,
+                   "kstar_ff_max_abs_diff": float(np.max(np.abs(np.delete(ff - ff_true, iz))))}
+            log(f"{case}: {rec}")
+            out[case] = rec
+            del data
+        gen.close()
     return out
 
 
