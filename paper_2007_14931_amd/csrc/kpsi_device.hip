@@ -66,7 +66,8 @@ template <typename P> __device__ __forceinline__ kconst_ptr<P> kernarg_laundered
 //   K* chain  : m, q(m), p_B(m), cos/sin theta_K*, cos/sin theta_J/psi, cos/sin phi
 //   Z chain   : m^2_Jpsi pi, nZ = (p_B/M_B) / sqrt(1 + (r_B p_B)^2), gZ = q/m_Jpsi pi,
 //               and the four complex angular factors Zang[l'][xi] of Eq. (10)
-//               (l' = 0 and l' = +-1 combined through Eq. 11, xi = +1, -1).
+//               (l' = 0 and l' = +-1 combined through Eq. 11, xi = +1, -1), each
+//               multiplied by nZ (the per-event factor common to every Z amplitude).
 // All arithmetic in double; stored in T.
 template <typename T>
 __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
@@ -168,11 +169,13 @@ __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
   const double pbz2 = (mB2 - (mz + mK) * (mz + mK)) * (mB2 - (mz - mK) * (mz - mK));
   const double pbz = pbz2 > 0.0 ? sqrt(pbz2) / (2.0 * mB) : 0.0;
   const double zb = a.rB * pbz * a.rB * pbz;
+  const double nZ = (pbz / mB) / sqrt(1.0 + zb);
   c[9 * ld + e] = (T)mz2;
-  c[10 * ld + e] = (T)((pbz / mB) / sqrt(1.0 + zb));
+  c[10 * ld + e] = (T)nZ;
   c[11 * ld + e] = (T)(qz / mz);
-  // Angular factors of Eq. (10): d^1_{0l'}(theta_Z) e^{i l' phi~} d^1_{l' xi}(theta~) e^{i xi alpha}
-  const double r2 = 0.7071067811865475244;
+  // Angular factors of Eq. (10): d^1_{0l'}(theta_Z) e^{i l' phi~} d^1_{l' xi}(theta~) e^{i xi alpha},
+  // times nZ
+  const double r2 = 0.7071067811865475244 * nZ;
   //  l' = 0:  xi = +1: cZ st/sqrt2 e^{i alpha};  xi = -1: -cZ st/sqrt2 e^{-i alpha}
   const double z0 = cZ * st * r2;
   c[12 * ld + e] = (T)(z0 * ca);
@@ -200,6 +203,25 @@ template <typename T> __device__ __forceinline__ void cmac(Cx<T>& acc, T ar, T a
 template <typename T> __device__ __forceinline__ void cacc(T& gr, T& gi, const Cx<T>& A, const Cx<T>& V) {
   gr = fma_(A.re, V.re, fma_(-A.im, V.im, gr));
   gi = fma_(A.re, V.im, fma_(A.im, V.re, gi));
+}
+
+// Lineshape-parameter derivatives of one floating resonance.  B = 1/(M^2 - m^2 - i P g) is its
+// bare Breit-Wigner and Q = sum_lambda H'_lambda V'_lambda its adjoint weight, so X = B Q is
+// the resonance's share of dS/dA times A.  With A = K n B (K and P depending on M, P also on
+// Gamma0 = P/PoG):
+//   dS/dM      = Re[X (kappa - (2M - i P' g) B)],   kappa = d ln K/dM, P' = dP/dM
+//   dS/dGamma0 = Re[X i PoG g B] = -PoG g Im[X B]
+// The floating slot index is uniform, so the branch on it is a scalar one.
+template <typename T, typename R>
+__device__ __forceinline__ void flt_deriv(const R& rc, const Cx<T>& B, const Cx<T>& Q, T g, T& gM0, T& gG0, T& gM1,
+                                          T& gG1) {
+  const T Xr = B.re * Q.re - B.im * Q.im, Xi = B.re * Q.im + B.im * Q.re;
+  const T pg = rc.dP * g;
+  const T Yr = fma_(rc.twoM, B.re, pg * B.im), Yi = fma_(rc.twoM, B.im, -pg * B.re);
+  const T dM = fma_(rc.kap, Xr, -fma_(Xr, Yr, -Xi * Yi));
+  const T dG = -rc.PoG * g * fma_(Xr, B.im, Xi * B.re);
+  if (rc.flt == 0) { gM0 += dM; gG0 += dG; }
+  else { gM1 += dM; gG1 += dG; }
 }
 
 // Blatt-Weisskopf polynomial B_L(z) (Horner form)
@@ -252,14 +274,17 @@ template <class Sh> __host__ __device__ constexpr int acc_base(int J) {   // acc
 //          (data: sum ln S; norm: sum eps S)
 //   2    : number of data events with S <= 0 or non-finite
 //   then per K* slot (spin order) 2 (spin 0) or 6 (lambda = -1, 0, +1) values re/im of
-//   sum w * dS/dH (before the factor 2), then per Z slot 4 values (lambda' = 0, +-1),
-//   then 2 per floating slot (d/dM, d/dGamma0).
+//   sum w * dS/dH' with H' = K H (before the factor 2), then per Z slot 4 values
+//   (lambda' = 0, +-1), then 2 per floating slot (d/dM, d/dGamma0).
 
 // The gradient kernel of the large shape asks for 4 (FP32) or 2 (FP64) wavefronts per SIMD, at
 // most 128 or 256 registers; its spin-1..3 accumulators live in LDS to make room (36 values x
 // 256 threads: 36 KB per block in FP32, 4 blocks per compute unit; 72 KB in FP64, 2 blocks).
+// The FP64 likelihood-only and density kernels of the large shape ask for 4 (128 registers).
 template <typename T, class Sh, int MODE> struct AmpWaves {
-  static constexpr int v = (MODE == MODE_GRAD && Sh::LDS_HI > Sh::LDS_LO) ? (std::is_same<T, float>::value ? 4 : 2) : 1;
+  static constexpr bool lds = MODE == MODE_GRAD && Sh::LDS_HI > Sh::LDS_LO;
+  static constexpr bool f32 = std::is_same<T, float>::value;
+  static constexpr int v = lds ? (f32 ? 4 : 2) : (!f32 && Sh::NK > 1 ? 4 : 1);
 };
 template <typename T, class Sh, int MODE>
 __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(const AmpArgs<T, Sh> a) {
@@ -325,8 +350,13 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     const T qq = q * q;
 
     // ---- K* lineshapes (Eq. 2-3) and coupling sums T_{J lambda}
+    // Each resonance's amplitude is K n_J(m) B_R(m) with B_R = 1/(M^2 - m^2 - i P g_J(m)) the
+    // bare Breit-Wigner, K the per-resonance constant and n_J the per-spin barrier and momentum
+    // factor.  K is folded into the couplings on the host (H' = K H) and n_J into the angular
+    // factors of its spin, so each resonance costs one complex reciprocal: Amp holds B_R.
     Cx<T> Amp[NK > 0 ? NK : 1];
     T gJv[5] = {T(0), T(0), T(0), T(0), T(0)};   // g_J(m) per spin (width derivative)
+    T nJv[5] = {T(0), T(0), T(0), T(0), T(0)};   // n_J(m) per spin
     Cx<T> Tl[5][3];
 #pragma unroll
     for (int J = 0; J < 5; ++J)
@@ -343,16 +373,16 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
           const T nJ = ipow<T, LB>(pbm) * ipow<T, J>(qm) * rJ;
           const T gJ = qm * ipow<T, J>(qq) * rcp_(BR);
           gJv[J] = gJ;
+          nJv[J] = nJ;
           constexpr int sb = slot_base<Sh>(J);
 #pragma unroll
           for (int j = 0; j < Sh::N[J]; ++j) {
             if (j < a.cnt[J]) {
               const auto& rc = ka.ks[sb + j];
               const T dre = rc.M2 - m2;
-              const T dim = -rc.P * gJ;
+              const T dim = rc.P * gJ;   // M Gamma(m)
               const T inv = rcp_(fma_(dre, dre, dim * dim));
-              const T sc = rc.K * nJ * inv;
-              const T br = sc * dre, bi = -sc * dim;
+              const T br = dre * inv, bi = dim * inv;
               T Ar = br, Ai = bi;
               if constexpr (J == 0) {
                 if (rc.lass) {
@@ -363,8 +393,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
                   const T u = fma_(rc.lhb, qq, rc.lai);
                   const T dn = rcp_(fma_(u, u, qq));
                   const T er = (u * u - qq) * dn, ei = T(2) * u * q * dn;
-                  const T pre = rc.K * nJ;
-                  const T md = m * dn * pre;
+                  const T md = m * dn;
                   Ar = fma_(md, u, rc.P * (er * br - ei * bi));
                   Ai = fma_(md, q, rc.P * (er * bi + ei * br));
                 }
@@ -388,12 +417,13 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     do_spin(std::integral_constant<int, 4>{});
 
     // ---- angular sums (Eq. 4): U_lambda = sum_J d^J_{lambda 0}(theta_K) T_{J lambda}
+    // (n_J times the d functions; the n_J of spins absent from the model are zero)
     T dd0[5], dd1[5];
-    dd0[0] = T(1); dd1[0] = T(0);
-    dd0[1] = d00<1>(cK); dd1[1] = d10<1>(cK, sK);
-    dd0[2] = d00<2>(cK); dd1[2] = d10<2>(cK, sK);
-    dd0[3] = d00<3>(cK); dd1[3] = d10<3>(cK, sK);
-    dd0[4] = d00<4>(cK); dd1[4] = d10<4>(cK, sK);
+    dd0[0] = nJv[0]; dd1[0] = T(0);
+    dd0[1] = nJv[1] * d00<1>(cK); dd1[1] = nJv[1] * d10<1>(cK, sK);
+    dd0[2] = nJv[2] * d00<2>(cK); dd1[2] = nJv[2] * d10<2>(cK, sK);
+    dd0[3] = nJv[3] * d00<3>(cK); dd1[3] = nJv[3] * d10<3>(cK, sK);
+    dd0[4] = nJv[4] * d00<4>(cK); dd1[4] = nJv[4] * d10<4>(cK, sK);
     Cx<T> U0{T(0), T(0)}, Up{T(0), T(0)}, Um{T(0), T(0)};
 #pragma unroll
     for (int J = 0; J < 5; ++J) {
@@ -416,12 +446,13 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     Cx<T> am{hm * eUp.re - s0 * U0.re + hp * eUm.re, hm * eUp.im - s0 * U0.im + hp * eUm.im};
 
     // ---- Z chain (Eq. 10-12)
+    // (AZ holds the bare Breit-Wigner; the Z barrier factor n_Z is in the angular columns)
     Cx<T> AZ[NZ > 0 ? NZ : 1];
     T za[8];
-    T gzv = T(0), dzr[NZ > 0 ? NZ : 1], dzi[NZ > 0 ? NZ : 1], zinv[NZ > 0 ? NZ : 1];
+    T gzv = T(0);
     if constexpr (NZ > 0) {
       if (a.cnt[5] > 0) {
-        const T mz2 = ldoff(cb + 9 * ld, ob), nz = ldoff(cb + 10 * ld, ob);
+        const T mz2 = ldoff(cb + 9 * ld, ob);
         gzv = ldoff(cb + 11 * ld, ob);
 #pragma unroll
         for (int k = 0; k < 8; ++k) za[k] = ldoff(cb + (12 + k) * ld, ob);
@@ -431,11 +462,9 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
           if (z < a.cnt[5]) {
             const auto& rc = ka.zs[z];
             const T dre = rc.M2 - mz2;
-            const T dim = -rc.P * gzv;
+            const T dim = rc.P * gzv;
             const T inv = rcp_(fma_(dre, dre, dim * dim));
-            const T sc = rc.K * nz * inv;
-            AZ[z] = Cx<T>{sc * dre, -sc * dim};
-            dzr[z] = dre; dzi[z] = dim; zinv[z] = inv;
+            AZ[z] = Cx<T>{dre * inv, dim * inv};
             cmac(T0, rc.hr[0], rc.hi[0], AZ[z].re, AZ[z].im);
             cmac(T1, rc.hr[1], rc.hi[1], AZ[z].re, AZ[z].im);
           }
@@ -541,27 +570,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
                     cmac(Q, rc.hr[2], rc.hi[2], Vp.re, Vp.im);
                   }
                 }
-                if (rc.flt >= 0) {
-                  // X = A Q;  d/dM: Re[X (kappa - (2M - i P' g) conj(den)/|den|^2)]
-                  //           d/dGamma0: Re[X i (P/Gamma0) g conj(den)/|den|^2]
-                  const T Xr = A.re * Q.re - A.im * Q.im, Xi = A.re * Q.im + A.im * Q.re;
-                  const T g_ = gJv[J];
-                  const T dre = rc.M2 - m2, dim = -rc.P * g_;
-                  const T inv = rcp_(fma_(dre, dre, dim * dim));
-                  // Y = (2M - i P' g)(dre - i dim) inv
-                  const T pr = rc.twoM, pim = -rc.dP * g_;
-                  const T Yr = (pr * dre + pim * dim) * inv;
-                  const T Yi = (pim * dre - pr * dim) * inv;
-                  const T dM = rc.kap * Xr - (Xr * Yr - Xi * Yi);
-                  const T zf = rc.PoG * g_ * inv;
-                  const T dG = zf * (Xr * dim - Xi * dre);
-                  // uniform selects into named registers (no indexed private array)
-                  const bool f0 = rc.flt == 0;
-                  gM0 += f0 ? (A_t)dM : A_t(0);
-                  gG0 += f0 ? (A_t)dG : A_t(0);
-                  gM1 += f0 ? A_t(0) : (A_t)dM;
-                  gG1 += f0 ? A_t(0) : (A_t)dG;
-                }
+                if (rc.flt >= 0) flt_deriv(rc, A, Q, gJv[J], gM0, gG0, gM1, gG1);
               }
             }
           }
@@ -592,19 +601,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
                 Cx<T> Q{T(0), T(0)};
                 cmac(Q, rc.hr[0], rc.hi[0], WZ0.re, WZ0.im);
                 cmac(Q, rc.hr[1], rc.hi[1], WZ1.re, WZ1.im);
-                const T Xr = A.re * Q.re - A.im * Q.im, Xi = A.re * Q.im + A.im * Q.re;
-                const T dre = dzr[z], dim = dzi[z], inv = zinv[z];
-                const T pr = rc.twoM, pim = -rc.dP * gzv;
-                const T Yr = (pr * dre + pim * dim) * inv;
-                const T Yi = (pim * dre - pr * dim) * inv;
-                const T dM = rc.kap * Xr - (Xr * Yr - Xi * Yi);
-                const T zf = rc.PoG * gzv * inv;
-                const T dG = zf * (Xr * dim - Xi * dre);
-                const bool f0 = rc.flt == 0;
-                gM0 += f0 ? (A_t)dM : A_t(0);
-                gG0 += f0 ? (A_t)dG : A_t(0);
-                gM1 += f0 ? A_t(0) : (A_t)dM;
-                gG1 += f0 ? A_t(0) : (A_t)dG;
+                flt_deriv(rc, A, Q, gzv, gM0, gG0, gM1, gG1);
               }
             }
           }

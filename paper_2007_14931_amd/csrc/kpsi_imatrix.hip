@@ -205,7 +205,8 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
       do_spin(std::integral_constant<int, 4>{});
       if constexpr (NZ > 0) {
         if (a.cnt[5] > 0) {
-          const T mz2 = col[9 * ld + e], nz = col[10 * ld + e], gz = col[11 * ld + e];
+          // (the angular columns za carry the Z barrier factor n_Z)
+          const T mz2 = col[9 * ld + e], gz = col[11 * ld + e];
           T za[8];
 #pragma unroll
           for (int i = 0; i < 8; ++i) za[i] = col[(12 + i) * ld + e];
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
             const auto& rc = a.zs[z];
             const T dre = rc.M2 - mz2, dim = -rc.P * gz;
             const T inv = rcp_(dre * dre + dim * dim);
-            const T sc = rc.K * nz * inv;
+            const T sc = rc.K * inv;
             const T Ar = sc * dre, Ai = -sc * dim;
             put(zc0 + 2 * z, Ar, Ai, za[0], za[1], za[2], za[3]);
             put(zc0 + 2 * z + 1, Ar, Ai, za[4], za[5], za[6], za[7]);

@@ -174,9 +174,15 @@ LsConst lineshape_consts(const kpsi_kinematics& k, const kpsi_resonance& r, doub
   return c;
 }
 
+// The couplings are stored multiplied by the resonance constant K (H' = K H): the per-event
+// kernel evaluates the bare Breit-Wigner and leaves K to the couplings, so its coupling
+// accumulators come out divided by K (undone in kpsi_nll_and_grad).
 template <typename T> void fill_rc(RC<T>& rc, const LsConst& c, const double* hr, const double* hi, int nl, int flt) {
   rc.M2 = (T)c.M2; rc.P = (T)c.P; rc.K = (T)c.K;
-  for (int l = 0; l < 3; ++l) { rc.hr[l] = (T)(l < nl ? hr[l] : 0.0); rc.hi[l] = (T)(l < nl ? hi[l] : 0.0); }
+  for (int l = 0; l < 3; ++l) {
+    rc.hr[l] = (T)(l < nl ? c.K * hr[l] : 0.0);
+    rc.hi[l] = (T)(l < nl ? c.K * hi[l] : 0.0);
+  }
   rc.kap = (T)c.kap; rc.twoM = (T)c.twoM; rc.dP = (T)c.dP; rc.PoG = (T)c.PoG;
   rc.flt = flt;
   rc.lass = 0;
@@ -1142,11 +1148,15 @@ kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, do
     const int ao = acc_offset(c, i, N);
     const int nl = ncoup(r);
     const double* p = params + c->coff[i];
+    // the kernel's coupling accumulators are d/dH' with H' = K H: multiply by K (the
+    // interference-matrix record is already in terms of H)
+    const double kr = lineshape_consts(c->kin, r, params[ncr + 2 * i], params[ncr + 2 * i + 1]).K;
+    const double km = cached ? 1.0 : kr;
     for (int l = 0; l < nl; ++l) {
       // K* spin >= 1 accumulators are lambda = -1, 0, +1; spin 0 has lambda = 0 only; Z has 0, +-1
       const int a = ao + 2 * l;
-      const double gr = -2.0 * rd[a] + fm * rm[a];
-      const double gi = -2.0 * rd[a + 1] + fm * rm[a + 1];
+      const double gr = -2.0 * kr * rd[a] + fm * km * rm[a];
+      const double gi = -2.0 * kr * rd[a + 1] + fm * km * rm[a + 1];
       const double mag = p[2 * l], ph = p[2 * l + 1];
       const double cph = std::cos(ph), sph = std::sin(ph);
       grad[c->coff[i] + 2 * l] = 2.0 * (cph * gr - sph * gi);
