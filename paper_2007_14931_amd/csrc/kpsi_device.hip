@@ -363,10 +363,13 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
 #pragma unroll
       for (int l = 0; l < 3; ++l) Tl[J][l] = Cx<T>{T(0), T(0)};
 
+    // Every K* slot of the shape is evaluated: the host gives the slots the model leaves empty
+    // zero couplings and the constants M^2 = P = 0 (a finite 1/D = -1/m^2), so they add nothing
+    // and need no per-event test (the Z slots keep theirs: models often use one of the two).
     auto do_spin = [&](auto Jc) {
       constexpr int J = decltype(Jc)::value;
       if constexpr (Sh::N[J] > 0) {
-        if (a.cnt[J] > 0) {
+        {
           constexpr int LB = LBof<J>::v;
           const T BR = bpoly<J>(zR), BB = bpoly<LB>(zB);
           const T rJ = rsq_(BR * BB);
@@ -377,7 +380,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
           constexpr int sb = slot_base<Sh>(J);
 #pragma unroll
           for (int j = 0; j < Sh::N[J]; ++j) {
-            if (j < a.cnt[J]) {
+            {
               const auto& rc = ka.ks[sb + j];
               const T dre = rc.M2 - m2;
               const T dim = rc.P * gJ;   // M Gamma(m)
@@ -525,7 +528,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
       auto grad_spin = [&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
         if constexpr (Sh::N[J] > 0) {
-          if (a.cnt[J] > 0) {
+          {
             constexpr int sb = slot_base<Sh>(J);
             constexpr int ab = acc_base<Sh>(J) - 3;
             // V_{J lambda} = d^J_{lambda 0} W_lambda
@@ -534,7 +537,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
             const Cx<T> Vm{-dd1[J] * Wm.re, -dd1[J] * Wm.im};
 #pragma unroll
             for (int j = 0; j < Sh::N[J]; ++j) {
-              if (j < a.cnt[J]) {
+              {
                 const Cx<T> A = Amp[sb + j];
                 const auto& rc = ka.ks[sb + j];
                 Cx<T> Q{T(0), T(0)};

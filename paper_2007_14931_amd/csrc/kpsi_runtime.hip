@@ -192,6 +192,12 @@ template <typename T> void fill_rc(RC<T>& rc, const LsConst& c, const double* hr
 // Pack the canonical parameter vector into kernel arguments.
 template <typename T, class Sh> void pack(const kpsi_ctx* c, const double* par, AmpArgs<T, Sh>& a) {
   const int ncr = c->nparams - 2 * (int)c->res.size();
+  // K* slots the model leaves empty are still evaluated by the kernel: zero couplings, M^2 = P = 0
+  // (a finite Breit-Wigner), not floating
+  for (int k = 0; k < Sh::NK; ++k) {
+    a.ks[k] = RC<T>{};
+    a.ks[k].flt = -1;
+  }
   for (size_t i = 0; i < c->res.size(); ++i) {
     const kpsi_resonance& r = c->res[i];
     const double M = par[ncr + 2 * i], G = par[ncr + 2 * i + 1];
