@@ -62,7 +62,7 @@ template <typename P> __device__ __forceinline__ kconst_ptr<P> kernarg_laundered
 }
 
 // ------------------------------------------------------------------ invariants
-// Columns written per event (type T, stride ld):
+// Columns written per event (type T, in groups of four at col_at(k, e, ld)):
 //   K* chain  : m, q(m), p_B(m), cos/sin theta_K*, cos/sin theta_J/psi, cos/sin phi
 //   Z chain   : m^2_Jpsi pi, nZ = (p_B/M_B) / sqrt(1 + (r_B p_B)^2), gZ = q/m_Jpsi pi,
 //               and the four complex angular factors Zang[l'][xi] of Eq. (10)
@@ -91,15 +91,15 @@ __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
   sincos(ph, &sph, &cph);
   T* c = a.cols;
   const int64_t ld = a.ld;
-  c[0 * ld + e] = (T)m;
-  c[1 * ld + e] = (T)q;
-  c[2 * ld + e] = (T)pB;
-  c[3 * ld + e] = (T)cK;
-  c[4 * ld + e] = (T)sK;
-  c[5 * ld + e] = (T)cJ;
-  c[6 * ld + e] = (T)sJ;
-  c[7 * ld + e] = (T)cph;
-  c[8 * ld + e] = (T)sph;
+  c[col_at(0, e, ld)] = (T)m;
+  c[col_at(1, e, ld)] = (T)q;
+  c[col_at(2, e, ld)] = (T)pB;
+  c[col_at(3, e, ld)] = (T)cK;
+  c[col_at(4, e, ld)] = (T)sK;
+  c[col_at(5, e, ld)] = (T)cJ;
+  c[col_at(6, e, ld)] = (T)sJ;
+  c[col_at(7, e, ld)] = (T)cph;
+  c[col_at(8, e, ld)] = (T)sph;
   if (!a.with_z && !a.diag) return;
 
   // J/psi rest frame, reached by a boost along z from the B frame, in which the K pi
@@ -170,26 +170,26 @@ __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
   const double pbz = pbz2 > 0.0 ? sqrt(pbz2) / (2.0 * mB) : 0.0;
   const double zb = a.rB * pbz * a.rB * pbz;
   const double nZ = (pbz / mB) / sqrt(1.0 + zb);
-  c[9 * ld + e] = (T)mz2;
-  c[10 * ld + e] = (T)nZ;
-  c[11 * ld + e] = (T)(qz / mz);
+  c[col_at(9, e, ld)] = (T)mz2;
+  c[col_at(10, e, ld)] = (T)nZ;
+  c[col_at(11, e, ld)] = (T)(qz / mz);
   // Angular factors of Eq. (10): d^1_{0l'}(theta_Z) e^{i l' phi~} d^1_{l' xi}(theta~) e^{i xi alpha},
   // times nZ
   const double r2 = 0.7071067811865475244 * nZ;
   //  l' = 0:  xi = +1: cZ st/sqrt2 e^{i alpha};  xi = -1: -cZ st/sqrt2 e^{-i alpha}
   const double z0 = cZ * st * r2;
-  c[12 * ld + e] = (T)(z0 * ca);
-  c[13 * ld + e] = (T)(z0 * sa);
-  c[14 * ld + e] = (T)(-z0 * ca);
-  c[15 * ld + e] = (T)(z0 * sa);
+  c[col_at(12, e, ld)] = (T)(z0 * ca);
+  c[col_at(13, e, ld)] = (T)(z0 * sa);
+  c[col_at(14, e, ld)] = (T)(-z0 * ca);
+  c[col_at(15, e, ld)] = (T)(z0 * sa);
   //  l' = +-1 (H'_{-1} = H'_{+1}):  xi = +1: sZ/sqrt2 (ct cpt + i spt) e^{i alpha}
   //                                 xi = -1: sZ/sqrt2 (-ct cpt + i spt) e^{-i alpha}
   const double z1 = sZ * r2;
   const double pr = ct * cpt, pi_ = spt;
-  c[16 * ld + e] = (T)(z1 * (pr * ca - pi_ * sa));
-  c[17 * ld + e] = (T)(z1 * (pr * sa + pi_ * ca));
-  c[18 * ld + e] = (T)(z1 * (-pr * ca + pi_ * sa));
-  c[19 * ld + e] = (T)(z1 * (pr * sa + pi_ * ca));
+  c[col_at(16, e, ld)] = (T)(z1 * (pr * ca - pi_ * sa));
+  c[col_at(17, e, ld)] = (T)(z1 * (pr * sa + pi_ * ca));
+  c[col_at(18, e, ld)] = (T)(z1 * (-pr * ca + pi_ * sa));
+  c[col_at(19, e, ld)] = (T)(z1 * (pr * sa + pi_ * ca));
 }
 
 // ------------------------------------------------------------------ per-event amplitude
@@ -326,20 +326,22 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     for (int i = 0; i < 4 * NZ; ++i) gz[i] = 0;
   }
 
-  const T* __restrict__ cb = col + e0;   // column 0 at this block's first event
+  using V4 = T __attribute__((ext_vector_type(4)));
+  const V4* __restrict__ gb = (const V4*)col + e0;   // column group 0 at this block's first event
   const uint32_t n_blk = (uint32_t)(e1 > e0 ? e1 - e0 : 0);
   for (uint32_t i = threadIdx.x; i < n_blk; i += 256) {
     const int64_t e = e0 + i;
     const uint32_t ob = i * (uint32_t)sizeof(T);
+    const uint32_t ob4 = i * (uint32_t)sizeof(V4);
     const auto& ka = *kernarg_laundered<AmpArgs<T, Sh>>();
     // this thread's LDS accumulator column, re-derived opaquely each event so the compiler keeps
     // the accumulators in LDS instead of promoting them back into registers across the loop
     lds_ptr<A_t> accb = (lds_ptr<A_t>)&accl[0][threadIdx.x];
     if constexpr (LDSACC) asm volatile("" : "+v"(accb));
-    const T m = ldoff(cb, ob), q = ldoff(cb + ld, ob), pB = ldoff(cb + 2 * ld, ob);
-    const T cK = ldoff(cb + 3 * ld, ob), sK = ldoff(cb + 4 * ld, ob);
-    const T cJ = ldoff(cb + 5 * ld, ob), sJ = ldoff(cb + 6 * ld, ob);
-    const T cph = ldoff(cb + 7 * ld, ob), sph = ldoff(cb + 8 * ld, ob);
+    const V4 g0 = ldoff(gb, ob4), g1 = ldoff(gb + ld, ob4), g2 = ldoff(gb + 2 * ld, ob4);
+    const T m = g0.x, q = g0.y, pB = g0.z, cK = g0.w;
+    const T sK = g1.x, cJ = g1.y, sJ = g1.z, cph = g1.w;
+    const T sph = g2.x;
 
     const T m2 = m * m;
     const T im = rcp_(m);
@@ -455,10 +457,11 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     T gzv = T(0);
     if constexpr (NZ > 0) {
       if (a.cnt[5] > 0) {
-        const T mz2 = ldoff(cb + 9 * ld, ob);
-        gzv = ldoff(cb + 11 * ld, ob);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) za[k] = ldoff(cb + (12 + k) * ld, ob);
+        const T mz2 = g2.y;   // (g2.z holds n_Z, already in the angular columns)
+        gzv = g2.w;
+        const V4 g3 = ldoff(gb + 3 * ld, ob4), g4 = ldoff(gb + 4 * ld, ob4);
+        za[0] = g3.x; za[1] = g3.y; za[2] = g3.z; za[3] = g3.w;
+        za[4] = g4.x; za[5] = g4.y; za[6] = g4.z; za[7] = g4.w;
         Cx<T> T0{T(0), T(0)}, T1{T(0), T(0)};
 #pragma unroll
         for (int z = 0; z < NZ; ++z) {

@@ -105,10 +105,10 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
     if (lane < 32 && e < a.n) {
       const T* col = a.cols;
       const int64_t ld = a.ld;
-      const T m = col[e], q = col[ld + e], pB = col[2 * ld + e];
-      const T cK = col[3 * ld + e], sK = col[4 * ld + e];
-      const T cJ = col[5 * ld + e], sJ = col[6 * ld + e];
-      const T cph = col[7 * ld + e], sph = col[8 * ld + e];
+      const T m = col[col_at(0, e, ld)], q = col[col_at(1, e, ld)], pB = col[col_at(2, e, ld)];
+      const T cK = col[col_at(3, e, ld)], sK = col[col_at(4, e, ld)];
+      const T cJ = col[col_at(5, e, ld)], sJ = col[col_at(6, e, ld)];
+      const T cph = col[col_at(7, e, ld)], sph = col[col_at(8, e, ld)];
       const T m2 = m * m, im_ = rcp_(m);
       const T zR = (a.rR * q) * (a.rR * q), zB = (a.rB * pB) * (a.rB * pB);
       const T qm = q * im_, pbm = pB * a.invMB, qq = q * q;
@@ -206,10 +206,10 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
       if constexpr (NZ > 0) {
         if (a.cnt[5] > 0) {
           // (the angular columns za carry the Z barrier factor n_Z)
-          const T mz2 = col[9 * ld + e], gz = col[11 * ld + e];
+          const T mz2 = col[col_at(9, e, ld)], gz = col[col_at(11, e, ld)];
           T za[8];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) za[i] = col[(12 + i) * ld + e];
+          for (int i = 0; i < 8; ++i) za[i] = col[col_at(12 + i, e, ld)];
           constexpr int zc0 = comp_base<Sh>(5);
 #pragma unroll
           for (int z = 0; z < NZ; ++z) {

@@ -12,6 +12,13 @@ constexpr int NFL = 2;          // floating (M, Gamma0) slots in the adjoint
 constexpr int NCOL_KSTAR = 9;   // per-event columns of the K* chain
 constexpr int NCOL_Z = 11;      // extra per-event columns of the Z chain
 constexpr int NCOL_MAX = NCOL_KSTAR + NCOL_Z;
+// Per-event columns are stored in groups of four: column k of event e sits at element
+// ((k / 4) * ld + e) * 4 + k % 4, so one 16-byte (FP32) or 32-byte (FP64) load per lane
+// reads four columns of an event, and a wavefront's load is one contiguous span.
+__host__ __device__ constexpr int col_groups(int ncol) { return (ncol + 3) / 4; }
+__host__ __device__ constexpr int64_t col_at(int k, int64_t e, int64_t ld) {
+  return ((int64_t)(k >> 2) * ld + e) * 4 + (k & 3);
+}
 
 enum { MODE_DENSITY = 0, MODE_NLL = 1, MODE_GRAD = 2 };
 

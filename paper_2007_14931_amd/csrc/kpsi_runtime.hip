@@ -286,7 +286,7 @@ kpsi_status derive_columns(kpsi_ctx* c, int s) {
   if (d.n == 0 || !c->has_model) return KPSI_OK;
   const int ncol = NCOL_KSTAR + (c->has_z ? NCOL_Z : 0);
   const int64_t ld = (d.n + 63) / 64 * 64;
-  const size_t bytes = (size_t)ld * ncol * tsize(c);
+  const size_t bytes = (size_t)ld * col_groups(ncol) * 4 * tsize(c);
   if (bytes > d.cols_cap) {
     if (d.cols) hipFree(d.cols);
     d.cols = nullptr;
