@@ -192,6 +192,22 @@ __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
   c[col_at(19, e, ld)] = (T)(z1 * (pr * sa + pi_ * ca));
 }
 
+// ------------------------------------------------------------------ compensated sums
+__device__ __forceinline__ void neumaier(double& s, double& c, double x) {
+  const double t = s + x;
+  c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+// Merge of two compensated sums; the two-sum error term is exact, so merging (a, b) and
+// (b, a) gives the same result.
+__device__ __forceinline__ void two_sum_merge(double& s, double& c, double s2, double c2) {
+  const double t = s + s2;
+  const double bp = t - s;
+  const double err = (s - (t - bp)) + (s2 - bp);
+  s = t;
+  c = c + c2 + err;
+}
+
 // ------------------------------------------------------------------ per-event amplitude
 template <typename T> struct Cx { T re, im; };
 template <typename T> __device__ __forceinline__ void cmac(Cx<T>& acc, T ar, T ai, T br, T bi) {
@@ -305,7 +321,35 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
   float nbad = 0.f;   // events with a non-positive or non-finite density (exact count)
   // Eq. 14 mixture on the data set: background weight k from the reduced normalisation total
   const bool mix = (set == 0) && a.bkg_data != nullptr;
-  const T kb = mix ? (T)(a.bkg_coef * (a.norm_total[0] + a.norm_total[1])) : T(0);
+  T kb = T(0);
+  if (mix) {
+    double tot;
+    if (a.mc_part) {
+      // sum eps S over the normalisation blocks in a fixed order (the same in every block):
+      // strided compensated sums per lane, a butterfly of exact two-sum merges in each
+      // wavefront (both partners get the same result), then the four wavefronts in order
+      __shared__ double kred[4][2];
+      double s = 0.0, c = 0.0;
+      for (int b = threadIdx.x; b < a.mc_nb; b += 256) {
+        neumaier(s, c, a.mc_part[b]);
+        neumaier(s, c, a.mc_part[a.pstride + b]);   // value 1: the Kahan correction
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) two_sum_merge(s, c, __shfl_xor(s, off, 64), __shfl_xor(c, off, 64));
+      if ((threadIdx.x & 63) == 0) {
+        kred[threadIdx.x >> 6][0] = s;
+        kred[threadIdx.x >> 6][1] = c;
+      }
+      __syncthreads();
+      s = kred[0][0];
+      c = kred[0][1];
+      for (int w = 1; w < 4; ++w) two_sum_merge(s, c, kred[w][0], kred[w][1]);
+      tot = s + c;
+    } else {
+      tot = a.norm_total[0] + a.norm_total[1];
+    }
+    kb = (T)(a.bkg_coef * tot);
+  }
   A_t ws = A_t(0);   // sum_i w_i S_i (mixture, gradient mode)
   // accumulators gk[LO, HI) live in this thread's LDS column accl[.][tid] (gradient kernel)
   constexpr bool LDSACC = GRAD && (Sh::LDS_HI > Sh::LDS_LO);
@@ -679,7 +723,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
   if (wave == 0) {
     const double t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
     // value-major layout: value v of block b at partial[v * gridDim.x + b]
-    if (GRAD || lane < 3) a.partial[(int64_t)lane * gridDim.x + blockIdx.x] = t;
+    if (GRAD || lane < 3) a.partial[(int64_t)lane * a.pstride + a.poff + blockIdx.x] = t;
   }
 }
 
@@ -687,13 +731,6 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
 // the blocks of one set: each thread runs a Neumaier sum over a strided subset, then the
 // 256 partial pairs are merged pairwise in a fixed tree.  Output goes to out[set*NACC + v]
 // (mapped pinned host memory).
-__device__ __forceinline__ void two_sum_merge(double& s, double& c, double s2, double c2) {
-  const double t = s + s2;
-  const double bp = t - s;
-  const double err = (s - (t - bp)) + (s2 - bp);
-  s = t;
-  c = c + c2 + err;
-}
 
 __global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ partial, int nb_data, int nb_mc,
                                                     int nv, double* __restrict__ out, double* __restrict__ out_dev,

@@ -57,7 +57,9 @@ template <typename T, class Sh> struct AmpArgs {
   int64_t ld[2];        // column strides (elements)
   int64_t n[2];         // events per set
   const T* eps;         // per-normalisation-event efficiency, or null (flat)
-  double* partial;      // value-major: value v of block b at [v * blocks + b]
+  double* partial;      // value-major: value v of block b at [v * pstride + poff + b]
+  int64_t pstride;      // row stride of the partials (blocks of both sets)
+  int poff;             // block offset of this launch in the partial rows
   double* s_out[2];     // density mode: per-event S of each set
   int nb_data;          // blocks of the data set; the rest cover the normalisation set
   int chunk;            // events per block
@@ -67,10 +69,14 @@ template <typename T, class Sh> struct AmpArgs {
   RC<T> zs[Sh::NZ > 0 ? Sh::NZ : 1];
   // Signal + background mixture (Eq. 14) on the data set, active when bkg_data != null:
   // each data event contributes ln t with t = purity eps_i S_i + k b_i, where
-  // k = bkg_coef * (norm_total[0] + norm_total[1]) (bkg_coef = (1 - p) / (N_b N_MC), and
-  // norm_total the reduced normalisation record in device memory).
+  // k = bkg_coef * sum eps S over the normalisation events (bkg_coef = (1 - p) / (N_b N_MC)).
+  // The sum comes from the normalisation launch's block partials (mc_part: values 0 and 1 of
+  // mc_nb blocks, rows pstride apart), or, when mc_part is null, from norm_total (a reduced
+  // record in device memory: the interference-matrix normalisation).
   const T* eps_data;    // per-data-event efficiency, or null (1)
   const T* bkg_data;    // per-data-event background density, or null (signal only)
+  const double* mc_part;
+  int mc_nb;
   const double* norm_total;
   double bkg_coef;
   T purity;

@@ -632,37 +632,65 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   }
   c->timing = mode != MODE_DENSITY && c->timing_every > 0 && (c->timing_calls++ % c->timing_every) == 0;
   if (c->timing) hipEventRecord(c->ev0, c->stream);
-  // one launch over the events of [nd data, nm normalisation], block partials reduced into the
-  // record slots of sets first..first+nsets-1 (written by the GPU straight into mapped pinned
-  // host memory, and into the device copy when out_dev is given)
-  auto pass = [&](int64_t nd, int64_t nm, int first, int nsets, double* out_dev, bool last) -> kpsi_status {
-    AmpArgs<T, Sh> b = a;
-    const int ept = pick_ept<T, Sh>(c, mode, nd, nm);
-    b.chunk = BLOCK * ept;
-    const int nbd = (int)((nd + b.chunk - 1) / b.chunk), nbm = (int)((nm + b.chunk - 1) / b.chunk);
-    b.nb_data = nbd;
-    if (mode != MODE_DENSITY) {
-      kpsi_status st = ensure_partial(c, (size_t)(nbd + nbm));
-      if (st) return st;
-    }
-    b.partial = c->partial;
-    hipError_t e = launch_amp<T, Sh>(b, mode, nbd + nbm, c->stream);
+  // Launches over the events of [nd data, nm normalisation] write block partials (rows of
+  // nbd + nbm blocks, data first); one reduction then writes the record of each set covered
+  // (by the GPU straight into mapped pinned host memory).
+  const int64_t nd = (which == 1) ? 0 : c->set[0].n, nm = (which == 0) ? 0 : c->set[1].n;
+  int chunk_d, chunk_m;
+  if (!mix) {
+    chunk_d = chunk_m = BLOCK * pick_ept<T, Sh>(c, mode, nd, nm);
+  } else {
+    // Eq. 14: the data terms need the normalisation total, so the normalisation events run in
+    // a launch of their own first, and the data launch sums their block partials (unless the
+    // normalisation record comes from the interference matrix and is already in red_dev)
+    chunk_m = BLOCK * pick_ept<T, Sh>(c, mode, 0, nm);
+    chunk_d = BLOCK * pick_ept<T, Sh>(c, mode, nd, 0);
+  }
+  const int nbd = (int)((nd + chunk_d - 1) / chunk_d), nbm = (int)((nm + chunk_m - 1) / chunk_m);
+  if (mode != MODE_DENSITY) {
+    kpsi_status st = ensure_partial(c, (size_t)(nbd + nbm));
+    if (st) return st;
+  }
+  a.partial = c->partial;
+  a.pstride = nbd + nbm;
+  auto launch = [&](const AmpArgs<T, Sh>& b, int nblocks) -> kpsi_status {
+    hipError_t e = launch_amp<T, Sh>(b, mode, nblocks, c->stream);
     if (e != hipSuccess) return fail(c, KPSI_E_HIP, "amplitude kernel: %s", hipGetErrorString(e));
-    if (last && c->timing) hipEventRecord(c->ev1, c->stream);   // end of the per-event work
-    if (mode == MODE_DENSITY) return KPSI_OK;
-    e = launch_reduce_final(c->partial, nbd, nbm, nv, c->red, out_dev, first, nsets, c->stream);
-    if (e != hipSuccess) return fail(c, KPSI_E_HIP, "reduction kernel: %s", hipGetErrorString(e));
     return KPSI_OK;
   };
-  const int64_t nd = (which == 1) ? 0 : c->set[0].n, nm = (which == 0) ? 0 : c->set[1].n;
   kpsi_status st = KPSI_OK;
   if (!mix) {
-    st = pass(nd, nm, which == 1 ? 1 : 0, which < 0 ? 2 : 1, nullptr, true);
+    AmpArgs<T, Sh> b = a;
+    b.chunk = chunk_d;
+    b.nb_data = nbd;
+    b.poff = 0;
+    st = launch(b, nbd + nbm);
   } else {
-    // Eq. 14: the data terms need the normalisation total, so the normalisation events go
-    // first (unless their record comes from the interference matrix and is already in red_dev)
-    if (nm > 0) st = pass(0, nm, 1, 1, c->red_dev, nd == 0);
-    if (!st && nd > 0) st = pass(nd, 0, 0, 1, nullptr, true);
+    if (nm > 0) {
+      AmpArgs<T, Sh> b = a;
+      b.chunk = chunk_m;
+      b.nb_data = 0;
+      b.poff = nbd;
+      st = launch(b, nbm);
+    }
+    if (!st && nd > 0) {
+      AmpArgs<T, Sh> b = a;
+      b.chunk = chunk_d;
+      b.nb_data = nbd;
+      b.poff = 0;
+      if (nm > 0) {
+        b.mc_part = c->partial + nbd;
+        b.mc_nb = nbm;
+      }
+      st = launch(b, nbd);
+    }
+  }
+  if (st) return st;
+  if (c->timing) hipEventRecord(c->ev1, c->stream);   // end of the per-event work
+  if (mode != MODE_DENSITY) {
+    hipError_t e = launch_reduce_final(c->partial, nbd, nbm, nv, c->red, nullptr, nd > 0 ? 0 : 1,
+                                       (nd > 0) + (nm > 0), c->stream);
+    if (e != hipSuccess) return fail(c, KPSI_E_HIP, "reduction kernel: %s", hipGetErrorString(e));
   }
   if (st) return st;
   if (mode == MODE_DENSITY) return KPSI_OK;
