@@ -26,10 +26,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic floating-point work per event of one NLL+gradient call of this workload
-# (fused multiply-add = 2, reciprocal/rsqrt/log = 1), from the op count of the
-# per-call formulation: forward amplitudes 541, adjoint 418.
+# (fused multiply-add = 2, other arithmetic and reciprocal/rsqrt/log = 1), from the op count
+# of the per-call formulation (bare Breit-Wigner per resonance, resonance constants in the
+# couplings, barrier factors in the d functions): forward 530, adjoint 384.
 TIMING_EVERY = 10
-FLOP_PER_EVENT = {"full_grad": 959}
+FLOP_PER_EVENT = {"full_grad": 914}
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}        # MI355X published vector peaks
 PEAK_TFLOPS_UNPACKED = {"f32": 78.6, "f64": 78.6}  # without packed-FP32 instructions
 
