@@ -20,6 +20,7 @@
 //   Eq. (11) parity relation of the Z helicity couplings
 //   Eq. (12) full signal density (K* + Z coherent sum)
 //   Eq. (14) efficiency-weighted PDF (signal part), normalised by phase-space MC
+//   text after Eq. (12): charge-conjugate decays (phi -> -phi) with a flavour mistag rate
 // Readings where the paper is silent are listed at each place they are used.
 
 #include <cmath>
@@ -566,6 +567,81 @@ int oracle_nll_mix(const oracle_kin* kin, const oracle_res* res, int n_res, cons
     for (int d = 0; d < n_dir; ++d) {
       const double df = purity * e * (s.d[d] / NS - s.v * dNS[d] / (NS * NS));
       gL[d] += df / f;
+    }
+  }
+  *nll = -2.0 * L.get();
+  for (int d = 0; d < n_dir; ++d) grad[d] = -2.0 * gL[d];
+  return 0;
+}
+
+// Charge-conjugate decays with a per-event flavour tag (text after Eq. 12): the density of the
+// conjugate decay is S with the sign of phi reversed.  Reading (the paper states only that the
+// sign flips and that mis-tagging is allowed for): an event tagged q = +1 (B0) or -1 (B0bar) is
+// of the other flavour with probability w, both flavours equally produced, so
+//   f(x, q) = [(1 - w) S(x^(q)) + w S(x^(-q))] / N_q,   x^(s) = (m, cos K, cos J, s phi),
+//   N_q = (1 - w) I(q) + w I(-q),   I(s) = (1/N_MC) sum_j eps_j S(y_j^(s)),
+// and NLL = -2 sum_i ln f(x_i, q_i) (the data efficiencies dropped as for the signal NLL).
+// The Z-chain angles of x^(s) are recomputed from the flipped event.  tag[i] is +1 or -1.
+// Returns 0, -1 on bad arguments, or -5 when a data term or a normalisation is not positive.
+int oracle_nll_cc(const oracle_kin* kin, const oracle_res* res, int n_res, const double* par, int64_t nd,
+                  const double* dm, const double* dck, const double* dcj, const double* dphi, const double* tag,
+                  int64_t nm, const double* mm, const double* mck, const double* mcj, const double* mphi,
+                  const double* eps_m, double mistag, int n_dir, const int* dirs, double* nll, double* grad) {
+  Kin k = to_kin(kin);
+  std::vector<Res> rs = to_res(res, n_res);
+  const int np = n_full_params(rs);
+  if (nd <= 0 || nm <= 0 || !tag || !(mistag >= 0.0 && mistag <= 0.5)) return -1;
+  if (n_dir < 0 || n_dir > KD) return -1;
+  for (int d = 0; d < n_dir; ++d) if (dirs[d] < 0 || dirs[d] >= np) return -1;
+  for (int64_t i = 0; i < nd; ++i) if (tag[i] != 1.0 && tag[i] != -1.0) return -1;
+  bool hasZ = false;
+  for (auto& r : rs) hasZ |= (r.chain == 1);
+  g_nd = n_dir;
+  std::vector<Dual> P(np);
+  for (int i = 0; i < np; ++i) P[i] = Dual(par[i]);
+  for (int d = 0; d < n_dir; ++d) P[dirs[d]].d[d] = 1.0;
+  auto dens = [&](double m, double cK, double cJ, double ph) {
+    Event ev{m, cK, cJ, ph};
+    ZAng za{0, 0, 0, 0, 0};
+    if (hasZ) za = z_angles(k, ev.m, ev.cK, ev.cJ, ev.phi);
+    return density<Dual>(k, rs, P.data(), ev, za);
+  };
+  // I(+1), I(-1) over the phase-space events
+  KSum sI[2];
+  std::vector<double> gI[2] = {std::vector<double>(n_dir, 0.0), std::vector<double>(n_dir, 0.0)};
+  for (int64_t j = 0; j < nm; ++j) {
+    const double e = eps_m ? eps_m[j] : 1.0;
+    for (int f = 0; f < 2; ++f) {
+      const Dual s = dens(mm[j], mck[j], mcj[j], f == 0 ? mphi[j] : -mphi[j]);
+      sI[f].add(e * s.v);
+      for (int d = 0; d < n_dir; ++d) gI[f][d] += e * s.d[d];
+    }
+  }
+  double I[2], dI[2][KD];
+  for (int f = 0; f < 2; ++f) {
+    I[f] = sI[f].get() / (double)nm;
+    for (int d = 0; d < n_dir; ++d) dI[f][d] = gI[f][d] / (double)nm;
+  }
+  // N_q for q = +1 (index 0) and q = -1 (index 1)
+  double N[2], dN[2][KD];
+  for (int f = 0; f < 2; ++f) {
+    N[f] = (1.0 - mistag) * I[f] + mistag * I[1 - f];
+    for (int d = 0; d < n_dir; ++d) dN[f][d] = (1.0 - mistag) * dI[f][d] + mistag * dI[1 - f][d];
+    if (!(N[f] > 0.0)) { *nll = INFINITY; return -5; }
+  }
+  KSum L;
+  std::vector<double> gL(n_dir, 0.0);
+  for (int64_t i = 0; i < nd; ++i) {
+    const int f = tag[i] > 0.0 ? 0 : 1;
+    const double ph = dphi[i];
+    const Dual s_same = dens(dm[i], dck[i], dcj[i], f == 0 ? ph : -ph);
+    const Dual s_other = dens(dm[i], dck[i], dcj[i], f == 0 ? -ph : ph);
+    const double t = (1.0 - mistag) * s_same.v + mistag * s_other.v;
+    if (!(t > 0.0) || !std::isfinite(t)) { *nll = INFINITY; return -5; }
+    L.add(std::log(t) - std::log(N[f]));
+    for (int d = 0; d < n_dir; ++d) {
+      const double dt = (1.0 - mistag) * s_same.d[d] + mistag * s_other.d[d];
+      gL[d] += dt / t - dN[f][d] / N[f];
     }
   }
   *nll = -2.0 * L.get();

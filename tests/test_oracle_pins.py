@@ -790,3 +790,101 @@ def test_lass_without_effective_range_phase_is_the_scaled_scalar_resonance():
     q0 = O.breakup(M, K["mK"], K["mPi"])
     for m in (0.8, 1.2, 1.425, 1.9):
         assert O.lineshape(K, r, M, G0, m) == pytest.approx(M * M * G0 / q0 * O.lineshape(K, bw, M, G0, m), rel=1e-10)
+
+
+# ---------------------------------------------------------------- charge conjugation, mistag
+def _mirror(ev):
+    out = np.array(ev, dtype=float, copy=True)
+    out[3] = -out[3]
+    return out
+
+
+def test_conjugate_density_of_one_kstar_with_real_couplings_is_phi_even():
+    # For one resonance a_xi = A(m) sum_lambda H_lambda d^1_{lambda xi}(theta_J) e^{i lambda phi} d^J(theta_K):
+    # reversing phi conjugates every angular factor, so with real couplings S(phi) = S(-phi),
+    # while a relative coupling phase makes the phi-odd interference terms appear.
+    res = [W.KSTAR892]
+    ev = W.neutral_events(40, 71)
+    par = W.params(res, seed=5)
+    real = par.copy()
+    real[1:6:2] = [0.0, math.pi, 0.0]
+    np.testing.assert_allclose(O.density(K, res, real, _mirror(ev)), O.density(K, res, real, ev), rtol=1e-12)
+    cplx = real.copy()
+    cplx[1] = 0.9
+    s, sm = O.density(K, res, cplx, ev), O.density(K, res, cplx, _mirror(ev))
+    assert np.max(np.abs(sm - s) / s) > 1e-2
+
+
+def test_conjugate_density_of_the_z_chain_alone_is_phi_even_and_the_full_model_is_not():
+    # Z alone: with H'_{-1} = H'_{+1} (Eq. 11) the xi = +1 and xi = -1 amplitudes differ only
+    # in the sign of the sin(phi~) term, and reversing phi reverses phi~, so the two swap and
+    # S is phi-even for any couplings.  With K* and Z interfering (Eq. 12) it is not.
+    ev = W.neutral_events(40, 72)
+    ev[0] = np.clip(ev[0], W.M_LO + 1e-3, W.M_HI - 1e-3)
+    res = [W.Z4430]
+    par = W.params(res, seed=6)
+    np.testing.assert_allclose(O.density(K, res, par, _mirror(ev)), O.density(K, res, par, ev), rtol=1e-12)
+    res = W.model("full")
+    par = W.params(res, seed=7)
+    s, sm = O.density(K, res, par, ev), O.density(K, res, par, _mirror(ev))
+    assert np.max(np.abs(sm - s) / s) > 1e-2
+
+
+def _cc_inputs(n_d=300, n_m=1500, model="full"):
+    res = W.model(model)
+    par = W.params(res, seed=61)
+    data = W.neutral_events(n_d, 62, peaked=True)
+    mc = O.gen_phsp(K, 63, n_m, W.PHSP_WMAX)
+    eps_m = O.acceptance(W.acceptance_coefficients(), W.M_LO, W.M_HI, mc)
+    tag = np.where(np.random.default_rng(64).random(n_d) < 0.5, 1.0, -1.0)
+    return res, par, data, mc, eps_m, tag
+
+
+def test_cc_without_mistag_and_with_b0_tags_is_the_signal_likelihood():
+    res, par, data, mc, eps_m, _ = _cc_inputs()
+    dirs = np.flatnonzero(W.free_mask(res, ("K*(1410)", "Z(4430)")))
+    st, v, g = O.nll_cc(K, res, par, data, np.ones(data.shape[1]), mc, 0.0, eps_m, dirs)
+    st2, v2, g2 = O.nll(K, res, par, data, mc, eps=eps_m, dirs=dirs)
+    assert st == 0 and st2 == 0
+    assert v == pytest.approx(v2, rel=1e-13)
+    np.testing.assert_allclose(g, g2, rtol=1e-11, atol=1e-11 * np.abs(g2).max())
+
+
+def test_cc_conjugate_tags_read_the_mirrored_events():
+    # tag -1 with no mistag: the conjugate density at x equals S at the mirrored x, and its
+    # normalisation I(-1) is the signal normalisation over the mirrored phase-space events
+    res, par, data, mc, eps_m, _ = _cc_inputs()
+    st, v, _ = O.nll_cc(K, res, par, data, -np.ones(data.shape[1]), mc, 0.0, eps_m)
+    st2, v2, _ = O.nll(K, res, par, _mirror(data), _mirror(mc), eps=eps_m)
+    assert st == 0 and st2 == 0
+    assert v == pytest.approx(v2, rel=1e-13)
+
+
+def test_cc_is_invariant_under_mirroring_events_and_swapping_tags():
+    res, par, data, mc, eps_m, tag = _cc_inputs()
+    _, v, _ = O.nll_cc(K, res, par, data, tag, mc, 0.07, eps_m)
+    _, v2, _ = O.nll_cc(K, res, par, _mirror(data), -tag, _mirror(mc), 0.07, eps_m)
+    assert v == pytest.approx(v2, rel=1e-13)
+
+
+def test_cc_with_half_mistag_ignores_the_tags():
+    # w = 1/2: every event has density (S(x) + S(x mirrored))/2 and N_+ = N_- whatever its tag
+    res, par, data, mc, eps_m, tag = _cc_inputs()
+    _, v, _ = O.nll_cc(K, res, par, data, tag, mc, 0.5, eps_m)
+    _, v2, _ = O.nll_cc(K, res, par, data, np.ones_like(tag), mc, 0.5, eps_m)
+    assert v == pytest.approx(v2, rel=1e-13)
+    _, v3, _ = O.nll_cc(K, res, par, data, tag, mc, 0.2, eps_m)
+    assert abs(v3 - v) > 1e-3
+
+
+def test_cc_gradient_matches_central_differences():
+    res, par, data, mc, eps_m, tag = _cc_inputs(120, 600)
+    dirs = np.flatnonzero(W.free_mask(res, ("K*(1410)", "Z(4430)")))
+    _, v, g = O.nll_cc(K, res, par, data, tag, mc, 0.06, eps_m, dirs)
+    for k, i in enumerate(dirs[::5]):
+        h = 1e-6 * max(1.0, abs(par[i]))
+        pp, pm = par.copy(), par.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (O.nll_cc(K, res, pp, data, tag, mc, 0.06, eps_m)[1] - O.nll_cc(K, res, pm, data, tag, mc, 0.06, eps_m)[1]) / (2 * h)
+        assert g[5 * k] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(g).max())
