@@ -173,7 +173,8 @@ def norm_cache_leg(eng, par, res, floating) -> dict:
 def extension_legs(stream, data, mc, par, res, floating, steps: int = 1000, warmup: int = 300) -> dict:
     """Per-call NLL+gradient rate of the extensions at the benchmark sizes (same data and
     normalisation events, FP32): the signal + background mixture of Eq. 14 with per-event
-    efficiency and background values, and the LASS S-wave model (LASS + 8 K* + two Z, the
+    efficiency and background values, flavour-tagged events with mistag (the normalisation
+    events evaluated at phi and -phi), and the LASS S-wave model (LASS + 8 K* + two Z, the
     K*(1410) and Z(4430) lineshapes floating)."""
     import torch
     from paper_2007_14931_amd import kpsi
@@ -206,6 +207,16 @@ def extension_legs(stream, data, mc, par, res, floating, steps: int = 1000, warm
     e.set_efficiency_values(eps_m)
     e.set_background(0.85, eps_d, b_d, b_m)
     out["mixture"] = {"model": "10 K* + Z(4430)", "purity": 0.85, **timed(e, par)}
+    e.close()
+    # flavour-tagged events (half of them the conjugate decay) with a 5% mistag fraction
+    e = kpsi.Engine(0, "fp32", stream)
+    e.set_model(W.KIN, res)
+    e.set_floating([1 if r.name in floating else 0 for r in res])
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    e.set_efficiency_values(eps_m)
+    e.set_flavour(np.where(rng.random(nd) < 0.5, 1.0, -1.0), 0.05)
+    out["flavour_tags"] = {"model": "10 K* + Z(4430)", "mistag": 0.05, **timed(e, par)}
     e.close()
     lres = W.model("lass_full2z")
     lfl = ("K*(1410)", "Z(4430)")

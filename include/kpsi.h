@@ -255,6 +255,25 @@ kpsi_status kpsi_fit_fractions(kpsi_ctx* ctx, const double* params, double* ff, 
 kpsi_status kpsi_set_background(kpsi_ctx* ctx, double purity, const double* eps_data, const double* b_data,
                                 const double* b_norm);
 
+/* ---------------------------------------------------------------- flavour tags (text after Eq. 12)
+ * Charge-conjugate decays: the density of the conjugate decay is S with the sign of phi
+ * reversed.  tags[i] = +1 (B0) or -1 (conjugate) for each loaded data event; an event is of the
+ * other flavour with probability `mistag`, both flavours equally produced.  Once set,
+ * kpsi_nll / kpsi_nll_and_grad return
+ *   -2 ln L = -2 sum_i ln[(1 - w) S(x_i^(q_i)) + w S(x_i^(-q_i))] + 2 sum_q n_q ln N_q,
+ *   x^(s) = (m, cos theta_K*, cos theta_J/psi, s phi),  N_q = (1 - w) I(q) + w I(-q),
+ *   I(s) = (1/N_MC) sum_j eps_j S(y_j^(s))
+ * (n_q the number of data events tagged q; the data efficiencies dropped as for the signal
+ * likelihood).  Each call evaluates the normalisation events at +phi and at -phi, so the
+ * interference-matrix normalisation is not used while tags are set.
+ *   tags:   n doubles (host, copied), n = the number of loaded data events; NULL switches the
+ *           tags off (every event a B0).
+ *   mistag: w in [0, 1/2].
+ * Loading data events drops the tags.  Errors: KPSI_E_ARG for a wrong count, a tag other than
+ * +-1 or w outside [0, 1/2]; KPSI_E_UNSUPPORTED while the background mixture is set (and
+ * kpsi_set_background returns it while tags are set). */
+kpsi_status kpsi_set_flavour(kpsi_ctx* ctx, const double* tags, int64_t n, double mistag);
+
 /* Per-event values of a 2D (mass variables) x 2D (angular variables) template, the form in
  * which the paper passes efficiency and background shapes to the fit: t_mass over
  * (m_Kpi in [m_K + m_pi, M_B - M_J/psi], cos theta_K* in [-1, 1]) with n_mass[0] x n_mass[1]

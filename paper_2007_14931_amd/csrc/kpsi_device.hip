@@ -302,18 +302,24 @@ template <typename T, class Sh, int MODE> struct AmpWaves {
   static constexpr bool f32 = std::is_same<T, float>::value;
   static constexpr int v = lds ? (f32 ? 4 : 2) : (!f32 && Sh::NK > 1 ? 4 : 1);
 };
-template <typename T, class Sh, int MODE>
+// CC: flavour-tagged events (text after Eq. 12).  Data events carry a tag q = +-1 and are read
+// with phi -> q phi, plus the other flavour with the mistag weight; the normalisation events run
+// twice, as record 1 (phi) and record 2 (-phi), blocks [nb_data + nb_mc, nb_data + 2 nb_mc).
+template <typename T, class Sh, int MODE, bool CC>
 __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(const AmpArgs<T, Sh> a) {
   constexpr int NK = Sh::NK;
   constexpr int NZ = Sh::NZ;
   constexpr bool GRAD = (MODE == MODE_GRAD);
   using A_t = typename AccType<T>::type;   // per-thread gradient accumulator type
 
-  const int set = (blockIdx.x < (unsigned)a.nb_data) ? 0 : 1;
-  const int64_t blk = set == 0 ? blockIdx.x : blockIdx.x - a.nb_data;
-  const int64_t n = a.n[set];
-  const T* __restrict__ col = a.cols[set];
-  const int64_t ld = a.ld[set];
+  const int set = (blockIdx.x < (unsigned)a.nb_data)
+                      ? 0
+                      : ((!CC || blockIdx.x < (unsigned)(a.nb_data + a.nb_mc)) ? 1 : 2);
+  const int src = set == 0 ? 0 : 1;   // event set read by this block
+  const int64_t blk = (int64_t)blockIdx.x - (set == 0 ? 0 : (set == 1 ? a.nb_data : a.nb_data + a.nb_mc));
+  const int64_t n = a.n[src];
+  const T* __restrict__ col = a.cols[src];
+  const int64_t ld = a.ld[src];
   const int64_t e0 = blk * (int64_t)a.chunk;
   const int64_t e1 = (e0 + a.chunk < n) ? e0 + a.chunk : n;
 
@@ -489,16 +495,34 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     // e^{i lambda phi} d^1_{lambda xi}(theta_J):  lambda=+1: (1+c)/2, (1-c)/2;  0: s/sqrt2, -s/sqrt2;
     // lambda=-1: (1-c)/2, (1+c)/2   for xi = +1, -1
     const T hp = T(0.5) * (T(1) + cJ), hm = T(0.5) * (T(1) - cJ), s0 = sJ * T(0.70710678118654752440);
-    const Cx<T> eUp{cph * Up.re - sph * Up.im, cph * Up.im + sph * Up.re};
-    const Cx<T> eUm{cph * Um.re + sph * Um.im, cph * Um.im - sph * Um.re};
-    Cx<T> ap{hp * eUp.re + s0 * U0.re + hm * eUm.re, hp * eUp.im + s0 * U0.im + hm * eUm.im};
-    Cx<T> am{hm * eUp.re - s0 * U0.re + hp * eUm.re, hm * eUp.im - s0 * U0.im + hp * eUm.im};
+    // Amplitudes a_xi (Eq. 12) of the event read with phi -> f phi.  f = -1 is the
+    // charge-conjugate decay: e^{i lambda phi} becomes e^{-i lambda phi}, and the Z-chain azimuths
+    // phi~ and alpha reverse, which conjugates the Z angular factors.
+    auto kstar_at = [&](T f, Cx<T>& ap_, Cx<T>& am_) {
+      const T sp = f * sph;
+      const Cx<T> eUp{cph * Up.re - sp * Up.im, cph * Up.im + sp * Up.re};
+      const Cx<T> eUm{cph * Um.re + sp * Um.im, cph * Um.im - sp * Um.re};
+      ap_ = Cx<T>{hp * eUp.re + s0 * U0.re + hm * eUm.re, hp * eUp.im + s0 * U0.im + hm * eUm.im};
+      am_ = Cx<T>{hm * eUp.re - s0 * U0.re + hp * eUm.re, hm * eUp.im - s0 * U0.im + hp * eUm.im};
+    };
+    T za[8];
+    auto z_add = [&](T f, const Cx<T>& T0, const Cx<T>& T1, Cx<T>& ap_, Cx<T>& am_) {
+      cmac(ap_, T0.re, T0.im, za[0], f * za[1]);
+      cmac(am_, T0.re, T0.im, za[2], f * za[3]);
+      cmac(ap_, T1.re, T1.im, za[4], f * za[5]);
+      cmac(am_, T1.re, T1.im, za[6], f * za[7]);
+    };
+    // flavour of this reading: the tag of a data event, + / - for the two normalisation records
+    T f1 = T(1);
+    if constexpr (CC) f1 = set == 0 ? ldoff(a.tag + e0, ob) : (set == 1 ? T(1) : T(-1));
+    Cx<T> ap, am;
+    kstar_at(f1, ap, am);
 
     // ---- Z chain (Eq. 10-12)
     // (AZ holds the bare Breit-Wigner; the Z barrier factor n_Z is in the angular columns)
     Cx<T> AZ[NZ > 0 ? NZ : 1];
-    T za[8];
     T gzv = T(0);
+    Cx<T> T0k{T(0), T(0)}, T1k{T(0), T(0)};   // Z coupling sums, kept for a second reading
     if constexpr (NZ > 0) {
       if (a.cnt[5] > 0) {
         const T mz2 = g2.y;   // (g2.z holds n_Z, already in the angular columns)
@@ -519,10 +543,11 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
             cmac(T1, rc.hr[1], rc.hi[1], AZ[z].re, AZ[z].im);
           }
         }
-        cmac(ap, T0.re, T0.im, za[0], za[1]);
-        cmac(am, T0.re, T0.im, za[2], za[3]);
-        cmac(ap, T1.re, T1.im, za[4], za[5]);
-        cmac(am, T1.re, T1.im, za[6], za[7]);
+        z_add(f1, T0, T1, ap, am);
+        if constexpr (CC) {
+          T0k = T0;
+          T1k = T1;
+        }
       }
     }
 
@@ -535,9 +560,28 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
 
     // ---- likelihood terms
     T w;
+    T w2 = T(0);                  // mistag: adjoint weight of the other-flavour reading
+    Cx<T> ap2{T(0), T(0)}, am2{T(0), T(0)};
     if (set == 0) {
       T arg = S;   // the quantity whose logarithm is summed
-      if (mix) {
+      if constexpr (CC) {
+        if (a.mistag > T(0)) {
+          // t = (1 - w) S(q phi) + w S(-q phi)
+          kstar_at(-f1, ap2, am2);
+          if constexpr (NZ > 0) {
+            if (a.cnt[5] > 0) z_add(-f1, T0k, T1k, ap2, am2);
+          }
+          const T S2 = ap2.re * ap2.re + ap2.im * ap2.im + am2.re * am2.re + am2.im * am2.im;
+          arg = fma_(a.keep, S, a.mistag * S2);
+          if (!(arg > T(0)) || !(arg < T(INFINITY))) { nbad += 1.f; continue; }
+          const T r = rcp_(arg);
+          w = a.keep * r;
+          w2 = a.mistag * r;
+        } else {
+          if (!(S > T(0)) || !(S < T(INFINITY))) { nbad += 1.f; continue; }
+          w = rcp_(S);
+        }
+      } else if (mix) {
         // Eq. 14: t = p eps S + k b; d ln t / dS = p eps / t
         const T pe = a.purity * (a.eps_data ? ldoff(a.eps_data + e0, ob) : T(1));
         arg = fma_(pe, S, kb * ldoff(a.bkg_data + e0, ob));
@@ -564,13 +608,33 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     }
 
     if constexpr (GRAD) {
-      // adjoint of S = sum_xi |a_xi|^2: b_xi = w conj(a_xi); W_lambda = sum_xi E_{lambda xi} b_xi
-      const Cx<T> bp{w * ap.re, -w * ap.im}, bm{w * am.re, -w * am.im};
-      const Cx<T> Wp0{hp * bp.re + hm * bm.re, hp * bp.im + hm * bm.im};
-      const Cx<T> Wp{cph * Wp0.re - sph * Wp0.im, cph * Wp0.im + sph * Wp0.re};   // e^{+i phi}
-      const Cx<T> W0{s0 * (bp.re - bm.re), s0 * (bp.im - bm.im)};
-      const Cx<T> Wm0{hm * bp.re + hp * bm.re, hm * bp.im + hp * bm.im};
-      const Cx<T> Wm{cph * Wm0.re + sph * Wm0.im, cph * Wm0.im - sph * Wm0.re};   // e^{-i phi}
+      // adjoint of S = sum_xi |a_xi|^2: b_xi = w conj(a_xi); W_lambda = sum_xi E_{lambda xi} b_xi,
+      // summed over the readings of the event
+      Cx<T> W0, Wp, Wm;
+      Cx<T> bp, bm, bp2{T(0), T(0)}, bm2{T(0), T(0)};
+      auto adj_w = [&](auto first, T wt, T f, const Cx<T>& ap_, const Cx<T>& am_, Cx<T>& bp_, Cx<T>& bm_) {
+        constexpr bool F = decltype(first)::value;
+        bp_ = Cx<T>{wt * ap_.re, -wt * ap_.im};
+        bm_ = Cx<T>{wt * am_.re, -wt * am_.im};
+        const T sp = f * sph;
+        const Cx<T> Wp0{hp * bp_.re + hm * bm_.re, hp * bp_.im + hm * bm_.im};
+        const Cx<T> wp{cph * Wp0.re - sp * Wp0.im, cph * Wp0.im + sp * Wp0.re};   // e^{+i f phi}
+        const Cx<T> w0{s0 * (bp_.re - bm_.re), s0 * (bp_.im - bm_.im)};
+        const Cx<T> Wm0{hm * bp_.re + hp * bm_.re, hm * bp_.im + hp * bm_.im};
+        const Cx<T> wm{cph * Wm0.re + sp * Wm0.im, cph * Wm0.im - sp * Wm0.re};   // e^{-i f phi}
+        if constexpr (F) {
+          Wp = wp; W0 = w0; Wm = wm;
+        } else {
+          Wp.re += wp.re; Wp.im += wp.im;
+          W0.re += w0.re; W0.im += w0.im;
+          Wm.re += wm.re; Wm.im += wm.im;
+        }
+      };
+      adj_w(std::true_type{}, w, f1, ap, am, bp, bm);
+      const bool two = CC && set == 0 && a.mistag > T(0);
+      if constexpr (CC) {
+        if (two) adj_w(std::false_type{}, w2, -f1, ap2, am2, bp2, bm2);
+      }
 
       auto grad_spin = [&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
@@ -634,11 +698,24 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
 
       if constexpr (NZ > 0) {
         if (a.cnt[5] > 0) {
-          // WZ_{l'} = sum_xi Zang_{l' xi} b_xi
-          const Cx<T> WZ0{za[0] * bp.re - za[1] * bp.im + za[2] * bm.re - za[3] * bm.im,
-                          za[0] * bp.im + za[1] * bp.re + za[2] * bm.im + za[3] * bm.re};
-          const Cx<T> WZ1{za[4] * bp.re - za[5] * bp.im + za[6] * bm.re - za[7] * bm.im,
-                          za[4] * bp.im + za[5] * bp.re + za[6] * bm.im + za[7] * bm.re};
+          // WZ_{l'} = sum_xi Zang_{l' xi} b_xi over the readings
+          auto wz = [&](T f, const Cx<T>& bp_, const Cx<T>& bm_, Cx<T>& WZ0, Cx<T>& WZ1) {
+            const T z1 = f * za[1], z3 = f * za[3], z5 = f * za[5], z7 = f * za[7];
+            WZ0 = Cx<T>{za[0] * bp_.re - z1 * bp_.im + za[2] * bm_.re - z3 * bm_.im,
+                        za[0] * bp_.im + z1 * bp_.re + za[2] * bm_.im + z3 * bm_.re};
+            WZ1 = Cx<T>{za[4] * bp_.re - z5 * bp_.im + za[6] * bm_.re - z7 * bm_.im,
+                        za[4] * bp_.im + z5 * bp_.re + za[6] * bm_.im + z7 * bm_.re};
+          };
+          Cx<T> WZ0, WZ1;
+          wz(f1, bp, bm, WZ0, WZ1);
+          if constexpr (CC) {
+            if (two) {
+              Cx<T> X0, X1;
+              wz(-f1, bp2, bm2, X0, X1);
+              WZ0.re += X0.re; WZ0.im += X0.im;
+              WZ1.re += X1.re; WZ1.im += X1.im;
+            }
+          }
 #pragma unroll
           for (int z = 0; z < NZ; ++z) {
             if (z < a.cnt[5]) {
@@ -730,14 +807,14 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
 // Fixed-order compensated sum of the block partials.  Block (set, v) sums value v over
 // the blocks of one set: each thread runs a Neumaier sum over a strided subset, then the
 // 256 partial pairs are merged pairwise in a fixed tree.  Output goes to out[set*NACC + v]
-// (mapped pinned host memory).
+// (mapped pinned host memory).  The partial rows hold the data blocks, then n_mc_sets runs of
+// nb_mc normalisation blocks (records 1, 2).
 
 __global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ partial, int nb_data, int nb_mc,
-                                                    int nv, double* __restrict__ out, double* __restrict__ out_dev,
-                                                    int first_set) {
+                                                    int n_mc_sets, int nv, double* __restrict__ out, int first_set) {
   const int set = first_set + (int)blockIdx.x / nv, v = blockIdx.x % nv;
-  const int nbt = nb_data + nb_mc;
-  const int b0 = set ? nb_data : 0;
+  const int64_t nbt = nb_data + (int64_t)n_mc_sets * nb_mc;   // row stride of the partials
+  const int b0 = set == 0 ? 0 : nb_data + (set - 1) * nb_mc;
   const int nb = set ? nb_mc : nb_data;
   const double* __restrict__ p = partial + (int64_t)v * nbt + b0;
   double s = 0.0, c = 0.0;
@@ -760,11 +837,7 @@ __global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ p
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double r = S[0] + Cc[0];
-    out[set * NACC + v] = r;
-    if (out_dev) out_dev[set * NACC + v] = r;
-  }
+  if (threadIdx.x == 0) out[set * NACC + v] = S[0] + Cc[0];
 }
 
 // ------------------------------------------------------------------ efficiency histogram
@@ -924,36 +997,48 @@ template hipError_t launch_invariants<double>(const InvArgs<double>&, hipStream_
 template <typename T, class Sh>
 hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  if (mode == MODE_GRAD) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_GRAD>), dim3(nblocks), dim3(256), 0, st, a);
-  else if (mode == MODE_NLL) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_NLL>), dim3(nblocks), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_DENSITY>), dim3(nblocks), dim3(256), 0, st, a);
+  const bool cc = a.tag != nullptr && mode != MODE_DENSITY;
+  if (mode == MODE_GRAD) {
+    if (cc) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_GRAD, true>), dim3(nblocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_GRAD, false>), dim3(nblocks), dim3(256), 0, st, a);
+  } else if (mode == MODE_NLL) {
+    if (cc) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_NLL, true>), dim3(nblocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_NLL, false>), dim3(nblocks), dim3(256), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_DENSITY, false>), dim3(nblocks), dim3(256), 0, st, a);
+  }
   return hipGetLastError();
 }
 // Blocks of the per-event kernel that can be resident on one compute unit at once (from its
 // register and LDS use), or 0 if the runtime cannot tell.
 template <typename T, class Sh>
-int amp_blocks_per_cu(int mode) {
+int amp_blocks_per_cu(int mode, bool cc) {
   int nb = 0;
   hipError_t e;
-  if (mode == MODE_GRAD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_GRAD>, 256, 0);
-  else if (mode == MODE_NLL) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_NLL>, 256, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_DENSITY>, 256, 0);
+  if (mode == MODE_GRAD)
+    e = cc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_GRAD, true>, 256, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_GRAD, false>, 256, 0);
+  else if (mode == MODE_NLL)
+    e = cc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_NLL, true>, 256, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_NLL, false>, 256, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_DENSITY, false>, 256, 0);
   return (e == hipSuccess && nb > 0) ? nb : 0;
 }
-template int amp_blocks_per_cu<float, ShapeSmall>(int);
-template int amp_blocks_per_cu<double, ShapeSmall>(int);
-template int amp_blocks_per_cu<float, ShapeFull>(int);
-template int amp_blocks_per_cu<double, ShapeFull>(int);
+template int amp_blocks_per_cu<float, ShapeSmall>(int, bool);
+template int amp_blocks_per_cu<double, ShapeSmall>(int, bool);
+template int amp_blocks_per_cu<float, ShapeFull>(int, bool);
+template int amp_blocks_per_cu<double, ShapeFull>(int, bool);
 
 template hipError_t launch_amp<float, ShapeSmall>(const AmpArgs<float, ShapeSmall>&, int, int, hipStream_t);
 template hipError_t launch_amp<double, ShapeSmall>(const AmpArgs<double, ShapeSmall>&, int, int, hipStream_t);
 template hipError_t launch_amp<float, ShapeFull>(const AmpArgs<float, ShapeFull>&, int, int, hipStream_t);
 template hipError_t launch_amp<double, ShapeFull>(const AmpArgs<double, ShapeFull>&, int, int, hipStream_t);
 
-hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int nv, double* out, double* out_dev,
+hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int n_mc_sets, int nv, double* out,
                                int first_set, int n_sets, hipStream_t st) {
-  if (first_set < 0 || n_sets < 1 || first_set + n_sets > 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(reduce_final, dim3(n_sets * nv), dim3(256), 0, st, partial, nb_data, nb_mc, nv, out, out_dev,
+  if (first_set < 0 || n_sets < 1 || n_mc_sets < 1 || n_mc_sets > 2 || first_set + n_sets > 1 + n_mc_sets)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(reduce_final, dim3(n_sets * nv), dim3(256), 0, st, partial, nb_data, nb_mc, n_mc_sets, nv, out,
                      first_set);
   return hipGetLastError();
 }

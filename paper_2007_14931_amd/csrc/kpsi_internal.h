@@ -73,6 +73,13 @@ template <typename T, class Sh> struct AmpArgs {
   // The sum comes from the normalisation launch's block partials (mc_part: values 0 and 1 of
   // mc_nb blocks, rows pstride apart), or, when mc_part is null, from norm_total (a reduced
   // record in device memory: the interference-matrix normalisation).
+  // Flavour-tagged events (text after Eq. 12), active when tag != null: data event i is read
+  // with phi -> tag[i] phi (weight keep = 1 - mistag) and, when mistag > 0, with -tag[i] phi
+  // (weight mistag); the normalisation events give record 1 (phi) and record 2 (-phi) from
+  // nb_mc blocks each.
+  const T* tag;
+  T mistag, keep;
+  int nb_mc;
   const T* eps_data;    // per-data-event efficiency, or null (1)
   const T* bkg_data;    // per-data-event background density, or null (signal only)
   const double* mc_part;
@@ -200,10 +207,11 @@ template <typename T> hipError_t launch_invariants(const InvArgs<T>& a, hipStrea
 template <typename T, class Sh>
 hipError_t launch_imatrix(const ImArgs<T, Sh>& a, int ncols, int nb, double* out, hipStream_t st);
 template <typename T, class Sh> hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st);
-template <typename T, class Sh> int amp_blocks_per_cu(int mode);
-// Fixed-order sums of the block partials of sets first_set .. first_set + n_sets - 1 into
-// out[set * NACC + v] (and, when out_dev != null, also into out_dev[set * NACC + v]).
-hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int nv, double* out, double* out_dev,
+template <typename T, class Sh> int amp_blocks_per_cu(int mode, bool cc);
+// Fixed-order sums of the block partials of records first_set .. first_set + n_sets - 1 into
+// out[set * NACC + v] (record 0: data blocks; records 1 .. n_mc_sets: runs of nb_mc
+// normalisation blocks).
+hipError_t launch_reduce_final(const double* partial, int nb_data, int nb_mc, int n_mc_sets, int nv, double* out,
                                int first_set, int n_sets, hipStream_t st);
 hipError_t launch_hist_lookup(const HistArgs& a, hipStream_t st);
 hipError_t launch_template(const TplArgs& a, hipStream_t st);

@@ -54,8 +54,14 @@ struct kpsi_ctx {
   double* partial = nullptr;
   size_t partial_cap = 0;       // in doubles
   double* red = nullptr;        // device view of red_host
-  double* red_host = nullptr;   // [2][NACC], mapped pinned host memory
+  double* red_host = nullptr;   // [3][NACC], mapped pinned host memory: data, normalisation,
+                                // and the normalisation read with phi reversed (flavour tags)
   double* red_dev = nullptr;    // [2][NACC] device copy of the normalisation record (mixture)
+  // flavour-tagged events (kpsi_set_flavour)
+  bool cc_on = false;
+  void* tag = nullptr;          // T array over the data set, +1 / -1
+  double mistag = 0.0;
+  int64_t ntag[2] = {0, 0};     // data events tagged +1, -1
   // signal + background mixture of Eq. 14 (kpsi_set_background)
   bool bkg_on = false;
   double purity = 1.0;
@@ -71,7 +77,7 @@ struct kpsi_ctx {
   int64_t t_n = 0;
   int ept_override = 0;
   int n_cu = 0;                                                   // compute units of the device
-  int blocks_per_cu[2][3] = {{-1, -1, -1}, {-1, -1, -1}};         // [shape][mode], -1: not queried
+  int blocks_per_cu[2][3][2] = {{{-1, -1}, {-1, -1}, {-1, -1}}, {{-1, -1}, {-1, -1}, {-1, -1}}};   // [shape][mode][cc]
   // interference-matrix cache of the normalisation sum (mode 0 off, 1 on, 2 auto)
   int cache_mode = 0;
   bool cache_valid = false;
@@ -268,8 +274,9 @@ kpsi_status ensure_partial(kpsi_ctx* c, size_t nblocks) {
 template <typename T, class Sh>
 int pick_ept(kpsi_ctx* c, int mode, int64_t nd, int64_t nm) {
   if (c->ept_override > 0) return c->ept_override;
-  int& bpc = c->blocks_per_cu[c->shape][mode];
-  if (bpc < 0) bpc = amp_blocks_per_cu<T, Sh>(mode);
+  const bool cc = c->cc_on && mode != MODE_DENSITY;
+  int& bpc = c->blocks_per_cu[c->shape][mode][cc ? 1 : 0];
+  if (bpc < 0) bpc = amp_blocks_per_cu<T, Sh>(mode, cc);
   const int64_t cap = (int64_t)(c->n_cu > 0 ? c->n_cu : 256) * (bpc > 0 ? bpc : 3);
   auto blocks = [&](int64_t ept) {
     const int64_t ch = (int64_t)BLOCK * ept;
@@ -582,7 +589,8 @@ void cached_norm_record(const kpsi_ctx* c, const double* par, double* rm) {
 // Decide whether this call uses the cache (building it when the policy says so).
 kpsi_status use_cache(kpsi_ctx* c, const double* par, bool* use) {
   *use = false;
-  if (c->cache_mode == 0) return KPSI_OK;
+  // the interference matrix holds the normalisation at +phi only
+  if (c->cache_mode == 0 || c->cc_on) return KPSI_OK;
   const std::vector<double> ls = lineshape_params(c, par);
   if (c->cache_valid && ls == c->cache_ls) { *use = true; c->cache_hits++; return KPSI_OK; }
   if (ls == c->last_ls) {
@@ -636,9 +644,17 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   // nbd + nbm blocks, data first); one reduction then writes the record of each set covered
   // (by the GPU straight into mapped pinned host memory).
   const int64_t nd = (which == 1) ? 0 : c->set[0].n, nm = (which == 0) ? 0 : c->set[1].n;
+  // flavour tags: the normalisation events run twice (records 1 and 2: phi and -phi)
+  const bool cc = c->cc_on && mode != MODE_DENSITY;
+  const int nmsets = cc ? 2 : 1;
+  if (cc) {
+    a.tag = (const T*)c->tag;
+    a.mistag = (T)c->mistag;
+    a.keep = (T)(1.0 - c->mistag);
+  }
   int chunk_d, chunk_m;
   if (!mix) {
-    chunk_d = chunk_m = BLOCK * pick_ept<T, Sh>(c, mode, nd, nm);
+    chunk_d = chunk_m = BLOCK * pick_ept<T, Sh>(c, mode, nd, nmsets * nm);
   } else {
     // Eq. 14: the data terms need the normalisation total, so the normalisation events run in
     // a launch of their own first, and the data launch sums their block partials (unless the
@@ -648,11 +664,12 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   }
   const int nbd = (int)((nd + chunk_d - 1) / chunk_d), nbm = (int)((nm + chunk_m - 1) / chunk_m);
   if (mode != MODE_DENSITY) {
-    kpsi_status st = ensure_partial(c, (size_t)(nbd + nbm));
+    kpsi_status st = ensure_partial(c, (size_t)(nbd + nmsets * nbm));
     if (st) return st;
   }
   a.partial = c->partial;
-  a.pstride = nbd + nbm;
+  a.pstride = nbd + nmsets * nbm;
+  a.nb_mc = nbm;
   auto launch = [&](const AmpArgs<T, Sh>& b, int nblocks) -> kpsi_status {
     hipError_t e = launch_amp<T, Sh>(b, mode, nblocks, c->stream);
     if (e != hipSuccess) return fail(c, KPSI_E_HIP, "amplitude kernel: %s", hipGetErrorString(e));
@@ -664,7 +681,7 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
     b.chunk = chunk_d;
     b.nb_data = nbd;
     b.poff = 0;
-    st = launch(b, nbd + nbm);
+    st = launch(b, nbd + nmsets * nbm);
   } else {
     if (nm > 0) {
       AmpArgs<T, Sh> b = a;
@@ -688,8 +705,8 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   if (st) return st;
   if (c->timing) hipEventRecord(c->ev1, c->stream);   // end of the per-event work
   if (mode != MODE_DENSITY) {
-    hipError_t e = launch_reduce_final(c->partial, nbd, nbm, nv, c->red, nullptr, nd > 0 ? 0 : 1,
-                                       (nd > 0) + (nm > 0), c->stream);
+    hipError_t e = launch_reduce_final(c->partial, nbd, nbm, nmsets, nv, c->red, nd > 0 ? 0 : 1,
+                                       (nd > 0) + (nm > 0) * nmsets, c->stream);
     if (e != hipSuccess) return fail(c, KPSI_E_HIP, "reduction kernel: %s", hipGetErrorString(e));
   }
   if (st) return st;
@@ -757,7 +774,7 @@ kpsi_status kpsi_create(int device, void* stream, kpsi_precision prec, kpsi_ctx*
     }
     c->own_stream = true;
   }
-  if (hipHostMalloc(&c->red_host, 2 * NACC * sizeof(double), hipHostMallocMapped) != hipSuccess ||
+  if (hipHostMalloc(&c->red_host, 3 * NACC * sizeof(double), hipHostMallocMapped) != hipSuccess ||
       hipHostGetDevicePointer((void**)&c->red, c->red_host, 0) != hipSuccess ||
       hipMalloc(&c->red_dev, 2 * NACC * sizeof(double)) != hipSuccess) {
     kpsi_destroy(c);
@@ -785,6 +802,7 @@ kpsi_status kpsi_destroy(kpsi_ctx* c) {
   if (c->red_dev) hipFree(c->red_dev);
   if (c->eps_data) hipFree(c->eps_data);
   if (c->bkg_data) hipFree(c->bkg_data);
+  if (c->tag) hipFree(c->tag);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -898,12 +916,21 @@ static void drop_background(kpsi_ctx* c) {
   c->bkg_on = false;
 }
 
+static void drop_flavour(kpsi_ctx* c) {
+  if (c->tag) hipFree(c->tag);
+  c->tag = nullptr;
+  c->cc_on = false;
+  c->mistag = 0.0;
+  c->ntag[0] = c->ntag[1] = 0;
+}
+
 static kpsi_status load_common(kpsi_ctx* c, kpsi_set set, int64_t n) {
   if (!c) return KPSI_E_ARG;
   if (set != KPSI_DATA && set != KPSI_NORM) return fail(c, KPSI_E_ARG, "unknown set");
   if (n <= 0) return fail(c, KPSI_E_ARG, "n must be positive");
   if (!c->has_model) return fail(c, KPSI_E_STATE, "set the model before loading events");
   drop_background(c);   // its per-event values belong to the previous events
+  if (set == KPSI_DATA) drop_flavour(c);
   return KPSI_OK;
 }
 
@@ -928,6 +955,7 @@ kpsi_status kpsi_set_background(kpsi_ctx* c, double purity, const double* eps_da
   hipSetDevice(c->device);
   drop_background(c);
   if (!b_data) return KPSI_OK;   // signal-only likelihood
+  if (c->cc_on) return fail(c, KPSI_E_UNSUPPORTED, "the background mixture and flavour tags cannot be combined");
   if (!b_norm) return fail(c, KPSI_E_ARG, "b_norm is NULL");
   if (!(purity > 0.0 && purity <= 1.0)) return fail(c, KPSI_E_ARG, "purity %g outside (0, 1]", purity);
   const int64_t nd = c->set[0].n, nm = c->set[1].n;
@@ -953,6 +981,30 @@ kpsi_status kpsi_set_background(kpsi_ctx* c, double purity, const double* eps_da
   c->purity = purity;
   c->bkg_coef = (1.0 - purity) / (nb * (double)nm);
   c->bkg_on = true;
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_set_flavour(kpsi_ctx* c, const double* tags, int64_t n, double mistag) {
+  if (!c) return KPSI_E_ARG;
+  hipSetDevice(c->device);
+  drop_flavour(c);
+  invalidate_cache(c);
+  if (!tags) return KPSI_OK;   // B0 only
+  if (c->bkg_on) return fail(c, KPSI_E_UNSUPPORTED, "the background mixture and flavour tags cannot be combined");
+  if (n != c->set[0].n || n <= 0) return fail(c, KPSI_E_ARG, "expected %lld tags (one per data event)", (long long)c->set[0].n);
+  if (!(mistag >= 0.0 && mistag <= 0.5)) return fail(c, KPSI_E_ARG, "mistag %g outside [0, 1/2]", mistag);
+  int64_t np = 0, nn = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (tags[i] == 1.0) ++np;
+    else if (tags[i] == -1.0) ++nn;
+    else return fail(c, KPSI_E_ARG, "tags[%lld] = %g is not +1 or -1", (long long)i, tags[i]);
+  }
+  kpsi_status st = upload_values(c, tags, n, &c->tag);
+  if (st) { drop_flavour(c); return st; }
+  c->mistag = mistag;
+  c->ntag[0] = np;
+  c->ntag[1] = nn;
+  c->cc_on = true;
   return KPSI_OK;
 }
 
@@ -1117,6 +1169,35 @@ kpsi_status kpsi_set_efficiency_hist(kpsi_ctx* c, const float* eff, const int nb
   return st;
 }
 
+// Normalisation term of the NLL from the normalisation records, and the factors that weight
+// their gradient accumulators.  Signal and mixture: 2 N_d ln(sum eps S / N_MC) from record 1,
+// gradient factor 2 W / sum eps S (W = N_d, or sum_i w_i S_i with the mixture).  Flavour
+// tags: 2 sum_q n_q ln N_q with N_q = (1 - w) I(q) + w I(-q), I(+) and I(-) from records 1
+// and 2.  Returns false when a normalisation is not positive (value then holds it).
+static bool norm_term(const kpsi_ctx* c, double wsum, double* value, double* c1, double* c2) {
+  const double* r1 = c->red_host + NACC;
+  const double nd = (double)c->set[0].n, nm = (double)c->set[1].n;
+  const double s1 = r1[0] + r1[1];
+  if (!c->cc_on) {
+    *value = s1;
+    if (!(s1 > 0.0)) return false;
+    *value = 2.0 * nd * std::log(s1 / nm);
+    *c1 = 2.0 * wsum / s1;
+    *c2 = 0.0;
+    return true;
+  }
+  const double* r2 = c->red_host + 2 * NACC;
+  const double ip = s1 / nm, im = (r2[0] + r2[1]) / nm, w = c->mistag;
+  const double np = (double)c->ntag[0], nn = (double)c->ntag[1];
+  const double Np = (1.0 - w) * ip + w * im, Nn = (1.0 - w) * im + w * ip;
+  *value = Np < Nn ? Np : Nn;
+  if (!(Np > 0.0) || !(Nn > 0.0)) return false;
+  *value = 2.0 * ((np > 0.0 ? np * std::log(Np) : 0.0) + (nn > 0.0 ? nn * std::log(Nn) : 0.0));
+  *c1 = 2.0 / nm * (np * (1.0 - w) / Np + nn * w / Nn);
+  *c2 = 2.0 / nm * (np * w / Np + nn * (1.0 - w) / Nn);
+  return true;
+}
+
 kpsi_status kpsi_nll(kpsi_ctx* c, const double* params, double* nll) {
   kpsi_status st = check_ready(c, params);
   if (st) return st;
@@ -1132,14 +1213,15 @@ kpsi_status kpsi_nll(kpsi_ctx* c, const double* params, double* nll) {
   st = dispatch(c, MODE_NLL, params, cached ? 0 : -1, nullptr);
   if (st) return st;
   const double* rd = c->red_host;
-  const double* rm = c->red_host + NACC;
-  const double nd = (double)c->set[0].n, nm = (double)c->set[1].n;
-  const double sm = rm[0] + rm[1];
-  if (rd[2] > 0.0 || !(sm > 0.0)) {
+  const double nd = (double)c->set[0].n;
+  double nt, c1, c2;
+  const bool ok = norm_term(c, nd, &nt, &c1, &c2);
+  if (rd[2] > 0.0 || !ok) {
     *nll = INFINITY;
-    return fail(c, KPSI_E_NONFINITE, "%.0f data events with non-positive density; normalisation %g", rd[2], sm);
+    return fail(c, KPSI_E_NONFINITE, "%.0f data events with non-positive density; normalisation %g", rd[2],
+                ok ? 1.0 : nt);
   }
-  *nll = -2.0 * (rd[0] + rd[1]) + 2.0 * nd * std::log(sm / nm);
+  *nll = -2.0 * (rd[0] + rd[1]) + nt;
   return KPSI_OK;
 }
 
@@ -1159,23 +1241,25 @@ kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, do
   if (st) return st;
   const double* rd = c->red_host;
   const double* rm = c->red_host + NACC;
-  const double nd = (double)c->set[0].n, nm = (double)c->set[1].n;
-  const double sm = rm[0] + rm[1];
+  const double* rm2 = c->red_host + 2 * NACC;
+  const double nd = (double)c->set[0].n;
   for (int i = 0; i < c->nparams; ++i) grad[i] = NAN;
-  if (rd[2] > 0.0 || !(sm > 0.0)) {
-    *nll = INFINITY;
-    return fail(c, KPSI_E_NONFINITE, "%.0f data events with non-positive density; normalisation %g", rd[2], sm);
-  }
-  *nll = -2.0 * (rd[0] + rd[1]) + 2.0 * nd * std::log(sm / nm);
-  // combined complex sensitivity G = -2 G_data + 2 W G_norm / sum(eps S), W = N_d (signal
-  // only) or sum_i w_i S_i (Eq. 14 mixture, w_i = p eps_i / t_i);
-  // dNLL/dr = 2 Re(e^{i phi} G), dNLL/dphi = -2 Im(H G)
+  // combined complex sensitivity G = -2 G_data + c1 G_norm1 (+ c2 G_norm2 with flavour tags):
+  // c1 = 2 W / sum(eps S), W = N_d (signal only) or sum_i w_i S_i (Eq. 14 mixture,
+  // w_i = p eps_i / t_i); dNLL/dr = 2 Re(e^{i phi} G), dNLL/dphi = -2 Im(H G)
   int N[5], NZ;
   shape_counts(c->shape, N, &NZ);
   int nkacc = 0;
   for (int j = 0; j < 5; ++j) nkacc += N[j] * (j == 0 ? 2 : 6);
   const double wsum = c->bkg_on ? rd[3 + nkacc + 4 * NZ + 2 * NFL] : nd;
-  const double fm = 2.0 * wsum / sm;
+  double nt, fm, fm2;
+  const bool ok = norm_term(c, wsum, &nt, &fm, &fm2);
+  if (rd[2] > 0.0 || !ok) {
+    *nll = INFINITY;
+    return fail(c, KPSI_E_NONFINITE, "%.0f data events with non-positive density; normalisation %g", rd[2],
+                ok ? 1.0 : nt);
+  }
+  *nll = -2.0 * (rd[0] + rd[1]) + nt;
   const int ncr = c->nparams - 2 * (int)c->res.size();
   for (size_t i = 0; i < c->res.size(); ++i) {
     const kpsi_resonance& r = c->res[i];
@@ -1189,8 +1273,8 @@ kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, do
     for (int l = 0; l < nl; ++l) {
       // K* spin >= 1 accumulators are lambda = -1, 0, +1; spin 0 has lambda = 0 only; Z has 0, +-1
       const int a = ao + 2 * l;
-      const double gr = -2.0 * kr * rd[a] + fm * km * rm[a];
-      const double gi = -2.0 * kr * rd[a + 1] + fm * km * rm[a + 1];
+      const double gr = -2.0 * kr * rd[a] + km * (fm * rm[a] + fm2 * rm2[a]);
+      const double gi = -2.0 * kr * rd[a + 1] + km * (fm * rm[a + 1] + fm2 * rm2[a + 1]);
       const double mag = p[2 * l], ph = p[2 * l + 1];
       const double cph = std::cos(ph), sph = std::sin(ph);
       grad[c->coff[i] + 2 * l] = 2.0 * (cph * gr - sph * gi);
@@ -1198,8 +1282,8 @@ kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, do
     }
     if (c->fslot[i] >= 0) {
       const int a = 3 + nkacc + 4 * NZ + 2 * c->fslot[i];
-      grad[ncr + 2 * i] = 2.0 * (-2.0 * rd[a] + fm * rm[a]);
-      grad[ncr + 2 * i + 1] = 2.0 * (-2.0 * rd[a + 1] + fm * rm[a + 1]);
+      grad[ncr + 2 * i] = 2.0 * (-2.0 * rd[a] + fm * rm[a] + fm2 * rm2[a]);
+      grad[ncr + 2 * i + 1] = 2.0 * (-2.0 * rd[a + 1] + fm * rm[a + 1] + fm2 * rm2[a + 1]);
     }
   }
   return KPSI_OK;

@@ -29,7 +29,7 @@ EXPORTS = [
     "kpsi_fit_default_options", "kpsi_migrad", "kpsi_hesse", "kpsi_set_norm_cache", "kpsi_norm_cache_stats",
     "kpsi_mlp_default_options", "kpsi_accept_labels", "kpsi_hist_efficiency", "kpsi_mlp_grad", "kpsi_mlp_train",
     "kpsi_mlp_eval", "kpsi_set_efficiency_mlp", "kpsi_fit_fractions", "kpsi_measure_peaks", "kpsi_set_background",
-    "kpsi_template_values",
+    "kpsi_template_values", "kpsi_set_flavour",
 ]
 MLP_NP = 4545
 
@@ -427,6 +427,15 @@ class Engine:
         tot = C.c_double()
         self._chk(self.L.kpsi_fit_fractions(self.h, _dp(p), _dp(ff), C.byref(tot)))
         return ff, tot.value
+
+    def set_flavour(self, tags, mistag: float = 0.0) -> None:
+        """Flavour tags of the data events (+1 B0, -1 conjugate decay; kpsi_set_flavour) and the
+        mistag fraction; tags None switches them off."""
+        if tags is None:
+            self._chk(self.L.kpsi_set_flavour(self.h, None, C.c_int64(0), C.c_double(0.0)))
+            return
+        t = _f64(tags)
+        self._chk(self.L.kpsi_set_flavour(self.h, _dp(t), C.c_int64(t.size), C.c_double(mistag)))
 
     def set_background(self, purity: float, eps_data, b_data, b_norm) -> None:
         """Eq. 14 mixture (kpsi_set_background); b_data None switches it off."""

@@ -1,0 +1,121 @@
+"""Flavour-tagged charge-conjugate likelihood with mistag (text after Eq. 12) in the HIP path
+against the FP64 oracle: NLL and gradient for random tags with and without mistag, the
+interference-matrix cache staying out of the way, the tag independence at w = 1/2, the
+reduction to the B0 likelihood, and the error paths of kpsi_set_flavour."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2007_14931_amd import kpsi
+from paper_2007_14931_amd import workloads as W
+
+K = W.KIN
+pytestmark = pytest.mark.gpu
+
+
+def _nll_close(v, ref, rel, nd):
+    """|v - ref| <= rel * max(|ref|, 2 nd): a relative error of `rel` in the per-event densities
+    where the two sums of the NLL cancel to a small value."""
+    return abs(v - ref) <= rel * max(abs(ref), 2.0 * nd)
+
+
+def _inputs(model, nd=5003, nm=15013, seed=81):
+    res = W.model(model)
+    data = W.neutral_events(nd, seed, peaked=True)
+    data[0] = np.clip(data[0], W.M_LO + 1e-6, W.M_HI - 1e-6)
+    mc = O.gen_phsp(K, seed + 1, nm, W.PHSP_WMAX)
+    eps_m = O.acceptance(W.acceptance_coefficients(), W.M_LO, W.M_HI, mc)
+    tag = np.where(np.random.default_rng(seed + 2).random(nd) < 0.45, 1.0, -1.0)
+    return res, data, mc, eps_m, tag
+
+
+def _engine(prec, res, data, mc, eps_m, floating=()):
+    e = kpsi.Engine(0, prec)
+    e.set_model(K, res)
+    if floating:
+        e.set_floating([1 if r.name in floating else 0 for r in res])
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    e.set_efficiency_values(eps_m)
+    return e
+
+
+@pytest.mark.parametrize("model,prec,w,tv,tg", [
+    ("full", "fp64", 0.0, 1e-10, 1e-9), ("full", "fp64", 0.06, 1e-10, 1e-9), ("kstar10", "fp64", 0.06, 1e-10, 1e-9),
+    ("full", "fp32", 0.0, 1e-6, 2e-5), ("full", "fp32", 0.06, 1e-6, 2e-5), ("kstar10", "fp32", 0.06, 1e-6, 2e-5)])
+def test_cc_nll_and_gradient_match_oracle(model, prec, w, tv, tg):
+    floating = ("K*(1410)", "Z(4430)") if model == "full" else ("K*(1410)",)
+    res, data, mc, eps_m, tag = _inputs(model)
+    e = _engine(prec, res, data, mc, eps_m, floating)
+    e.set_flavour(tag, w)
+    par = W.params(res, seed=83) + 0.04 * W.free_mask(res, floating)
+    dirs = np.flatnonzero(W.free_mask(res, floating))
+    st, ref, gref = O.nll_cc(K, res, par, data, tag, mc, w, eps_m, dirs)
+    assert st == 0
+    v, g = e.nll_and_grad(par)
+    nd = data.shape[1]
+    assert _nll_close(v, ref, tv, nd), (v, ref)
+    err = np.max(np.abs(g[dirs] - gref)) / np.max(np.abs(gref))
+    assert err < tg, err
+    assert _nll_close(e.nll(par), ref, tv, nd)
+
+
+def test_cc_ignores_the_interference_matrix_cache():
+    res, data, mc, eps_m, tag = _inputs("full", 3001, 9001)
+    e = _engine("fp64", res, data, mc, eps_m)
+    e.set_flavour(tag, 0.03)
+    e.set_norm_cache(1)
+    par = W.params(res, seed=84)
+    _, ref, _ = O.nll_cc(K, res, par, data, tag, mc, 0.03, eps_m)
+    assert e.nll(par) == pytest.approx(ref, rel=1e-10)
+    assert e.nll_and_grad(par)[0] == pytest.approx(ref, rel=1e-10)
+    assert e.norm_cache_stats()[0] == 0
+
+
+def test_cc_tags_off_and_b0_tags_give_the_signal_likelihood():
+    res, data, mc, eps_m, tag = _inputs("full", 3001, 9001)
+    e = _engine("fp64", res, data, mc, eps_m, ("Z(4430)",))
+    par = W.params(res, seed=85)
+    v0, g0 = e.nll_and_grad(par)
+    e.set_flavour(np.ones_like(tag), 0.0)
+    v1, g1 = e.nll_and_grad(par)
+    assert v1 == pytest.approx(v0, rel=1e-12)
+    fin = np.isfinite(g0)
+    np.testing.assert_allclose(g1[fin], g0[fin], rtol=1e-9, atol=1e-9 * np.abs(g0[fin]).max())
+    e.set_flavour(None)
+    assert e.nll(par) == pytest.approx(v0, rel=1e-14)
+
+
+def test_cc_half_mistag_makes_the_tags_irrelevant():
+    res, data, mc, eps_m, tag = _inputs("full", 3001, 9001)
+    e = _engine("fp64", res, data, mc, eps_m)
+    par = W.params(res, seed=86)
+    e.set_flavour(tag, 0.5)
+    v = e.nll(par)
+    e.set_flavour(-tag, 0.5)
+    assert e.nll(par) == pytest.approx(v, rel=1e-11)
+    e.set_flavour(tag, 0.1)
+    assert abs(e.nll(par) - v) > 1e-3
+
+
+def test_cc_errors_and_reload():
+    res, data, mc, eps_m, tag = _inputs("kstar10", 1001, 3001)
+    e = _engine("fp64", res, data, mc, eps_m)
+    with pytest.raises(kpsi.KpsiError):
+        e.set_flavour(tag[:-1], 0.0)
+    bad = tag.copy()
+    bad[3] = 0.5
+    with pytest.raises(kpsi.KpsiError):
+        e.set_flavour(bad, 0.0)
+    with pytest.raises(kpsi.KpsiError):
+        e.set_flavour(tag, 0.6)
+    e.set_flavour(tag, 0.02)
+    with pytest.raises(kpsi.KpsiError):
+        e.set_background(0.9, None, np.ones(data.shape[1]), np.ones(mc.shape[1]))
+    par = W.params(res, seed=87)
+    _, ref, _ = O.nll_cc(K, res, par, data, tag, mc, 0.02, eps_m)
+    assert e.nll(par) == pytest.approx(ref, rel=1e-10)
+    # loading new data events drops the tags
+    e.load(kpsi.DATA, data)
+    _, ref0, _ = O.nll(K, res, par, data, mc, eps=eps_m)
+    assert e.nll(par) == pytest.approx(ref0, rel=1e-10)
