@@ -192,6 +192,30 @@ __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
   c[col_at(19, e, ld)] = (T)(z1 * (pr * sa + pi_ * ca));
 }
 
+// ------------------------------------------------------------------ cross-lane exchange
+// One step of a transposed butterfly at distance D = 32 or 16 on a pair of per-lane values:
+// lanes whose bit log2(D) is clear end with (their lo, the partner's lo), the others with
+// (the partner's hi, their hi), so lo + hi is the pair sum each lane keeps.  v_permlane32_swap
+// exchanges lanes 32-63 of its first operand with lanes 0-31 of its second; v_permlane16_swap
+// exchanges the odd 16-lane rows of the first with the even rows of the second.
+template <int D> __device__ __forceinline__ void swap_halves(double& lo, double& hi) {
+  static_assert(D == 32 || D == 16, "lane-swap distance");
+  const uint64_t a = __builtin_bit_cast(uint64_t, lo), b = __builtin_bit_cast(uint64_t, hi);
+  const unsigned al = (unsigned)a, ah = (unsigned)(a >> 32), bl = (unsigned)b, bh = (unsigned)(b >> 32);
+  unsigned nl0, nl1, nh0, nh1;
+  if constexpr (D == 32) {
+    const auto l = __builtin_amdgcn_permlane32_swap(al, bl, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(ah, bh, false, false);
+    nl0 = l[0]; nl1 = l[1]; nh0 = h[0]; nh1 = h[1];
+  } else {
+    const auto l = __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+    nl0 = l[0]; nl1 = l[1]; nh0 = h[0]; nh1 = h[1];
+  }
+  lo = __builtin_bit_cast(double, ((uint64_t)nh0 << 32) | nl0);
+  hi = __builtin_bit_cast(double, ((uint64_t)nh1 << 32) | nl1);
+}
+
 // ------------------------------------------------------------------ compensated sums
 __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
   const double t = s + x;
@@ -761,21 +785,24 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     };
     // Transpose butterfly: after the step of width h, lane l keeps h values, each summed
     // with its partner lane's; after the last step lane l holds the wave sum of value l.
-    // The first step reads the typed accumulators directly so that at most 32 doubles are
-    // live at once.
+    // The steps of width 32 and 16 use the lane-swap instructions (swap_halves), the rest
+    // lane shuffles.  The first step reads the typed accumulators directly so that at most
+    // 32 doubles are live at once.
     double v[32];
-    {
-      const bool up = (lane >> 5) & 1;
 #pragma unroll
-      for (int i = 0; i < 32; ++i) {
-        const double lo = accv(i), hi = accv(i + 32);
-        const double keep = up ? hi : lo;
-        const double send = up ? lo : hi;
-        v[i] = keep + __shfl_xor(send, 32, 64);
-      }
+    for (int i = 0; i < 32; ++i) {
+      double lo = accv(i), hi = accv(i + 32);
+      swap_halves<32>(lo, hi);
+      v[i] = lo + hi;
     }
 #pragma unroll
-    for (int s = 4; s >= 0; --s) {
+    for (int i = 0; i < 16; ++i) {
+      double lo = v[i], hi = v[i + 16];
+      swap_halves<16>(lo, hi);
+      v[i] = lo + hi;
+    }
+#pragma unroll
+    for (int s = 3; s >= 0; --s) {
       const int half = 1 << s;
       const bool up = (lane >> s) & 1;
 #pragma unroll
