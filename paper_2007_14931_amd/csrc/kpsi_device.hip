@@ -831,10 +831,10 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
   }
 }
 
-// Fixed-order compensated sum of the block partials.  Block (set, v) sums value v over
-// the blocks of one set: each thread runs a Neumaier sum over a strided subset, then the
-// 256 partial pairs are merged pairwise in a fixed tree.  Output goes to out[set*NACC + v]
-// (mapped pinned host memory).  The partial rows hold the data blocks, then n_mc_sets runs of
+// Fixed-order compensated sum of the block partials.  Block (set, v) sums value v over the
+// blocks of one set: each thread runs a Neumaier sum over a strided subset, the pairs are merged
+// in a butterfly within each wavefront and the four wavefronts in order.  Output goes to
+// out[set*NACC + v] (mapped pinned host memory).  The partial rows hold the data blocks, then n_mc_sets runs of
 // nb_mc normalisation blocks (records 1, 2).
 
 __global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ partial, int nb_data, int nb_mc,
@@ -845,26 +845,22 @@ __global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ p
   const int nb = set ? nb_mc : nb_data;
   const double* __restrict__ p = partial + (int64_t)v * nbt + b0;
   double s = 0.0, c = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 256) {
-    const double x = p[b];
-    const double t = s + x;
-    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
-    s = t;
+  for (int b = threadIdx.x; b < nb; b += 256) neumaier(s, c, p[b]);
+  // butterfly of exact two-sum merges in each wavefront (every lane ends with the wavefront's
+  // total), then the four wavefronts in order
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) two_sum_merge(s, c, __shfl_xor(s, off, 64), __shfl_xor(c, off, 64));
+  __shared__ double S[4], Cc[4];
+  if ((threadIdx.x & 63) == 0) {
+    S[threadIdx.x >> 6] = s;
+    Cc[threadIdx.x >> 6] = c;
   }
-  __shared__ double S[256], Cc[256];
-  S[threadIdx.x] = s;
-  Cc[threadIdx.x] = c;
   __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (threadIdx.x < w) {
-      double a = S[threadIdx.x], ca = Cc[threadIdx.x];
-      two_sum_merge(a, ca, S[threadIdx.x + w], Cc[threadIdx.x + w]);
-      S[threadIdx.x] = a;
-      Cc[threadIdx.x] = ca;
-    }
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = S[0], tc = Cc[0];
+    for (int w = 1; w < 4; ++w) two_sum_merge(t, tc, S[w], Cc[w]);
+    out[set * NACC + v] = t + tc;
   }
-  if (threadIdx.x == 0) out[set * NACC + v] = S[0] + Cc[0];
 }
 
 // ------------------------------------------------------------------ efficiency histogram
