@@ -5,6 +5,7 @@
     python -m paper_2007_14931_amd.studies pulls         # seeded pseudo-experiments of the 1M-event fit
     python -m paper_2007_14931_amd.studies z_sensitivity # Z fit fractions: null test and positive control
     python -m paper_2007_14931_amd.studies real_life     # efficiency + 15% background (Eq. 14) vs ideal fit
+    python -m paper_2007_14931_amd.studies flavour_tags  # B0 + conjugate decays, 5% mistag, tagged fit
 
 Each prints one JSON line.  All events are synthetic, from the library's seeded generators:
 flat phase space, accept labels under the seeded analytic acceptance (the paper's
@@ -455,9 +456,79 @@ def real_life(args) -> dict:
             "real_minus_ideal_sigma_max": float(np.max(np.abs(x_r[free] - x_i[free]) / s_r))}
 
 
+def flavour_tags(args) -> dict:
+    """Flavour-tagged pseudo-data (text after Eq. 12): half of the events are B0 decays drawn
+    from S, half are conjugate decays drawn from S and mirrored in phi; each tag is flipped with
+    the mistag probability w = 0.05.  Fits: the tagged likelihood with w fixed (FP32 adjoint
+    MIGRAD, then an FP64 polish with HESSE), and, as a control, the same events all taken as
+    B0.  Reports the pulls against the generated point."""
+    import torch
+    res = W.model("full")
+    truth = W.params(res, 31)
+    w = 0.05
+    n_data, n_mc = int(args.data_events), int(args.norm_events) if args.norm_events else 2_000_000
+    stream = torch.cuda.current_stream().cuda_stream
+    gen = kpsi.Engine(0, "fp64", stream)
+    gen.set_model(W.KIN, res)
+    mc = gen.generate_phsp(7101, n_mc, W.PHSP_WMAX)
+    scan = gen.generate_phsp(7102, 1_000_000, W.PHSP_WMAX)
+    gen.load(kpsi.DATA, scan)
+    smax = 1.5 * float(gen.density(kpsi.DATA, truth).max())
+    n_b0 = n_data // 2
+    b0, _, _ = gen.generate_model(truth, 7103, n_b0, W.PHSP_WMAX, smax)
+    bb, _, _ = gen.generate_model(truth, 7104, n_data - n_b0, W.PHSP_WMAX, smax)
+    bb = bb.clone()
+    bb[3] = -bb[3]   # the conjugate decay's density is S(-phi)
+    data = torch.cat([b0, bb], dim=1).contiguous()
+    gen.close()
+    flavour = np.concatenate([np.ones(n_b0), -np.ones(n_data - n_b0)])
+    rng = np.random.Generator(np.random.PCG64(7105))
+    mistagged = rng.uniform(size=n_data) < w
+    tags = np.where(mistagged, -flavour, flavour)
+    mask = W.free_mask(res)
+    free = np.flatnonzero(mask)
+    ct = W.canonical(res, truth)
+    nc = W.n_params(res) - 2 * len(res)
+
+    def fit(tagged):
+        start = truth.copy()
+        out = None
+        for prec in ("fp32", "fp64"):
+            e = kpsi.Engine(0, prec, stream)
+            e.set_model(W.KIN, res)
+            e.load(kpsi.DATA, data)
+            e.load(kpsi.NORM, mc)
+            if tagged:
+                e.set_flavour(tags, w)
+            x, cov, r = e.migrad(start, mask)
+            e.close()
+            start = x
+            out = (W.canonical(res, x), np.sqrt(np.abs(np.diag(cov))), r)
+        return out
+
+    def pulls(x, s):
+        d = x[free] - ct[free]
+        for k, i in enumerate(free):
+            if i < nc and i % 2 == 1:
+                d[k] = math.remainder(d[k], 2 * math.pi)
+        return d / s
+
+    out = {"study": "flavour_tags", "data_events": n_data, "b0_events": n_b0, "mistag": w,
+           "mistagged_events": int(mistagged.sum()), "norm_events": n_mc, "free_params": int(mask.sum()),
+           "model": "10 K* + Z(4430)"}
+    for name, tagged in (("tagged_fit", True), ("untagged_control_fit", False)):
+        x, s, r = fit(tagged)
+        p = pulls(x, s)
+        out[name] = {"status": r.status, "wall_s": r.wall_seconds, "pull_mean": float(p.mean()),
+                     "pull_rms": float(np.sqrt((p ** 2).mean())), "pull_max_abs": float(np.max(np.abs(p)))}
+        log(f"{name}: {out[name]}")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["learned_eff", "large_fit", "pulls", "z_sensitivity", "real_life"])
+    ap.add_argument("study", choices=["learned_eff", "large_fit", "pulls", "z_sensitivity", "real_life",
+                                      "flavour_tags"])
     ap.add_argument("--train", type=int, default=5_000_000, help="labelled training events")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the large-fit event counts")
@@ -468,7 +539,7 @@ def main() -> int:
                     "(default: the workload's)")
     args = ap.parse_args()
     out = {"learned_eff": learned_eff, "large_fit": large_fit, "pulls": pulls,
-           "z_sensitivity": z_sensitivity, "real_life": real_life}[args.study](args)
+           "z_sensitivity": z_sensitivity, "real_life": real_life, "flavour_tags": flavour_tags}[args.study](args)
     print(json.dumps(out), flush=True)
     return 0
 
