@@ -274,6 +274,17 @@ kpsi_status kpsi_set_background(kpsi_ctx* ctx, double purity, const double* eps_
  * kpsi_set_background returns it while tags are set). */
 kpsi_status kpsi_set_flavour(kpsi_ctx* ctx, const double* tags, int64_t n, double mistag);
 
+/* ---------------------------------------------------------------- Gaussian constraints
+ * Gaussian constraints on fit parameters (Conclusion: applied when required): a factor
+ * N(p[index_k]; mean_k, sigma_k) per constraint in the likelihood, i.e.
+ *   sum_k ((p[index_k] - mean_k) / sigma_k)^2
+ * added to -2 ln L by kpsi_nll and kpsi_nll_and_grad (gradient 2 (p - mean) / sigma^2), and so
+ * seen by kpsi_migrad and kpsi_hesse.  index: positions in the canonical parameter vector;
+ * arrays of n (host, copied); n = 0 removes the constraints.  kpsi_set_model removes them.
+ * Errors: KPSI_E_ARG for an index out of range, sigma <= 0 or non-finite values, NULL arrays
+ * with n > 0; KPSI_E_STATE without a model. */
+kpsi_status kpsi_set_constraints(kpsi_ctx* ctx, int n, const int* index, const double* mean, const double* sigma);
+
 /* Per-event values of a 2D (mass variables) x 2D (angular variables) template, the form in
  * which the paper passes efficiency and background shapes to the fit: t_mass over
  * (m_Kpi in [m_K + m_pi, M_B - M_J/psi], cos theta_K* in [-1, 1]) with n_mass[0] x n_mass[1]

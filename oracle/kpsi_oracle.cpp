@@ -918,6 +918,26 @@ double oracle_acceptance(const double* coef, double m_lo, double m_hi, double m,
   return eps;
 }
 
+// Gaussian constraints on fit parameters (Conclusion: applied to fit parameters when required):
+// a factor prod_k N(p[idx_k]; mean_k, sigma_k) in the likelihood adds
+//   sum_k ((p[idx_k] - mean_k) / sigma_k)^2
+// to -2 ln L (up to a constant).  grad (length n_par, may be NULL) receives its gradient
+// 2 (p - mean) / sigma^2 at the constrained positions and 0 elsewhere.  Returns -1 on a bad
+// index or a non-positive sigma.
+int oracle_gauss_penalty(int n, const int* idx, const double* mean, const double* sigma, int n_par, const double* par,
+                         double* value, double* grad) {
+  double v = 0.0;
+  if (grad) for (int i = 0; i < n_par; ++i) grad[i] = 0.0;
+  for (int k = 0; k < n; ++k) {
+    if (idx[k] < 0 || idx[k] >= n_par || !(sigma[k] > 0.0)) return -1;
+    const double z = (par[idx[k]] - mean[k]) / sigma[k];
+    v += z * z;
+    if (grad) grad[idx[k]] += 2.0 * z / sigma[k];
+  }
+  *value = v;
+  return 0;
+}
+
 int oracle_max_threads(void) { return omp_get_max_threads(); }
 void oracle_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 

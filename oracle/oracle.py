@@ -331,3 +331,20 @@ def nll_cc(kind: dict, res, par, data, tag, mc, mistag: float, eps_mc=None, dirs
            mcols[0].size, *(_dp(c) for c in mcols), _dp(em) if em is not None else None, C.c_double(mistag),
            len(dirs_arr), dirs_arr.ctypes.data_as(C.POINTER(C.c_int)), C.byref(out), _dp(g))
     return st, out.value, (g[: len(dirs_arr)] if len(dirs_arr) else None)
+
+
+def gauss_penalty(idx, mean, sigma, par):
+    """Gaussian constraints: (sum_k ((p[idx_k] - mean_k)/sigma_k)^2, its gradient over par)."""
+    par = _f64(par)
+    ix = np.ascontiguousarray(idx, dtype=np.int32)
+    mu, sg = _f64(mean), _f64(sigma)
+    g = np.zeros(par.size)
+    v = C.c_double(0.0)
+    f = lib().oracle_gauss_penalty
+    dp = C.POINTER(C.c_double)
+    f.argtypes = [C.c_int, C.POINTER(C.c_int), dp, dp, C.c_int, dp, dp, dp]
+    f.restype = C.c_int
+    st = f(ix.size, ix.ctypes.data_as(C.POINTER(C.c_int)), _dp(mu), _dp(sg), par.size, _dp(par), C.byref(v), _dp(g))
+    if st != 0:
+        raise ValueError("bad constraint")
+    return v.value, g

@@ -57,6 +57,9 @@ struct kpsi_ctx {
   double* red_host = nullptr;   // [3][NACC], mapped pinned host memory: data, normalisation,
                                 // and the normalisation read with phi reversed (flavour tags)
   double* red_dev = nullptr;    // [2][NACC] device copy of the normalisation record (mixture)
+  // Gaussian constraints on parameters (kpsi_set_constraints): position, mean, sigma
+  std::vector<int> con_idx;
+  std::vector<double> con_mean, con_sigma;
   // flavour-tagged events (kpsi_set_flavour)
   bool cc_on = false;
   void* tag = nullptr;          // T array over the data set, +1 / -1
@@ -873,6 +876,9 @@ kpsi_status kpsi_set_model(kpsi_ctx* c, const kpsi_kinematics* kin, const kpsi_r
   for (int j = 0; j < 5; ++j) c->cnt[j] = counts[j];
   c->cnt[5] = nz;
   c->nparams = off + 2 * n_res;
+  c->con_idx.clear();   // constraint positions refer to the previous parameter vector
+  c->con_mean.clear();
+  c->con_sigma.clear();
   c->has_model = true;
   invalidate_cache(c);
   hipSetDevice(c->device);
@@ -1198,6 +1204,34 @@ static bool norm_term(const kpsi_ctx* c, double wsum, double* value, double* c1,
   return true;
 }
 
+kpsi_status kpsi_set_constraints(kpsi_ctx* c, int n, const int* index, const double* mean, const double* sigma) {
+  if (!c) return KPSI_E_ARG;
+  if (n < 0) return fail(c, KPSI_E_ARG, "negative constraint count");
+  if (n > 0 && (!index || !mean || !sigma)) return fail(c, KPSI_E_ARG, "NULL constraint arrays");
+  if (n > 0 && !c->has_model) return fail(c, KPSI_E_STATE, "no model set");
+  for (int k = 0; k < n; ++k) {
+    if (index[k] < 0 || index[k] >= c->nparams) return fail(c, KPSI_E_ARG, "constraint %d: index %d out of range", k, index[k]);
+    if (!(sigma[k] > 0.0) || !std::isfinite(sigma[k]) || !std::isfinite(mean[k]))
+      return fail(c, KPSI_E_ARG, "constraint %d: needs a finite mean and sigma > 0", k);
+  }
+  c->con_idx.assign(index, index + n);
+  c->con_mean.assign(mean, mean + n);
+  c->con_sigma.assign(sigma, sigma + n);
+  return KPSI_OK;
+}
+
+// Gaussian constraints: sum_k ((p - mean)/sigma)^2 added to -2 ln L, and 2 (p - mean)/sigma^2
+// to the gradient (grad may be null).
+static double add_constraints(const kpsi_ctx* c, const double* params, double* grad) {
+  double v = 0.0;
+  for (size_t k = 0; k < c->con_idx.size(); ++k) {
+    const double z = (params[c->con_idx[k]] - c->con_mean[k]) / c->con_sigma[k];
+    v += z * z;
+    if (grad) grad[c->con_idx[k]] += 2.0 * z / c->con_sigma[k];
+  }
+  return v;
+}
+
 kpsi_status kpsi_nll(kpsi_ctx* c, const double* params, double* nll) {
   kpsi_status st = check_ready(c, params);
   if (st) return st;
@@ -1221,7 +1255,7 @@ kpsi_status kpsi_nll(kpsi_ctx* c, const double* params, double* nll) {
     return fail(c, KPSI_E_NONFINITE, "%.0f data events with non-positive density; normalisation %g", rd[2],
                 ok ? 1.0 : nt);
   }
-  *nll = -2.0 * (rd[0] + rd[1]) + nt;
+  *nll = -2.0 * (rd[0] + rd[1]) + nt + add_constraints(c, params, nullptr);
   return KPSI_OK;
 }
 
@@ -1286,6 +1320,7 @@ kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, do
       grad[ncr + 2 * i + 1] = 2.0 * (-2.0 * rd[a + 1] + fm * rm[a + 1] + fm2 * rm2[a + 1]);
     }
   }
+  *nll += add_constraints(c, params, grad);
   return KPSI_OK;
 }
 

@@ -29,7 +29,7 @@ EXPORTS = [
     "kpsi_fit_default_options", "kpsi_migrad", "kpsi_hesse", "kpsi_set_norm_cache", "kpsi_norm_cache_stats",
     "kpsi_mlp_default_options", "kpsi_accept_labels", "kpsi_hist_efficiency", "kpsi_mlp_grad", "kpsi_mlp_train",
     "kpsi_mlp_eval", "kpsi_set_efficiency_mlp", "kpsi_fit_fractions", "kpsi_measure_peaks", "kpsi_set_background",
-    "kpsi_template_values", "kpsi_set_flavour",
+    "kpsi_template_values", "kpsi_set_flavour", "kpsi_set_constraints",
 ]
 MLP_NP = 4545
 
@@ -436,6 +436,16 @@ class Engine:
             return
         t = _f64(tags)
         self._chk(self.L.kpsi_set_flavour(self.h, _dp(t), C.c_int64(t.size), C.c_double(mistag)))
+
+    def set_constraints(self, index=(), mean=(), sigma=()) -> None:
+        """Gaussian constraints on parameters (kpsi_set_constraints); empty removes them."""
+        ix = np.ascontiguousarray(index, dtype=np.int32)
+        mu, sg = _f64(mean), _f64(sigma)
+        n = int(ix.size)
+        if n == 0:
+            self._chk(self.L.kpsi_set_constraints(self.h, 0, None, None, None))
+            return
+        self._chk(self.L.kpsi_set_constraints(self.h, n, ix.ctypes.data_as(C.POINTER(C.c_int)), _dp(mu), _dp(sg)))
 
     def set_background(self, purity: float, eps_data, b_data, b_norm) -> None:
         """Eq. 14 mixture (kpsi_set_background); b_data None switches it off."""

@@ -888,3 +888,27 @@ def test_cc_gradient_matches_central_differences():
         pm[i] -= h
         fd = (O.nll_cc(K, res, pp, data, tag, mc, 0.06, eps_m)[1] - O.nll_cc(K, res, pm, data, tag, mc, 0.06, eps_m)[1]) / (2 * h)
         assert g[5 * k] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(g).max())
+
+
+# ---------------------------------------------------------------- Gaussian constraints
+def test_gauss_penalty_is_minus_two_log_of_the_normal_density():
+    # a Gaussian factor N(p; mu, sigma) in the likelihood adds -2 ln N - ln(2 pi sigma^2) = z^2
+    rng = np.random.default_rng(90)
+    par = rng.normal(size=12)
+    idx = np.array([2, 7, 11])
+    mu = rng.normal(size=3)
+    sg = rng.uniform(0.1, 2.0, size=3)
+    v, g = O.gauss_penalty(idx, mu, sg, par)
+    ref = sum(-2.0 * stats.norm.logpdf(par[i], m, s) - math.log(2.0 * math.pi * s * s) for i, m, s in zip(idx, mu, sg))
+    assert v == pytest.approx(ref, rel=1e-12)
+    # k sigma away from the mean costs k^2; the gradient matches central differences
+    p2 = par.copy()
+    p2[idx] = mu + np.array([1.0, -2.0, 0.5]) * sg
+    assert O.gauss_penalty(idx, mu, sg, p2)[0] == pytest.approx(1.0 + 4.0 + 0.25, rel=1e-13)
+    for i in range(par.size):
+        h = 1e-6
+        pp, pm = par.copy(), par.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (O.gauss_penalty(idx, mu, sg, pp)[0] - O.gauss_penalty(idx, mu, sg, pm)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-6, abs=1e-8)
