@@ -97,9 +97,12 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
   for (int t = 0; t < NTILE; ++t) acc[t] = d4_t{0.0, 0.0, 0.0, 0.0};
 
   const int64_t ntiles = (a.n + 31) / 32;
+  // Every tile writes the same row positions (the columns of the model's components and
+  // derivatives), so the rows are cleared once: the padding and unused columns stay zero.  Rows
+  // of events past the end keep the previous tile's values but get weight 0.
+  for (int i = lane; i < 64 * LDX; i += 64) X[i] = T(0);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     // ---- rows of this tile: lane l < 32 fills rows 2l (xi = +1) and 2l + 1 (xi = -1)
-    for (int i = lane; i < 64 * LDX; i += 64) X[i] = T(0);
     __syncthreads();
     const int64_t e = tile * 32 + (lane & 31);
     if (lane < 32 && e < a.n) {
@@ -315,6 +318,23 @@ hipError_t launch_imatrix_c(const ImArgs<T, Sh>& a, int nb, double* out, hipStre
   hipLaunchKernelGGL(reduce_values, dim3(nv), dim3(256), 0, st, a.partial, nb, out);
   return hipGetLastError();
 }
+
+template <typename T, class Sh, int C> int imatrix_blocks_per_cu_c() {
+  int nb = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, imatrix_kernel<T, Sh, C>, 64, 0);
+  return (e == hipSuccess && nb > 0) ? nb : 0;
+}
+// Blocks (one wavefront each) of the interference-matrix kernel resident per compute unit.
+template <typename T, class Sh> int imatrix_blocks_per_cu(int ncols) {
+  if (ncols <= 16) return imatrix_blocks_per_cu_c<T, Sh, 16>();
+  if (ncols <= 32) return imatrix_blocks_per_cu_c<T, Sh, 32>();
+  if (ncols <= 64) return imatrix_blocks_per_cu_c<T, Sh, 64>();
+  return imatrix_blocks_per_cu_c<T, Sh, 80>();
+}
+template int imatrix_blocks_per_cu<float, ShapeSmall>(int);
+template int imatrix_blocks_per_cu<double, ShapeSmall>(int);
+template int imatrix_blocks_per_cu<float, ShapeFull>(int);
+template int imatrix_blocks_per_cu<double, ShapeFull>(int);
 
 template <typename T, class Sh>
 hipError_t launch_imatrix(const ImArgs<T, Sh>& a, int ncols, int nb, double* out, hipStream_t st) {

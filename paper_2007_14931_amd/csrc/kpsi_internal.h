@@ -206,6 +206,7 @@ hipError_t launch_hist_count(const HistCountArgs& a, hipStream_t st);
 template <typename T> hipError_t launch_invariants(const InvArgs<T>& a, hipStream_t st);
 template <typename T, class Sh>
 hipError_t launch_imatrix(const ImArgs<T, Sh>& a, int ncols, int nb, double* out, hipStream_t st);
+template <typename T, class Sh> int imatrix_blocks_per_cu(int ncols);
 template <typename T, class Sh> hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st);
 template <typename T, class Sh> int amp_blocks_per_cu(int mode, bool cc);
 // Fixed-order sums of the block partials of records first_set .. first_set + n_sets - 1 into

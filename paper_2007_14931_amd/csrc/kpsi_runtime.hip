@@ -434,7 +434,10 @@ kpsi_status gram_build_t(kpsi_ctx* c, const double* par, bool with_eps, bool wit
   if (!C) return fail(c, KPSI_E_UNSUPPORTED, "interference matrix of %d columns exceeds the compiled 80", ncols);
   const int NT = C / 16, NTILE = NT * (NT + 1) / 2, nv = NTILE * 256;
   const int64_t ntiles = (d.n + 31) / 32;
-  const int nb = (int)std::min<int64_t>(ntiles, 1024);
+  // one resident round of one-wavefront blocks (their LDS rows limit them per compute unit)
+  const int bpc = imatrix_blocks_per_cu<T, Sh>(ncols);
+  const int64_t cap = (int64_t)(c->n_cu > 0 ? c->n_cu : 256) * (bpc > 0 ? bpc : 4);
+  const int nb = (int)std::min<int64_t>(ntiles, cap);
   const size_t need = (size_t)nv * nb;
   if (need > c->cache_partial_cap) {
     if (c->cache_partial) hipFree(c->cache_partial);
