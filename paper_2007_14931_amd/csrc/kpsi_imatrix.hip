@@ -85,7 +85,9 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
   using namespace im;
   constexpr int NT = C / 16;
   constexpr int NTILE = NT * (NT + 1) / 2;
-  constexpr int LDX = C + 2;
+  // Odd row stride: the 32 lanes writing rows l (and l + 32) hit 32 different banks, and the
+  // four 16-lane groups reading rows 4s + k overlap in at most a few banks.
+  constexpr int LDX = C + 1;
   constexpr int NZ = Sh::NZ;
   // rows are staged at the context precision: FP32 values take half the LDS, so more blocks
   // (one wavefront each) fit per compute unit and row building overlaps other waves' MFMA
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
   // of events past the end keep the previous tile's values but get weight 0.
   for (int i = lane; i < 64 * LDX; i += 64) X[i] = T(0);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    // ---- rows of this tile: lane l < 32 fills rows 2l (xi = +1) and 2l + 1 (xi = -1)
+    // ---- rows of this tile: lane l < 32 fills rows l (xi = +1) and l + 32 (xi = -1)
     __syncthreads();
     const int64_t e = tile * 32 + (lane & 31);
     if (lane < 32 && e < a.n) {
@@ -116,10 +118,10 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
       const T zR = (a.rR * q) * (a.rR * q), zB = (a.rB * pB) * (a.rB * pB);
       const T qm = q * im_, pbm = pB * a.invMB, qq = q * q;
       const T hp = T(0.5) * (T(1) + cJ), hm = T(0.5) * (T(1) - cJ), s0 = sJ * T(0.70710678118654752440);
-      T* rp = X + (2 * lane) * LDX;
-      T* rm = X + (2 * lane + 1) * LDX;
-      Wr[2 * lane] = a.eps ? (double)a.eps[e] : 1.0;
-      Wr[2 * lane + 1] = Wr[2 * lane];
+      T* rp = X + lane * LDX;          // xi = +1
+      T* rm = X + (lane + 32) * LDX;   // xi = -1
+      Wr[lane] = a.eps ? (double)a.eps[e] : 1.0;
+      Wr[lane + 32] = Wr[lane];
       // write a component (or derivative) column: value A times angular pair (gp, gm)
       auto put = [&](int c, T Ar, T Ai, T gpr, T gpi, T gmr, T gmi) {
         rp[2 * c] = Ar * gpr - Ai * gpi;
@@ -242,8 +244,8 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
         }
       }
     } else if (lane < 32) {
-      Wr[2 * lane] = 0.0;
-      Wr[2 * lane + 1] = 0.0;
+      Wr[lane] = 0.0;
+      Wr[lane + 32] = 0.0;
     }
     __syncthreads();
     // ---- Gram tiles: A[i][k] = w_row X[row][16 ti + i], B[k][j] = X[row][16 tj + j],
