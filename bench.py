@@ -246,6 +246,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--ept", type=int, default=0, help="events per thread (0 = automatic)")
     ap.add_argument("--no-fit", action="store_true", help="skip the fit wall-time comparison")
+    ap.add_argument("--ext-steps", type=int, default=1000,
+                    help="timed calls per extension leg (mixture, flavour tags, LASS); 0 skips them")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain 512 MiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -376,7 +378,9 @@ def main() -> int:
                                                            else peaks["fp64_fma_tflops"])},
     }
     out["norm_cache"] = norm_cache_leg(eng, par, res, floating)
-    out["extensions"] = extension_legs(stream.cuda_stream, data, mc, par, res, floating)
+    if args.ext_steps > 0:
+        out["extensions"] = extension_legs(stream.cuda_stream, data, mc, par, res, floating, args.ext_steps,
+                                           max(10, args.ext_steps // 3))
     if not args.no_fit:
         out["fit"] = fit_comparison(make, truth, W.free_mask(res, floating), lambda p: W.canonical(res, p))
     if not args.no_cpu_baseline:
