@@ -104,10 +104,13 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
   // of events past the end keep the previous tile's values but get weight 0.
   for (int i = lane; i < 64 * LDX; i += 64) X[i] = T(0);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    // ---- rows of this tile: lane l < 32 fills rows l (xi = +1) and l + 32 (xi = -1)
+    // ---- rows of this tile: lane l fills row l, event l % 32 at xi = +1 (l < 32) or -1.  The
+    //      two lanes of an event both evaluate its amplitudes (the same instructions), and each
+    //      writes one row with its own angular factors.
     __syncthreads();
     const int64_t e = tile * 32 + (lane & 31);
-    if (lane < 32 && e < a.n) {
+    const bool xm = lane >= 32;   // xi = -1
+    if (e < a.n) {
       const T* col = a.cols;
       const int64_t ld = a.ld;
       const T m = col[col_at(0, e, ld)], q = col[col_at(1, e, ld)], pB = col[col_at(2, e, ld)];
@@ -118,20 +121,18 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
       const T zR = (a.rR * q) * (a.rR * q), zB = (a.rB * pB) * (a.rB * pB);
       const T qm = q * im_, pbm = pB * a.invMB, qq = q * q;
       const T hp = T(0.5) * (T(1) + cJ), hm = T(0.5) * (T(1) - cJ), s0 = sJ * T(0.70710678118654752440);
-      T* rp = X + lane * LDX;          // xi = +1
-      T* rm = X + (lane + 32) * LDX;   // xi = -1
+      T* rr = X + lane * LDX;
       Wr[lane] = a.eps ? (double)a.eps[e] : 1.0;
-      Wr[lane + 32] = Wr[lane];
-      // write a component (or derivative) column: value A times angular pair (gp, gm)
-      auto put = [&](int c, T Ar, T Ai, T gpr, T gpi, T gmr, T gmi) {
-        rp[2 * c] = Ar * gpr - Ai * gpi;
-        rp[2 * c + 1] = Ar * gpi + Ai * gpr;
-        rm[2 * c] = Ar * gmr - Ai * gmi;
-        rm[2 * c + 1] = Ar * gmi + Ai * gmr;
+      // write a component (or derivative) column: value A times this row's angular factor g
+      auto put = [&](int c, T Ar, T Ai, T gr, T gi) {
+        rr[2 * c] = Ar * gr - Ai * gi;
+        rr[2 * c + 1] = Ar * gi + Ai * gr;
       };
-      // angular pairs of lambda = +1, 0, -1 for d^J_{lambda 0} = 1
-      const T ep_r = cph * hp, ep_i = sph * hp, em_r = cph * hm, em_i = sph * hm;     // e^{+i phi} (hp, hm)
-      const T fp_r = cph * hm, fp_i = -sph * hm, fm_r = cph * hp, fm_i = -sph * hp;   // e^{-i phi} (hm, hp)
+      // e^{i lambda phi} d^1_{lambda xi}(theta_J) of this row for lambda = +1, 0, -1
+      // (xi = +1: (1+c)/2, s/sqrt2, (1-c)/2;  xi = -1: (1-c)/2, -s/sqrt2, (1+c)/2)
+      const T h1 = xm ? hm : hp, h2 = xm ? hp : hm, sx = xm ? -s0 : s0;
+      const T ep_r = cph * h1, ep_i = sph * h1;     // lambda = +1
+      const T fp_r = cph * h2, fp_i = -sph * h2;    // lambda = -1
       auto do_spin = [&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
         if constexpr (Sh::N[J] > 0) {
@@ -176,28 +177,28 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
               dGi = Ar * zi + Ai * zr;
             }
             if constexpr (J == 0) {
-              put(c0, Ar, Ai, s0, T(0), -s0, T(0));
+              put(c0, Ar, Ai, sx, T(0));
               if (rc.flt >= 0) {
                 const int dc = a.dcol[rc.flt];
-                put(dc, dMr, dMi, s0, T(0), -s0, T(0));
-                put(dc + 1, dGr, dGi, s0, T(0), -s0, T(0));
+                put(dc, dMr, dMi, sx, T(0));
+                put(dc + 1, dGr, dGi, sx, T(0));
               }
             } else {
-              // lambda = -1: -d10 e^{-i phi}(hm, hp); 0: d00 (s0, -s0); +1: d10 e^{+i phi}(hp, hm)
-              const T g1r = -a1 * fp_r, g1i = -a1 * fp_i, g2r = -a1 * fm_r, g2i = -a1 * fm_i;
-              const T h1r = a0 * s0, h2r = -a0 * s0;
-              const T k1r = a1 * ep_r, k1i = a1 * ep_i, k2r = a1 * em_r, k2i = a1 * em_i;
-              put(c0, Ar, Ai, g1r, g1i, g2r, g2i);
-              put(c0 + 1, Ar, Ai, h1r, T(0), h2r, T(0));
-              put(c0 + 2, Ar, Ai, k1r, k1i, k2r, k2i);
+              // lambda = -1: -d10 e^{-i phi} h2; 0: d00 (+-s0); +1: d10 e^{+i phi} h1
+              const T g1r = -a1 * fp_r, g1i = -a1 * fp_i;
+              const T h0 = a0 * sx;
+              const T k1r = a1 * ep_r, k1i = a1 * ep_i;
+              put(c0, Ar, Ai, g1r, g1i);
+              put(c0 + 1, Ar, Ai, h0, T(0));
+              put(c0 + 2, Ar, Ai, k1r, k1i);
               if (rc.flt >= 0) {
                 const int dc = a.dcol[rc.flt];
-                put(dc, dMr, dMi, g1r, g1i, g2r, g2i);
-                put(dc + 1, dMr, dMi, h1r, T(0), h2r, T(0));
-                put(dc + 2, dMr, dMi, k1r, k1i, k2r, k2i);
-                put(dc + 3, dGr, dGi, g1r, g1i, g2r, g2i);
-                put(dc + 4, dGr, dGi, h1r, T(0), h2r, T(0));
-                put(dc + 5, dGr, dGi, k1r, k1i, k2r, k2i);
+                put(dc, dMr, dMi, g1r, g1i);
+                put(dc + 1, dMr, dMi, h0, T(0));
+                put(dc + 2, dMr, dMi, k1r, k1i);
+                put(dc + 3, dGr, dGi, g1r, g1i);
+                put(dc + 4, dGr, dGi, h0, T(0));
+                put(dc + 5, dGr, dGi, k1r, k1i);
               }
             }
           }
@@ -212,9 +213,10 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
         if (a.cnt[5] > 0) {
           // (the angular columns za carry the Z barrier factor n_Z)
           const T mz2 = col[col_at(9, e, ld)], gz = col[col_at(11, e, ld)];
-          T za[8];
-#pragma unroll
-          for (int i = 0; i < 8; ++i) za[i] = col[col_at(12 + i, e, ld)];
+          // this row's Zang[l'][xi]: xi = +1 columns 12-13 (l' = 0) and 16-17 (l' = 1), xi = -1 14-15, 18-19
+          const int zo = xm ? 2 : 0;
+          const T z0r = col[col_at(12 + zo, e, ld)], z0i = col[col_at(13 + zo, e, ld)];
+          const T z1r = col[col_at(16 + zo, e, ld)], z1i = col[col_at(17 + zo, e, ld)];
           constexpr int zc0 = comp_base<Sh>(5);
 #pragma unroll
           for (int z = 0; z < NZ; ++z) {
@@ -224,8 +226,8 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
             const T inv = rcp_(dre * dre + dim * dim);
             const T sc = rc.K * inv;
             const T Ar = sc * dre, Ai = -sc * dim;
-            put(zc0 + 2 * z, Ar, Ai, za[0], za[1], za[2], za[3]);
-            put(zc0 + 2 * z + 1, Ar, Ai, za[4], za[5], za[6], za[7]);
+            put(zc0 + 2 * z, Ar, Ai, z0r, z0i);
+            put(zc0 + 2 * z + 1, Ar, Ai, z1r, z1i);
             if (rc.flt >= 0) {
               const T pr = rc.twoM, pim = -rc.dP * gz;
               const T Yr = (pr * dre + pim * dim) * inv, Yi = (pim * dre - pr * dim) * inv;
@@ -235,17 +237,16 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
               const T zr = zf * dim, zi = zf * dre;
               const T dGr = Ar * zr - Ai * zi, dGi = Ar * zi + Ai * zr;
               const int dc = a.dcol[rc.flt];
-              put(dc, dMr, dMi, za[0], za[1], za[2], za[3]);
-              put(dc + 1, dMr, dMi, za[4], za[5], za[6], za[7]);
-              put(dc + 2, dGr, dGi, za[0], za[1], za[2], za[3]);
-              put(dc + 3, dGr, dGi, za[4], za[5], za[6], za[7]);
+              put(dc, dMr, dMi, z0r, z0i);
+              put(dc + 1, dMr, dMi, z1r, z1i);
+              put(dc + 2, dGr, dGi, z0r, z0i);
+              put(dc + 3, dGr, dGi, z1r, z1i);
             }
           }
         }
       }
-    } else if (lane < 32) {
+    } else {
       Wr[lane] = 0.0;
-      Wr[lane + 32] = 0.0;
     }
     __syncthreads();
     // ---- Gram tiles: A[i][k] = w_row X[row][16 ti + i], B[k][j] = X[row][16 tj + j],
