@@ -134,7 +134,8 @@ kpsi_status kpsi_nll(kpsi_ctx* ctx, const double* params, double* nll);
 kpsi_status kpsi_nll_and_grad(kpsi_ctx* ctx, const double* params, double* nll, double* grad);
 
 /* Diagnostics (not on the fit path).  Per-event density S of a loaded set into a host
- * array of n doubles; per-event Z-chain observables into a host array of 5n doubles
+ * array of n doubles (S of Eq. 12 at the event as loaded: flavour tags and the background
+ * mixture are not applied); per-event Z-chain observables into a host array of 5n doubles
  * (m_Jpsi pi, cos theta_Z, cos theta~_J/psi, phi~, alpha). */
 kpsi_status kpsi_density(kpsi_ctx* ctx, kpsi_set set, const double* params, double* out);
 kpsi_status kpsi_invariants(kpsi_ctx* ctx, kpsi_set set, double* out);

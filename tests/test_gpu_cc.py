@@ -42,7 +42,8 @@ def _engine(prec, res, data, mc, eps_m, floating=()):
 
 @pytest.mark.parametrize("model,prec,w,tv,tg", [
     ("full", "fp64", 0.0, 1e-10, 1e-9), ("full", "fp64", 0.06, 1e-10, 1e-9), ("kstar10", "fp64", 0.06, 1e-10, 1e-9),
-    ("full", "fp32", 0.0, 1e-6, 2e-5), ("full", "fp32", 0.06, 1e-6, 2e-5), ("kstar10", "fp32", 0.06, 1e-6, 2e-5)])
+    ("full", "fp32", 0.0, 1e-6, 2e-5), ("full", "fp32", 0.06, 1e-6, 2e-5), ("kstar10", "fp32", 0.06, 1e-6, 2e-5),
+    ("lass_full2z", "fp64", 0.04, 1e-10, 1e-9)])
 def test_cc_nll_and_gradient_match_oracle(model, prec, w, tv, tg):
     floating = ("K*(1410)", "Z(4430)") if model == "full" else ("K*(1410)",)
     res, data, mc, eps_m, tag = _inputs(model)

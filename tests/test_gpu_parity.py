@@ -243,3 +243,25 @@ def test_threshold_p_wave_event_is_nonfinite_on_both_sides(prec):
     assert st_o == -5 and st == kpsi.KPSI_E_NONFINITE and v == math.inf
     st, v = e.nll_status(par, grad=True)
     assert st == kpsi.KPSI_E_NONFINITE and v == math.inf
+
+
+def test_autograd_function_returns_the_adjoint_gradient():
+    # the torch.autograd.Function binding: forward = one kpsi_nll_and_grad call, backward scales
+    # the stored gradient by the incoming one
+    import torch
+    e, res = _engine("full", "fp64", ("K*(1410)",))
+    data, mc = _sets(3001, 9001, seed=21)
+    data = _interior(data)
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    par = W.params(res, seed=22)
+    NLL = kpsi.make_nll_function(e)
+    p = torch.tensor(par, dtype=torch.float64, requires_grad=True)
+    v = NLL.apply(p)
+    (3.0 * v).backward()
+    v_ref, g_ref = e.nll_and_grad(par)
+    assert float(v) == pytest.approx(v_ref, rel=1e-14)
+    g = p.grad.numpy()
+    fin = np.isfinite(g_ref)
+    np.testing.assert_allclose(g[fin], 3.0 * g_ref[fin], rtol=1e-14)
+    assert np.all(np.isnan(g[~fin]))   # lineshape entries that are not floating stay NaN
