@@ -450,7 +450,9 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
           const T BR = bpoly<J>(zR), BB = bpoly<LB>(zB);
           const T rJ = rsq_(BR * BB);
           const T nJ = ipow<T, LB>(pbm) * ipow<T, J>(qm) * rJ;
-          const T gJ = qm * ipow<T, J>(qq) * rcp_(BR);
+          // 1/B_J(z_R) = rJ^2 B_LB(z_B): no second reciprocal
+          T gJ = qm;
+          if constexpr (J > 0) gJ = qm * ipow<T, J>(qq) * (rJ * rJ * BB);
           gJv[J] = gJ;
           nJv[J] = nJ;
           constexpr int sb = slot_base<Sh>(J);
