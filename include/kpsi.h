@@ -52,8 +52,9 @@ typedef enum {
   KPSI_E_STATE = -2,       /* model or event set missing, or a call made in the wrong order */
   KPSI_E_HIP = -3,         /* a HIP runtime call failed */
   KPSI_E_OOM = -4,         /* device or pinned-host allocation failed */
-  KPSI_E_NONFINITE = -5,   /* a data-event density is <= 0 or not finite, or the MC
-                              normalisation is <= 0; *nll is set to +inf */
+  KPSI_E_NONFINITE = -5,   /* a data-event density is <= 0 (in FP32: below the smallest
+                              normal float) or not finite, or the MC normalisation is <= 0;
+                              *nll is set to +inf */
   KPSI_E_UNSUPPORTED = -6  /* model outside what the compiled kernels cover */
 } kpsi_status;
 

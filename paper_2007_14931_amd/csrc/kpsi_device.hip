@@ -40,7 +40,13 @@ __device__ __forceinline__ double rsq_(double x) {
 }
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float log_(float x) { return __logf(x); }
+// natural log from the hardware base-2 logarithm, for normal inputs only: the FP32 path counts
+// an event whose density is below the smallest normal float as a bad event (pos_floor)
+__device__ __forceinline__ float log_(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+template <typename T> __device__ __forceinline__ constexpr T pos_floor() {
+  if constexpr (std::is_same_v<T, float>) return 1.17549435e-38f;
+  else return T(0);
+}
 __device__ __forceinline__ double log_(double x) { return log(x); }
 
 template <typename T> __device__ __forceinline__ T ldnt(const T* p) { return __builtin_nontemporal_load(p); }
@@ -63,11 +69,12 @@ template <typename P> __device__ __forceinline__ kconst_ptr<P> kernarg_laundered
 
 // ------------------------------------------------------------------ invariants
 // Columns written per event (type T, in groups of four at col_at(k, e, ld)):
-//   K* chain  : m, q(m), p_B(m), cos/sin theta_K*, cos/sin theta_J/psi, cos/sin phi
-//   Z chain   : m^2_Jpsi pi, nZ = (p_B/M_B) / sqrt(1 + (r_B p_B)^2), gZ = q/m_Jpsi pi,
-//               and the four complex angular factors Zang[l'][xi] of Eq. (10)
-//               (l' = 0 and l' = +-1 combined through Eq. 11, xi = +1, -1), each
-//               multiplied by nZ (the per-event factor common to every Z amplitude).
+//   K* chain  : m, q(m), p_B(m), cos/sin theta_K*, cos/sin theta_J/psi, cos/sin phi, and
+//               q/m (column 10)
+//   Z chain   : m^2_Jpsi pi (column 9), gZ = q/m_Jpsi pi (column 11), and the four complex
+//               angular factors Zang[l'][xi] of Eq. (10) (l' = 0 and l' = +-1 combined
+//               through Eq. 11, xi = +1, -1), each multiplied by
+//               nZ = (p_B/M_B) / sqrt(1 + (r_B p_B)^2), the factor common to every Z amplitude.
 // All arithmetic in double; stored in T.
 template <typename T>
 __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
@@ -100,6 +107,7 @@ __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
   c[col_at(6, e, ld)] = (T)sJ;
   c[col_at(7, e, ld)] = (T)cph;
   c[col_at(8, e, ld)] = (T)sph;
+  c[col_at(10, e, ld)] = (T)(q / m);
   if (!a.with_z && !a.diag) return;
 
   // J/psi rest frame, reached by a boost along z from the B frame, in which the K pi
@@ -171,7 +179,6 @@ __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
   const double zb = a.rB * pbz * a.rB * pbz;
   const double nZ = (pbz / mB) / sqrt(1.0 + zb);
   c[col_at(9, e, ld)] = (T)mz2;
-  c[col_at(10, e, ld)] = (T)nZ;
   c[col_at(11, e, ld)] = (T)(qz / mz);
   // Angular factors of Eq. (10): d^1_{0l'}(theta_Z) e^{i l' phi~} d^1_{l' xi}(theta~) e^{i xi alpha},
   // times nZ
@@ -415,13 +422,11 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     const V4 g0 = ldoff(gb, ob4), g1 = ldoff(gb + ld, ob4), g2 = ldoff(gb + 2 * ld, ob4);
     const T m = g0.x, q = g0.y, pB = g0.z, cK = g0.w;
     const T sK = g1.x, cJ = g1.y, sJ = g1.z, cph = g1.w;
-    const T sph = g2.x;
+    const T sph = g2.x, qm = g2.z;   // q/m from the event columns
 
     const T m2 = m * m;
-    const T im = rcp_(m);
     const T zR = (ka.rR * q) * (ka.rR * q);
     const T zB = (ka.rB * pB) * (ka.rB * pB);
-    const T qm = q * im;
     const T pbm = pB * ka.invMB;
     const T qq = q * q;
 
@@ -551,7 +556,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     Cx<T> T0k{T(0), T(0)}, T1k{T(0), T(0)};   // Z coupling sums, kept for a second reading
     if constexpr (NZ > 0) {
       if (a.cnt[5] > 0) {
-        const T mz2 = g2.y;   // (g2.z holds n_Z, already in the angular columns)
+        const T mz2 = g2.y;
         gzv = g2.w;
         const V4 g3 = ldoff(gb + 3 * ld, ob4), g4 = ldoff(gb + 4 * ld, ob4);
         za[0] = g3.x; za[1] = g3.y; za[2] = g3.z; za[3] = g3.w;
@@ -599,23 +604,23 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
           }
           const T S2 = ap2.re * ap2.re + ap2.im * ap2.im + am2.re * am2.re + am2.im * am2.im;
           arg = fma_(a.keep, S, a.mistag * S2);
-          if (!(arg > T(0)) || !(arg < T(INFINITY))) { nbad += 1.f; continue; }
+          if (!(arg > pos_floor<T>()) || !(arg < T(INFINITY))) { nbad += 1.f; continue; }
           const T r = rcp_(arg);
           w = a.keep * r;
           w2 = a.mistag * r;
         } else {
-          if (!(S > T(0)) || !(S < T(INFINITY))) { nbad += 1.f; continue; }
+          if (!(S > pos_floor<T>()) || !(S < T(INFINITY))) { nbad += 1.f; continue; }
           w = rcp_(S);
         }
       } else if (mix) {
         // Eq. 14: t = p eps S + k b; d ln t / dS = p eps / t
         const T pe = a.purity * (a.eps_data ? ldoff(a.eps_data + e0, ob) : T(1));
         arg = fma_(pe, S, kb * ldoff(a.bkg_data + e0, ob));
-        if (!(arg > T(0)) || !(arg < T(INFINITY))) { nbad += 1.f; continue; }
+        if (!(arg > pos_floor<T>()) || !(arg < T(INFINITY))) { nbad += 1.f; continue; }
         w = pe * rcp_(arg);
         ws += (A_t)(w * S);
       } else {
-        if (!(S > T(0)) || !(S < T(INFINITY))) { nbad += 1.f; continue; }
+        if (!(S > pos_floor<T>()) || !(S < T(INFINITY))) { nbad += 1.f; continue; }
         w = rcp_(S);
       }
       const double x = (double)log_(arg);
