@@ -64,18 +64,36 @@ def cpu_baseline(res, par, floating, n_data: int, n_mc: int, seconds: float = 15
     nd_s, nm_s = 2000, 4000
     data = W.neutral_events(nd_s, 91, peaked=True)
     mc = O.gen_phsp(K, 92, nm_s, W.PHSP_WMAX)
+    scale = (n_data + n_mc) / (nd_s + nm_s)
+    cores = O.max_threads()
+    O.nll(K, res, par, data, mc, dirs=dirs)   # warm-up
     t0 = time.perf_counter()
-    reps = 0
+    times = []
     while True:
-        st, v, g = O.nll(K, res, par, data, mc, dirs=dirs)
-        reps += 1
+        t1 = time.perf_counter()
+        O.nll(K, res, par, data, mc, dirs=dirs)
+        times.append(time.perf_counter() - t1)
         if time.perf_counter() - t0 > seconds:
             break
-    dt = (time.perf_counter() - t0) / reps
-    scale = (n_data + n_mc) / (nd_s + nm_s)
-    return {"value": 1.0 / (dt * scale), "unit": "NLL+grad evals/s", "cores": O.max_threads(), "kind": "oracle",
+    dt = float(np.mean(times))
+    med = float(np.median(times))
+    # the same oracle on one core: one warm-up, then the median of five evaluations
+    O.set_threads(1)
+    try:
+        O.nll(K, res, par, data, mc, dirs=dirs)
+        one = []
+        for _ in range(5):
+            t1 = time.perf_counter()
+            O.nll(K, res, par, data, mc, dirs=dirs)
+            one.append(time.perf_counter() - t1)
+    finally:
+        O.set_threads(cores)
+    one_med = float(np.median(one))
+    return {"value": 1.0 / (dt * scale), "unit": "NLL+grad evals/s", "cores": cores, "kind": "oracle",
+            "median_value": 1.0 / (med * scale), "one_core_value": 1.0 / (one_med * scale),
             "sample": f"{nd_s} data + {nm_s} normalisation events, {len(dirs)} gradient directions, "
-                      f"{reps} evaluations in {dt * reps:.1f} s, scaled by {scale:.0f} to the full workload"}
+                      f"{len(times)} evaluations in {sum(times):.1f} s on {cores} threads after one warm-up "
+                      f"(one_core_value: median of 5 on one thread), scaled by {scale:.0f} to the full workload"}
 
 
 def fit_comparison(make, truth, mask, canonical_fn) -> dict:
@@ -325,11 +343,16 @@ def main() -> int:
     eng.set_timing(TIMING_EVERY)
     eng.timing(reset=True)
     torch.cuda.synchronize()
+    stamps = np.empty(args.steps + 1)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        v, g = eng.nll_and_grad(par)
+    stamps[0] = t0
+    for i in range(args.steps):
+        v, g = eng.nll_and_grad(par)   # returns after the call's stream synchronisation
+        stamps[i + 1] = time.perf_counter()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    host_med_ms = float(np.median(np.diff(stamps))) * 1e3
+    kmed = eng.timing_median()
     kms, kn = eng.timing(reset=True)
     eng.set_timing(False)
     ms_step = wall / args.steps * 1e3
@@ -376,6 +399,9 @@ def main() -> int:
                    "reductions": "f64 compensated"},
         "events_per_s": n_ev / (kernel_ms * 1e-3),
         "kernel_ms": kernel_ms,
+        "kernel_ms_median": kmed,
+        "host_ms_median": host_med_ms,
+        "timed_kernel_calls": kn,
         "nll": v,
         "other_precision": {"precision": other, "ms_per_step": ms2, "kernel_ms": k2 / max(kn2, 1),
                             "evals_per_s": 1e3 / ms2, "nll": v2, "rel_nll_diff": abs(v2 - v) / abs(v)},

@@ -161,6 +161,9 @@ kpsi_status kpsi_generate_model(kpsi_ctx* ctx, const double* params, uint64_t se
  * KPSI_E_ARG if every < 0. */
 kpsi_status kpsi_set_timing(kpsi_ctx* ctx, int every);
 kpsi_status kpsi_timing(kpsi_ctx* ctx, double* kernel_ms, int64_t* n_calls, int reset);
+/* Median kernel milliseconds of the timed calls since the last reset (the first 65536 of them);
+ * NaN when none was timed.  kernel_ms: one double (host, caller-owned).  KPSI_E_ARG for NULL. */
+kpsi_status kpsi_timing_median(kpsi_ctx* ctx, double* kernel_ms);
 
 /* ---------------------------------------------------------------- fit driver
  * Variable-metric minimisation (MINUIT MIGRAD style: BFGS update of the inverse Hessian,

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -31,6 +32,7 @@ struct DevSet {
 };
 
 std::string g_create_error;
+constexpr size_t kTimingSamples = 65536;   // timed kernel durations kept for the median
 
 }  // namespace
 
@@ -78,6 +80,7 @@ struct kpsi_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double t_ms = 0.0;
   int64_t t_n = 0;
+  std::vector<float> t_samples;  // the first kTimingSamples timed durations since the last reset
   int ept_override = 0;
   int n_cu = 0;                                                   // compute units of the device
   int blocks_per_cu[2][3][2] = {{{-1, -1}, {-1, -1}, {-1, -1}}, {{-1, -1}, {-1, -1}, {-1, -1}}};   // [shape][mode][cc]
@@ -720,7 +723,11 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   if (c->timing) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) { c->t_ms += ms; c->t_n += 1; }
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) {
+      c->t_ms += ms;
+      c->t_n += 1;
+      if (c->t_samples.size() < kTimingSamples) c->t_samples.push_back(ms);
+    }
   }
   return KPSI_OK;
 }
@@ -1544,7 +1551,17 @@ kpsi_status kpsi_timing(kpsi_ctx* c, double* ms, int64_t* n, int reset) {
   if (!c) return KPSI_E_ARG;
   if (ms) *ms = c->t_ms;
   if (n) *n = c->t_n;
-  if (reset) { c->t_ms = 0.0; c->t_n = 0; }
+  if (reset) { c->t_ms = 0.0; c->t_n = 0; c->t_samples.clear(); }
+  return KPSI_OK;
+}
+
+kpsi_status kpsi_timing_median(kpsi_ctx* c, double* ms) {
+  if (!c || !ms) return KPSI_E_ARG;
+  std::vector<float> v = c->t_samples;
+  if (v.empty()) { *ms = NAN; return KPSI_OK; }
+  std::sort(v.begin(), v.end());
+  const size_t h = v.size() / 2;
+  *ms = (v.size() & 1) ? v[h] : 0.5 * ((double)v[h - 1] + (double)v[h]);
   return KPSI_OK;
 }
 

@@ -25,7 +25,7 @@ EXPORTS = [
     "kpsi_create", "kpsi_destroy", "kpsi_set_model", "kpsi_n_params", "kpsi_set_floating", "kpsi_load_events",
     "kpsi_load_events_device", "kpsi_set_efficiency_flat", "kpsi_set_efficiency_values", "kpsi_set_efficiency_hist",
     "kpsi_nll", "kpsi_nll_and_grad", "kpsi_density", "kpsi_invariants", "kpsi_generate_phsp", "kpsi_generate_model",
-    "kpsi_set_timing", "kpsi_timing", "kpsi_set_events_per_thread", "kpsi_last_error",
+    "kpsi_set_timing", "kpsi_timing", "kpsi_timing_median", "kpsi_set_events_per_thread", "kpsi_last_error",
     "kpsi_fit_default_options", "kpsi_migrad", "kpsi_hesse", "kpsi_set_norm_cache", "kpsi_norm_cache_stats",
     "kpsi_mlp_default_options", "kpsi_accept_labels", "kpsi_hist_efficiency", "kpsi_mlp_grad", "kpsi_mlp_train",
     "kpsi_mlp_eval", "kpsi_set_efficiency_mlp", "kpsi_fit_fractions", "kpsi_measure_peaks", "kpsi_set_background",
@@ -114,6 +114,7 @@ def lib() -> C.CDLL:
                                           C.POINTER(i64), C.POINTER(i64)]
         L.kpsi_set_timing.argtypes = [vp, C.c_int]
         L.kpsi_timing.argtypes = [vp, dp, C.POINTER(i64), C.c_int]
+        L.kpsi_timing_median.argtypes = [vp, dp]
         L.kpsi_set_events_per_thread.argtypes = [vp, C.c_int]
         L.kpsi_fit_default_options.argtypes = [C.POINTER(FitOptions)]
         L.kpsi_migrad.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(FitOptions), C.POINTER(FitResult), dp]
@@ -315,6 +316,12 @@ class Engine:
         ms, n = C.c_double(), C.c_int64()
         self._chk(self.L.kpsi_timing(self.h, C.byref(ms), C.byref(n), 1 if reset else 0))
         return ms.value, n.value
+
+    def timing_median(self) -> float:
+        """Median kernel milliseconds of the timed calls since the last reset (NaN if none)."""
+        ms = C.c_double()
+        self._chk(self.L.kpsi_timing_median(self.h, C.byref(ms)))
+        return ms.value
 
     def fit_options(self, **kw) -> FitOptions:
         o = FitOptions()
