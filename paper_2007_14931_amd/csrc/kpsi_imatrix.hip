@@ -29,6 +29,8 @@ __device__ __forceinline__ double rcp_(double x) {
   return __builtin_fma(r, e, r);
 }
 __device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ double rsq_(double x) {
   double r = __builtin_amdgcn_rsq(x);
   double h = 0.5 * x;
@@ -85,14 +87,18 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
   using namespace im;
   constexpr int NT = C / 16;
   constexpr int NTILE = NT * (NT + 1) / 2;
-  // Odd row stride: the 32 lanes writing rows l (and l + 32) hit 32 different banks, and the
-  // four 16-lane groups reading rows 4s + k overlap in at most a few banks.
-  constexpr int LDX = C + 1;
   constexpr int NZ = Sh::NZ;
-  // rows are staged at the context precision: FP32 values take half the LDS, so more blocks
-  // (one wavefront each) fit per compute unit and row building overlaps other waves' MFMA
-  __shared__ T X[64 * LDX];
-  __shared__ double Wr[64];
+  // Rows are staged at the context precision in dynamic LDS sized for the columns in use (the
+  // padded width C is only the MFMA tiling): FP32 rows of the 76-column benchmark model take
+  // 19.5 KB, so eight one-wavefront blocks fit per compute unit (two per SIMD), and one wave's
+  // row building overlaps the other's matrix work.  The row stride LDX = ncols + 1 is odd:
+  // the 32 lanes writing rows l (and l + 32) hit 32 different banks.  Column ncols of every
+  // row is never written and stays zero; the matrix phase reads it in place of the padded
+  // columns ncols .. C - 1.  Each row is scaled by sqrt(eps) of its event, so the Gram product
+  // of the rows with themselves carries the weight eps once.
+  extern __shared__ double im_smem[];
+  T* X = reinterpret_cast<T*>(im_smem);
+  const int LDX = a.ncols + 1;
   const int lane = threadIdx.x;
   d4_t acc[NTILE];
 #pragma unroll
@@ -100,29 +106,49 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
 
   const int64_t ntiles = (a.n + 31) / 32;
   // Every tile writes the same row positions (the columns of the model's components and
-  // derivatives), so the rows are cleared once: the padding and unused columns stay zero.  Rows
-  // of events past the end keep the previous tile's values but get weight 0.
+  // derivatives), so the rows are cleared once: the padding and unused columns stay zero.
   for (int i = lane; i < 64 * LDX; i += 64) X[i] = T(0);
+
+  // The event columns of this lane's event in the next tile are fetched before the matrix phase
+  // of the current one, so their latency hides behind it.  Column groups of four (K* chain:
+  // 0-11; Z chain: 12-19, present when the model has Z states).
+  using V4 = T __attribute__((ext_vector_type(4)));
+  const V4* __restrict__ gcol = reinterpret_cast<const V4*>(a.cols);
+  const int64_t ld = a.ld;
+  const bool zon = NZ > 0 && a.cnt[5] > 0;
+  V4 g0{}, g1{}, g2{}, g3{}, g4{};
+  T wv = T(0);
+  auto fetch = [&](int64_t tile) {
+    const int64_t e = tile * 32 + (lane & 31);
+    if (tile < ntiles && e < a.n) {
+      g0 = gcol[e];
+      g1 = gcol[ld + e];
+      g2 = gcol[2 * ld + e];
+      if (zon) {
+        g3 = gcol[3 * ld + e];
+        g4 = gcol[4 * ld + e];
+      }
+      wv = a.eps ? a.eps[e] : T(1);
+    }
+  };
+  fetch(blockIdx.x);
+
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     // ---- rows of this tile: lane l fills row l, event l % 32 at xi = +1 (l < 32) or -1.  The
     //      two lanes of an event both evaluate its amplitudes (the same instructions), and each
     //      writes one row with its own angular factors.
-    __syncthreads();
     const int64_t e = tile * 32 + (lane & 31);
     const bool xm = lane >= 32;   // xi = -1
+    T* rr = X + lane * LDX;
     if (e < a.n) {
-      const T* col = a.cols;
-      const int64_t ld = a.ld;
-      const T m = col[col_at(0, e, ld)], q = col[col_at(1, e, ld)], pB = col[col_at(2, e, ld)];
-      const T cK = col[col_at(3, e, ld)], sK = col[col_at(4, e, ld)];
-      const T cJ = col[col_at(5, e, ld)], sJ = col[col_at(6, e, ld)];
-      const T cph = col[col_at(7, e, ld)], sph = col[col_at(8, e, ld)];
-      const T m2 = m * m, im_ = rcp_(m);
+      const T m = g0.x, q = g0.y, pB = g0.z, cK = g0.w;
+      const T sK = g1.x, cJ = g1.y, sJ = g1.z, cph = g1.w;
+      const T sph = g2.x, qm = g2.z;   // column 10: q/m
+      const T sw = sqrt_(wv);
+      const T m2 = m * m;
       const T zR = (a.rR * q) * (a.rR * q), zB = (a.rB * pB) * (a.rB * pB);
-      const T qm = q * im_, pbm = pB * a.invMB, qq = q * q;
+      const T pbm = pB * a.invMB, qq = q * q;
       const T hp = T(0.5) * (T(1) + cJ), hm = T(0.5) * (T(1) - cJ), s0 = sJ * T(0.70710678118654752440);
-      T* rr = X + lane * LDX;
-      Wr[lane] = a.eps ? (double)a.eps[e] : 1.0;
       // write a component (or derivative) column: value A times this row's angular factor g
       auto put = [&](int c, T Ar, T Ai, T gr, T gi) {
         rr[2 * c] = Ar * gr - Ai * gi;
@@ -138,7 +164,8 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
         if constexpr (Sh::N[J] > 0) {
           constexpr int LB = (J == 0) ? 1 : J - 1;
           const T BR = bpoly<J>(zR), BB = bpoly<LB>(zB);
-          const T nJ = ipow<T, LB>(pbm) * ipow<T, J>(qm) * rsq_(BR * BB);
+          // n_J with the row weight sqrt(eps) folded in
+          const T nJ = ipow<T, LB>(pbm) * ipow<T, J>(qm) * rsq_(BR * BB) * sw;
           const T gJ = qm * ipow<T, J>(qq) * rcp_(BR);
           const T a0 = d00<J>(cK), a1 = d10<J>(cK, sK);
 #pragma unroll
@@ -210,13 +237,12 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
       do_spin(std::integral_constant<int, 3>{});
       do_spin(std::integral_constant<int, 4>{});
       if constexpr (NZ > 0) {
-        if (a.cnt[5] > 0) {
+        if (zon) {
           // (the angular columns za carry the Z barrier factor n_Z)
-          const T mz2 = col[col_at(9, e, ld)], gz = col[col_at(11, e, ld)];
+          const T mz2 = g2.y, gz = g2.w;
           // this row's Zang[l'][xi]: xi = +1 columns 12-13 (l' = 0) and 16-17 (l' = 1), xi = -1 14-15, 18-19
-          const int zo = xm ? 2 : 0;
-          const T z0r = col[col_at(12 + zo, e, ld)], z0i = col[col_at(13 + zo, e, ld)];
-          const T z1r = col[col_at(16 + zo, e, ld)], z1i = col[col_at(17 + zo, e, ld)];
+          const T z0r = xm ? g3.z : g3.x, z0i = xm ? g3.w : g3.y;
+          const T z1r = xm ? g4.z : g4.x, z1i = xm ? g4.w : g4.y;
           constexpr int zc0 = comp_base<Sh>(5);
 #pragma unroll
           for (int z = 0; z < NZ; ++z) {
@@ -224,7 +250,7 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
             const auto& rc = a.zs[z];
             const T dre = rc.M2 - mz2, dim = -rc.P * gz;
             const T inv = rcp_(dre * dre + dim * dim);
-            const T sc = rc.K * inv;
+            const T sc = rc.K * inv * sw;
             const T Ar = sc * dre, Ai = -sc * dim;
             put(zc0 + 2 * z, Ar, Ai, z0r, z0i);
             put(zc0 + 2 * z + 1, Ar, Ai, z1r, z1i);
@@ -246,93 +272,125 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
         }
       }
     } else {
-      Wr[lane] = 0.0;
+      // past the last event (the final tile only): a zero row
+      for (int c = 0; c < a.ncols; ++c) rr[c] = T(0);
     }
+    fetch(tile + gridDim.x);
     __syncthreads();
-    // ---- Gram tiles: A[i][k] = w_row X[row][16 ti + i], B[k][j] = X[row][16 tj + j],
-    //      row = 4 s + k; lane = i + 16 k provides A[i][k] and B[k][j = i].  The A and B
-    //      operands of a row group are the same LDS elements (A scaled by the event weight),
-    //      so each group loads NT values per lane and feeds all NT(NT+1)/2 tiles; consecutive
-    //      MFMAs accumulate into different tiles.
+    // ---- Gram tiles: A[i][k] = X[row][16 ti + i], B[k][j] = X[row][16 tj + j], row = 4 s + k;
+    //      lane = i + 16 k provides A[i][k] and B[k][j = i].  The A and B operands of a row group
+    //      are the same LDS elements, so each group loads NT values per lane and feeds all
+    //      NT(NT+1)/2 tiles; consecutive MFMAs accumulate into different tiles.  The next
+    //      group's values are read from LDS before the current group's MFMAs are issued.
     const int r16 = lane & 15, k4 = lane >> 4;
+    int cofs[NT];   // this lane's column of each tile, padded columns mapped to the zero column
+#pragma unroll
+    for (int t = 0; t < NT; ++t) cofs[t] = min(16 * t + r16, a.ncols);
+    T nx[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) nx[t] = X[k4 * LDX + cofs[t]];
 #pragma unroll 2
     for (int s = 0; s < 16; ++s) {
-      const int row = 4 * s + k4;
-      const double w = Wr[row];
-      double av[NT], bv[NT];
+      double v[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        bv[t] = (double)X[row * LDX + 16 * t + r16];
-        av[t] = w * bv[t];
+      for (int t = 0; t < NT; ++t) v[t] = (double)nx[t];
+      if (s + 1 < 16) {
+        const int row = 4 * (s + 1) + k4;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) nx[t] = X[row * LDX + cofs[t]];
       }
+      // keep those reads ahead of the MFMAs in the instruction stream
+      __builtin_amdgcn_sched_barrier(0);
       int t = 0;
 #pragma unroll
       for (int ti = 0; ti < NT; ++ti) {
 #pragma unroll
-        for (int tj = ti; tj < NT; ++tj, ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ti], bv[tj], acc[t], 0, 0, 0);
+        for (int tj = ti; tj < NT; ++tj, ++t) {
+          // the last diagonal tile holds only derivative x derivative products when the
+          // derivative columns fill it: nothing reads them, so it is left at zero
+          if (ti == NT - 1 && tj == NT - 1 && a.skip_last) continue;
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[ti], v[tj], acc[t], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
   }
-  // ---- block partial, value-major: value (t, lane, reg) at partial[((t*64 + lane)*4 + reg) * nb + block]
+  // ---- block partial: the four accumulator registers of (tile t, lane) are values
+  //      v = (t*64 + lane)*4 + r, stored as one 32-byte record per (t, lane) and block at
+  //      record (t*64 + lane) * nb + block (blocks of one record group adjacent)
   const int nb = gridDim.x;
+  d4_t* P = reinterpret_cast<d4_t*>(a.partial);
 #pragma unroll
-  for (int t = 0; t < NTILE; ++t) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) a.partial[(((int64_t)t * 64 + lane) * 4 + r) * nb + blockIdx.x] = acc[t][r];
-  }
+  for (int t = 0; t < NTILE; ++t) P[((int64_t)t * 64 + lane) * nb + blockIdx.x] = acc[t];
 }
 
-// Fixed-order compensated sum over blocks of value-major partials: out[v] = sum_b p[v*nb + b].
+// Fixed-order compensated sums over blocks of the 32-byte partial records: block g sums record
+// group g (values 4g .. 4g+3) over the nb blocks into out[4g + r].
 __global__ __launch_bounds__(256) void reduce_values(const double* __restrict__ partial, int nb, double* out) {
-  const int v = blockIdx.x;
-  const double* p = partial + (int64_t)v * nb;
-  double s = 0.0, c = 0.0;
+  using im::d4_t;
+  const int g = blockIdx.x;
+  const d4_t* p = reinterpret_cast<const d4_t*>(partial) + (int64_t)g * nb;
+  double s[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nb; b += 256) {
-    const double x = p[b];
-    const double t = s + x;
-    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
-    s = t;
+    const d4_t x4 = p[b];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double x = x4[r];
+      const double t = s[r] + x;
+      c[r] += (fabs(s[r]) >= fabs(x)) ? (s[r] - t) + x : (x - t) + s[r];
+      s[r] = t;
+    }
   }
-  __shared__ double S[256], Cc[256];
-  S[threadIdx.x] = s;
-  Cc[threadIdx.x] = c;
+  __shared__ double S[4][256], Cc[4][256];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    S[r][threadIdx.x] = s[r];
+    Cc[r][threadIdx.x] = c[r];
+  }
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
     if (threadIdx.x < w) {
-      const double a = S[threadIdx.x], b = S[threadIdx.x + w];
-      const double tt = a + b, bp = tt - a;
-      const double err = (a - (tt - bp)) + (b - bp);
-      S[threadIdx.x] = tt;
-      Cc[threadIdx.x] = Cc[threadIdx.x] + Cc[threadIdx.x + w] + err;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double a = S[r][threadIdx.x], b = S[r][threadIdx.x + w];
+        const double tt = a + b, bp = tt - a;
+        const double err = (a - (tt - bp)) + (b - bp);
+        S[r][threadIdx.x] = tt;
+        Cc[r][threadIdx.x] = Cc[r][threadIdx.x] + Cc[r][threadIdx.x + w] + err;
+      }
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[v] = S[0] + Cc[0];
+  if (threadIdx.x < 4) out[4 * g + threadIdx.x] = S[threadIdx.x][0] + Cc[threadIdx.x][0];
 }
+
+// dynamic LDS of a block: 64 rows of ncols + 1 values
+template <typename T> size_t imatrix_smem(int ncols) { return 64 * (size_t)(ncols + 1) * sizeof(T); }
 
 template <typename T, class Sh, int C>
 hipError_t launch_imatrix_c(const ImArgs<T, Sh>& a, int nb, double* out, hipStream_t st) {
-  hipLaunchKernelGGL((imatrix_kernel<T, Sh, C>), dim3(nb), dim3(64), 0, st, a);
+  if (a.ncols <= 0 || a.ncols > C || (a.ncols & 1)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((imatrix_kernel<T, Sh, C>), dim3(nb), dim3(64), imatrix_smem<T>(a.ncols), st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   constexpr int NT = C / 16;
   const int nv = NT * (NT + 1) / 2 * 256;
-  hipLaunchKernelGGL(reduce_values, dim3(nv), dim3(256), 0, st, a.partial, nb, out);
+  hipLaunchKernelGGL(reduce_values, dim3(nv / 4), dim3(256), 0, st, a.partial, nb, out);
   return hipGetLastError();
 }
 
-template <typename T, class Sh, int C> int imatrix_blocks_per_cu_c() {
+template <typename T, class Sh, int C> int imatrix_blocks_per_cu_c(int ncols) {
   int nb = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, imatrix_kernel<T, Sh, C>, 64, 0);
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, imatrix_kernel<T, Sh, C>, 64, imatrix_smem<T>(ncols));
   return (e == hipSuccess && nb > 0) ? nb : 0;
 }
 // Blocks (one wavefront each) of the interference-matrix kernel resident per compute unit.
 template <typename T, class Sh> int imatrix_blocks_per_cu(int ncols) {
-  if (ncols <= 16) return imatrix_blocks_per_cu_c<T, Sh, 16>();
-  if (ncols <= 32) return imatrix_blocks_per_cu_c<T, Sh, 32>();
-  if (ncols <= 64) return imatrix_blocks_per_cu_c<T, Sh, 64>();
-  return imatrix_blocks_per_cu_c<T, Sh, 80>();
+  if (ncols <= 16) return imatrix_blocks_per_cu_c<T, Sh, 16>(ncols);
+  if (ncols <= 32) return imatrix_blocks_per_cu_c<T, Sh, 32>(ncols);
+  if (ncols <= 64) return imatrix_blocks_per_cu_c<T, Sh, 64>(ncols);
+  return imatrix_blocks_per_cu_c<T, Sh, 80>(ncols);
 }
 template int imatrix_blocks_per_cu<float, ShapeSmall>(int);
 template int imatrix_blocks_per_cu<double, ShapeSmall>(int);

@@ -156,7 +156,9 @@ template <typename T, class Sh> struct ImArgs {
   const T* cols;
   int64_t ld, n;
   const T* eps;         // per-event efficiency or null
-  double* partial;      // value-major block partials of the Gram tiles
+  double* partial;      // block partials of the Gram tiles, in 32-byte records (four values)
+  int ncols;            // real columns in use (even; at most the kernel's padded width)
+  int skip_last;        // 1: the last diagonal 16 x 16 tile has derivative columns only; skip it
   int cnt[6];
   int dcol[NFL];        // first derivative component of floating slot f
   T rR, rB, invMB;

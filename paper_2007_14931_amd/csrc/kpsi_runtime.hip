@@ -464,6 +464,8 @@ kpsi_status gram_build_t(kpsi_ctx* c, const double* par, bool with_eps, bool wit
   a.n = d.n;
   a.eps = with_eps ? (const T*)c->eps : nullptr;
   a.partial = c->cache_partial;
+  a.ncols = ncols;
+  a.skip_last = (NT > 1 && 16 * (NT - 1) >= 2 * ncomp) ? 1 : 0;
   for (int j = 0; j < 6; ++j) a.cnt[j] = pa.cnt[j];
   for (int f = 0; f < NFL; ++f) a.dcol[f] = dcol[f];
   a.rR = pa.rR; a.rB = pa.rB; a.invMB = pa.invMB;
