@@ -78,12 +78,13 @@ template <class Sh> __host__ __device__ constexpr int comp_base(int J) {   // fi
 }
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
 
 }  // namespace im
 
 // One wavefront per block.  Each tile holds 32 events (64 rows: xi = +1, -1).
 template <typename T, class Sh, int C>
-__global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void imatrix_kernel(const ImArgs<T, Sh> a) {
   using namespace im;
   constexpr int NT = C / 16;
   constexpr int NTILE = NT * (NT + 1) / 2;
@@ -289,27 +290,64 @@ __global__ __launch_bounds__(64) void imatrix_kernel(const ImArgs<T, Sh> a) {
     T nx[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) nx[t] = X[k4 * LDX + cofs[t]];
+    if constexpr (std::is_same_v<T, float>) {
+      // FP32 rows: FP32 matrix cores (each product of two FP32 values, summed in FP32 over the
+      // tile's 64 rows), then the tile's sums are added into the FP64 accumulators.  Accumulator
+      // layout of the 32-bit form: lane l, register r hold row 4 (l / 16) + r, column l % 16.
+      f4_t a32[NTILE];
+#pragma unroll
+      for (int t = 0; t < NTILE; ++t) a32[t] = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
-    for (int s = 0; s < 16; ++s) {
-      double v[NT];
+      for (int s = 0; s < 16; ++s) {
+        float v[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) v[t] = (double)nx[t];
-      if (s + 1 < 16) {
-        const int row = 4 * (s + 1) + k4;
+        for (int t = 0; t < NT; ++t) v[t] = nx[t];
+        if (s + 1 < 16) {
+          const int row = 4 * (s + 1) + k4;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) nx[t] = X[row * LDX + cofs[t]];
+          for (int t = 0; t < NT; ++t) nx[t] = X[row * LDX + cofs[t]];
+        }
+        // keep those reads ahead of the MFMAs in the instruction stream
+        __builtin_amdgcn_sched_barrier(0);
+        int t = 0;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) {
+#pragma unroll
+          for (int tj = ti; tj < NT; ++tj, ++t) {
+            if (ti == NT - 1 && tj == NT - 1 && a.skip_last) continue;
+            a32[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[ti], v[tj], a32[t], 0, 0, 0);
+          }
+        }
       }
-      // keep those reads ahead of the MFMAs in the instruction stream
-      __builtin_amdgcn_sched_barrier(0);
-      int t = 0;
 #pragma unroll
-      for (int ti = 0; ti < NT; ++ti) {
+      for (int t = 0; t < NTILE; ++t) {
 #pragma unroll
-        for (int tj = ti; tj < NT; ++tj, ++t) {
-          // the last diagonal tile holds only derivative x derivative products when the
-          // derivative columns fill it: nothing reads them, so it is left at zero
-          if (ti == NT - 1 && tj == NT - 1 && a.skip_last) continue;
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[ti], v[tj], acc[t], 0, 0, 0);
+        for (int r = 0; r < 4; ++r) acc[t][r] += (double)a32[t][r];
+      }
+    } else {
+      // FP64 rows: FP64 matrix cores.  Accumulator layout of the FP64 form: lane l, register r
+      // hold row l / 16 + 4 r, column l % 16.
+#pragma unroll 2
+      for (int s = 0; s < 16; ++s) {
+        double v[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) v[t] = (double)nx[t];
+        if (s + 1 < 16) {
+          const int row = 4 * (s + 1) + k4;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) nx[t] = X[row * LDX + cofs[t]];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        int t = 0;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) {
+#pragma unroll
+          for (int tj = ti; tj < NT; ++tj, ++t) {
+            // the last diagonal tile holds only derivative x derivative products when the
+            // derivative columns fill it: nothing reads them, so it is left at zero
+            if (ti == NT - 1 && tj == NT - 1 && a.skip_last) continue;
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[ti], v[tj], acc[t], 0, 0, 0);
+          }
         }
       }
     }

@@ -487,17 +487,18 @@ kpsi_status gram_build_t(kpsi_ctx* c, const double* par, bool with_eps, bool wit
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   g.ms = 0.f;
   hipEventElapsedTime(&g.ms, e0, e1);
-  // real Gram matrix G from its upper 16x16 tiles.  The FP64 16x16x4 MFMA accumulator holds, in
-  // lane l and register r, row l/16 + 4 r and column l % 16 of the tile (rows interleaved across
-  // the four registers, unlike the 32-bit-accumulator forms): tile t, lane, reg ->
-  // row 16 ti + lane/16 + 4 reg, column 16 tj + lane % 16
+  // real Gram matrix G from its upper 16x16 tiles.  The FP64 16x16x4 MFMA accumulator (FP64
+  // context) holds, in lane l and register r, row l/16 + 4 r and column l % 16 of the tile (rows
+  // interleaved across the four registers); the FP32 16x16x4 form (FP32 context) holds row
+  // 4 (l/16) + r, column l % 16
   std::vector<double> G((size_t)C * C, 0.0);
   int t = 0;
   for (int ti = 0; ti < NT; ++ti)
     for (int tj = ti; tj < NT; ++tj, ++t)
       for (int lane = 0; lane < 64; ++lane)
         for (int r = 0; r < 4; ++r) {
-          const int row = 16 * ti + lane / 16 + 4 * r, col = 16 * tj + lane % 16;
+          const int row = 16 * ti + (std::is_same<T, float>::value ? 4 * (lane / 16) + r : lane / 16 + 4 * r);
+          const int col = 16 * tj + lane % 16;
           const double v = out[((size_t)t * 64 + lane) * 4 + r];
           G[(size_t)row * C + col] = v;
           G[(size_t)col * C + row] = v;
