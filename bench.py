@@ -33,6 +33,7 @@ TIMING_EVERY = 10
 FLOP_PER_EVENT = {"full_grad": 914}
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}        # MI355X published vector peaks
 PEAK_TFLOPS_UNPACKED = {"f32": 78.6, "f64": 78.6}  # without packed-FP32 instructions
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}     # MI355X published dense matrix-core peaks
 
 
 def measured_traffic(kernel_source: str) -> float | None:
@@ -160,10 +161,11 @@ def fit_comparison(make, truth, mask, canonical_fn) -> dict:
     }
 
 
-def norm_cache_leg(eng, par, res, floating) -> dict:
+def norm_cache_leg(eng, par, res, floating, precision: str) -> dict:
     """The interference-matrix path on the benchmark engine: one build of the normalisation
-    matrices at the benchmark point (FP64 MFMA Gram product over the 2e6 normalisation events),
-    then NLL+gradient calls that change only couplings, served from the matrices (only the data
+    matrices at the benchmark point (matrix-core Gram product over the 2e6 normalisation events:
+    FP32 products with FP64 tile sums in the FP32 context, FP64 in the FP64 context), then
+    NLL+gradient calls that change only couplings, served from the matrices (only the data
     events are evaluated per call)."""
     ncomp = sum(r.n_coup for r in res)                                   # complex coupling components
     nderiv = sum(2 * r.n_coup for r in res if r.name in floating)       # d/dM and d/dGamma0 components
@@ -194,10 +196,12 @@ def norm_cache_leg(eng, par, res, floating) -> dict:
     eng.set_norm_cache(0)
     n_mc = eng.n[1]
     flop = 2.0 * macs_per_row * 2 * n_mc          # 2 flop per MAC, rows xi = +1, -1 per event
+    mm = "f32" if precision == "fp32" else "f64"
+    peak = MFMA_PEAK_TFLOPS[mm]
     return {"components": ncomp, "derivative_components": nderiv, "build_ms": build_ms,
             "kernel": "imatrix_kernel + reduce_values", "flop_per_build": flop,
-            "achieved_tflops": flop / (build_ms * 1e-3) / 1e12, "peak_tflops_fp64_mfma": 78.6,
-            "frac": flop / (build_ms * 1e-3) / 1e12 / 78.6,
+            "achieved_tflops": flop / (build_ms * 1e-3) / 1e12, "mfma_dtype": mm,
+            "peak_tflops_mfma": peak, "frac": flop / (build_ms * 1e-3) / 1e12 / peak,
             "cached_ms_per_step": ms, "cached_evals_per_s": 1e3 / ms, "builds": b2, "hits": hits}
 
 
@@ -416,7 +420,7 @@ def main() -> int:
                      "frac_measured_fma_peak": achieved / (peaks["fp32_fma_tflops"] if dt == "f32"
                                                            else peaks["fp64_fma_tflops"])},
     }
-    out["norm_cache"] = norm_cache_leg(eng, par, res, floating)
+    out["norm_cache"] = norm_cache_leg(eng, par, res, floating, args.precision)
     if args.ext_steps > 0:
         out["extensions"] = extension_legs(stream.cuda_stream, data, mc, par, res, floating, args.ext_steps,
                                            max(10, args.ext_steps // 3))

@@ -212,14 +212,15 @@ kpsi_status kpsi_hesse(kpsi_ctx* ctx, const double* params, const int* free_mask
  * I_kl = sum_j eps_j sum_xi B_k,xi(y_j) conj(B_l,xi(y_j)) over the complex couplings c_k and
  * per-event component amplitudes B_k,xi of Eq. 4 and Eq. 10, plus the matrices
  * D^p_kl = sum_j eps_j sum_xi dB_k,xi/dp conj(B_l,xi) for the floating lineshapes.  They are
- * built with FP64 matrix-core products over the normalisation set and depend only on the
+ * built with matrix-core products over the normalisation set (in the FP32 context FP32
+ * products summed in FP64 per 64-row tile, in the FP64 context FP64 products) and depend only on the
  * masses and widths, so a call whose masses and widths equal those of the cached build
  * evaluates only the data events.
  *   mode 0: off (default; every call evaluates both sets)
  *   mode 1: on (rebuild whenever masses or widths change)
  *   mode 2: auto (use the cache when it matches; build only after KPSI_CACHE_AUTO_STREAK
  *           consecutive calls at the same masses and widths, e.g. the coupling directions of
- *           a finite-difference gradient; a build costs about as much as 20-30 direct calls)
+ *           a finite-difference gradient; a build costs about as much as 5-10 direct calls)
  * Loading the normalisation set, changing the efficiency, the model or the floating set
  * drops the cache. */
 #define KPSI_CACHE_AUTO_STREAK 16
@@ -231,7 +232,7 @@ kpsi_status kpsi_norm_cache_stats(const kpsi_ctx* ctx, int64_t* builds, int64_t*
  * model, where S_j is the density with all helicity couplings outside resonance j set to zero
  * and the integrals run over phase space without efficiency.  They are estimated on the loaded
  * normalisation events (flat phase space) through one interference-matrix build at the
- * masses and widths of params (FP64 matrix-core Gram product, efficiency column not applied;
+ * masses and widths of params (matrix-core Gram product as above, efficiency column not applied;
  * the normalisation cache is left untouched): ff[j] = c_j^H I_jj c_j / c^H I c.
  *   params: full parameter vector (kpsi_n_params doubles, host).
  *   ff:     n_res doubles (host, caller-owned), table order.

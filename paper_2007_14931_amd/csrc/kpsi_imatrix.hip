@@ -1,14 +1,15 @@
-// Interference matrix of the normalisation integral (gfx950, FP64 MFMA).
+// Interference matrix of the normalisation integral (gfx950 matrix cores).
 //
 // With a_xi = sum_k c_k B_k,xi (complex couplings c_k, per-event component amplitudes
 // B_k,xi = A_R(m) x angular factor of Eq. 4 or Eq. 10), the MC normalisation sum is
 //   sum_j eps_j S(y_j) = sum_kl c_k conj(c_l) I_kl,   I_kl = sum_j eps_j sum_xi B_k,xi conj(B_l,xi),
 // and its derivative with respect to a lineshape parameter p of resonance R needs
 //   D^p_kl = sum_j eps_j sum_xi dB_k,xi/dp conj(B_l,xi)   (k in R).
-// Both are blocks of the real Gram matrix G = X_w^T X of the matrix X whose rows are
-// (event, xi) and whose columns are the real and imaginary parts of the components
-// followed by the derivative components; X_w is X with each row scaled by eps.  G is
-// accumulated with v_mfma_f64_16x16x4f64 over 16x16 tiles of its upper triangle.
+// Both are blocks of the real Gram matrix G = X^T X of the matrix X whose rows are
+// (event, xi), each scaled by sqrt(eps) of its event, and whose columns are the real and
+// imaginary parts of the components followed by the derivative components.  G is accumulated
+// over 16x16 tiles of its upper triangle on the matrix cores: v_mfma_f32_16x16x4f32 for FP32
+// rows (FP32 sums over one 64-row tile, then FP64 sums), v_mfma_f64_16x16x4f64 for FP64 rows.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
