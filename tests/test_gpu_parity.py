@@ -265,3 +265,26 @@ def test_autograd_function_returns_the_adjoint_gradient():
     fin = np.isfinite(g_ref)
     np.testing.assert_allclose(g[fin], 3.0 * g_ref[fin], rtol=1e-14)
     assert np.all(np.isnan(g[~fin]))   # lineshape entries that are not floating stay NaN
+
+
+def test_kernel_timing_samples_every_kth_call_and_reports_the_median():
+    e, res = _engine("kstar10", "fp32")
+    data, mc = _sets(2001, 6001, seed=23)
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    par = W.params(res, seed=24)
+    assert math.isnan(e.timing_median())          # nothing timed yet
+    e.set_timing(3)
+    for _ in range(10):
+        e.nll_and_grad(par)
+    med = e.timing_median()
+    ms, n = e.timing()
+    assert n == 4                                  # calls 1, 4, 7 and 10
+    assert 0.0 < med <= ms                         # a median of positive samples, below their sum
+    e.nll(par)                                     # the 11th call: not a timed one
+    assert e.timing()[1] == 4
+    ms, n = e.timing(reset=True)
+    assert math.isnan(e.timing_median()) and e.timing() == (0.0, 0)
+    e.set_timing(False)
+    e.nll_and_grad(par)
+    assert e.timing()[1] == 0
