@@ -222,6 +222,20 @@ template <int D> __device__ __forceinline__ void swap_halves(double& lo, double&
   lo = __builtin_bit_cast(double, ((uint64_t)nh0 << 32) | nl0);
   hi = __builtin_bit_cast(double, ((uint64_t)nh1 << 32) | nl1);
 }
+template <int D> __device__ __forceinline__ void swap_halves(float& lo, float& hi) {
+  static_assert(D == 32 || D == 16, "lane-swap distance");
+  const unsigned a = __builtin_bit_cast(unsigned, lo), b = __builtin_bit_cast(unsigned, hi);
+  unsigned n0, n1;
+  if constexpr (D == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    n0 = r[0]; n1 = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    n0 = r[0]; n1 = r[1];
+  }
+  lo = __builtin_bit_cast(float, n0);
+  hi = __builtin_bit_cast(float, n1);
+}
 
 // ------------------------------------------------------------------ compensated sums
 __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
@@ -774,39 +788,53 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ double red[4][NACC];
   if constexpr (GRAD) {
-    // accumulator i of this lane as double (compile-time index after unrolling)
-    auto accv = [&](int i) -> double {
-      if (i == 0) return ms;
-      if (i == 1) return -mc;   // Kahan: the running sum exceeds the exact one by mc
-      if (i == 2) return (double)nbad;
-      if (LDSACC && i >= 3 + LO && i < 3 + HI) return (double)accl[i - 3 - LO][threadIdx.x];
-      if (i < 3 + Sh::NKACC) return (double)gk[i - 3];
-      if (i < 3 + Sh::NKACC + 4 * NZ) return (double)gz[i - 3 - Sh::NKACC];
+    // accumulator i >= 2 of this lane at its accumulation type (compile-time index after
+    // unrolling); 0 and 1 are the FP64 likelihood sums
+    auto accf = [&](int i) -> A_t {
+      if (i == 2) return (A_t)nbad;
+      if (LDSACC && i >= 3 + LO && i < 3 + HI) return accl[i - 3 - LO][threadIdx.x];
+      if (i < 3 + Sh::NKACC) return gk[i - 3];
+      if (i < 3 + Sh::NKACC + 4 * NZ) return gz[i - 3 - Sh::NKACC];
       const int f = i - 3 - Sh::NKACC - 4 * NZ;
-      if (f == 0) return (double)gM0;
-      if (f == 1) return (double)gG0;
-      if (f == 2) return (double)gM1;
-      if (f == 3) return (double)gG1;
-      if (f == 4) return (double)ws;
-      return 0.0;
+      if (f == 0) return gM0;
+      if (f == 1) return gG0;
+      if (f == 2) return gM1;
+      if (f == 3) return gG1;
+      if (f == 4) return ws;
+      return A_t(0);
     };
     // Transpose butterfly: after the step of width h, lane l keeps h values, each summed
     // with its partner lane's; after the last step lane l holds the wave sum of value l.
     // The steps of width 32 and 16 use the lane-swap instructions (swap_halves), the rest
-    // lane shuffles.  The first step reads the typed accumulators directly so that at most
-    // 32 doubles are live at once.
-    double v[32];
+    // lane shuffles.  Slots 0 and 1 carry the FP64 likelihood sums and every value merged into
+    // them (as double); the other slots move the accumulators at their own type (FP32 sums of
+    // the wave's FP32 thread accumulators in the FP32 kernel).
+    double d[2];
+    A_t v[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
-      double lo = accv(i), hi = accv(i + 32);
-      swap_halves<32>(lo, hi);
-      v[i] = lo + hi;
+      if (i < 2) {
+        double lo = (i == 0) ? ms : -mc;   // Kahan: the running sum exceeds the exact one by mc
+        double hi = (double)accf(i + 32);
+        swap_halves<32>(lo, hi);
+        d[i] = lo + hi;
+      } else {
+        A_t lo = accf(i), hi = accf(i + 32);
+        swap_halves<32>(lo, hi);
+        v[i] = lo + hi;
+      }
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      double lo = v[i], hi = v[i + 16];
-      swap_halves<16>(lo, hi);
-      v[i] = lo + hi;
+      if (i < 2) {
+        double lo = d[i], hi = (double)v[i + 16];
+        swap_halves<16>(lo, hi);
+        d[i] = lo + hi;
+      } else {
+        A_t lo = v[i], hi = v[i + 16];
+        swap_halves<16>(lo, hi);
+        v[i] = lo + hi;
+      }
     }
 #pragma unroll
     for (int s = 3; s >= 0; --s) {
@@ -814,12 +842,23 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
       const bool up = (lane >> s) & 1;
 #pragma unroll
       for (int i = 0; i < half; ++i) {
-        const double keep = up ? v[i + half] : v[i];
-        const double send = up ? v[i] : v[i + half];
-        v[i] = keep + __shfl_xor(send, half, 64);
+        if (i < 2) {
+          const double hv = (i + half < 2) ? d[i + half] : (double)v[i + half];
+          const double keep = up ? hv : d[i];
+          const double send = up ? d[i] : hv;
+          d[i] = keep + __shfl_xor(send, half, 64);
+        } else {
+          // (the empty asm keeps the two slots as values, so that the selects below stay
+          // selects instead of becoming a lane-dependent index into the slot array)
+          A_t a0 = v[i], a1 = v[i + half];
+          asm("" : "+v"(a0), "+v"(a1));
+          const A_t keep = up ? a1 : a0;
+          const A_t send = up ? a0 : a1;
+          v[i] = keep + __shfl_xor(send, half, 64);
+        }
       }
     }
-    red[wave][lane] = v[0];
+    red[wave][lane] = d[0];
   } else {
     double v0 = ms, v1 = -mc, v2 = (double)nbad;
 #pragma unroll
