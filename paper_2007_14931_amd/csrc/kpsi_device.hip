@@ -272,7 +272,7 @@ template <typename T> __device__ __forceinline__ void cacc(T& gr, T& gi, const C
 // Gamma0 = P/PoG):
 //   dS/dM      = Re[X (kappa - (2M - i P' g) B)],   kappa = d ln K/dM, P' = dP/dM
 //   dS/dGamma0 = Re[X i PoG g B] = -PoG g Im[X B]
-// The floating slot index is uniform, so the branch on it is a scalar one.
+// The slot's 0/1 selectors f0, f1 route the two derivatives to floating slot 0 or 1.
 template <typename T, typename R>
 __device__ __forceinline__ void flt_deriv(const R& rc, const Cx<T>& B, const Cx<T>& Q, T g, T& gM0, T& gG0, T& gM1,
                                           T& gG1) {
@@ -281,8 +281,10 @@ __device__ __forceinline__ void flt_deriv(const R& rc, const Cx<T>& B, const Cx<
   const T Yr = fma_(rc.twoM, B.re, pg * B.im), Yi = fma_(rc.twoM, B.im, -pg * B.re);
   const T dM = fma_(rc.kap, Xr, -fma_(Xr, Yr, -Xi * Yi));
   const T dG = -rc.PoG * g * fma_(Xr, B.im, Xi * B.re);
-  if (rc.flt == 0) { gM0 += dM; gG0 += dG; }
-  else { gM1 += dM; gG1 += dG; }
+  gM0 = fma_(rc.f0, dM, gM0);
+  gG0 = fma_(rc.f0, dG, gG0);
+  gM1 = fma_(rc.f1, dM, gM1);
+  gG1 = fma_(rc.f1, dG, gG1);
 }
 
 // Blatt-Weisskopf polynomial B_L(z) (Horner form)

@@ -29,6 +29,7 @@ template <typename T> struct RC {
   T hr[3], hi[3];     // K*: lambda = -1, 0, +1; Z: [0] lambda' = 0, [1] lambda' = +-1
   T kap, twoM, dP, PoG;   // d ln K/dM, 2M, dP/dM, P/Gamma0
   int flt;            // floating slot or -1
+  T f0, f1;           // 1 where flt is 0 (1), else 0
   int lass;           // 1: LASS S-wave (spin-0 K* only), 0: Breit-Wigner
   T lai, lhb;         // LASS 1/a and b/2: q cot(delta_B) = lai + lhb q^2
 };

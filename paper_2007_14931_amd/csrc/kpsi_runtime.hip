@@ -197,6 +197,8 @@ template <typename T> void fill_rc(RC<T>& rc, const LsConst& c, const double* hr
   }
   rc.kap = (T)c.kap; rc.twoM = (T)c.twoM; rc.dP = (T)c.dP; rc.PoG = (T)c.PoG;
   rc.flt = flt;
+  rc.f0 = (T)(flt == 0 ? 1 : 0);
+  rc.f1 = (T)(flt == 1 ? 1 : 0);
   rc.lass = 0;
   rc.lai = rc.lhb = T(0);
 }
