@@ -71,10 +71,11 @@ template <typename P> __device__ __forceinline__ kconst_ptr<P> kernarg_laundered
 // Columns written per event (type T, in groups of four at col_at(k, e, ld)):
 //   K* chain  : m, q(m), p_B(m), cos/sin theta_K*, cos/sin theta_J/psi, cos/sin phi, and
 //               q/m (column 10)
-//   Z chain   : m^2_Jpsi pi (column 9), gZ = q/m_Jpsi pi (column 11), and the four complex
-//               angular factors Zang[l'][xi] of Eq. (10) (l' = 0 and l' = +-1 combined
-//               through Eq. 11, xi = +1, -1), each multiplied by
+//   Z chain   : m^2_Jpsi pi (column 9), gZ = q/m_Jpsi pi (column 11), and the complex angular
+//               factors Zang[l'][xi = +1] of Eq. (10) for l' = 0 (columns 12-13) and l' = +-1
+//               combined through Eq. 11 (columns 14-15), each multiplied by
 //               nZ = (p_B/M_B) / sqrt(1 + (r_B p_B)^2), the factor common to every Z amplitude.
+//               The xi = -1 factors are (-Re, Im) of the xi = +1 ones and are not stored.
 // All arithmetic in double; stored in T.
 template <typename T>
 __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
@@ -184,19 +185,17 @@ __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
   // times nZ
   const double r2 = 0.7071067811865475244 * nZ;
   //  l' = 0:  xi = +1: cZ st/sqrt2 e^{i alpha};  xi = -1: -cZ st/sqrt2 e^{-i alpha}
+  //  (xi = -1 is -z0 ca + i z0 sa: minus the real part, the same imaginary part)
   const double z0 = cZ * st * r2;
   c[col_at(12, e, ld)] = (T)(z0 * ca);
   c[col_at(13, e, ld)] = (T)(z0 * sa);
-  c[col_at(14, e, ld)] = (T)(-z0 * ca);
-  c[col_at(15, e, ld)] = (T)(z0 * sa);
   //  l' = +-1 (H'_{-1} = H'_{+1}):  xi = +1: sZ/sqrt2 (ct cpt + i spt) e^{i alpha}
-  //                                 xi = -1: sZ/sqrt2 (-ct cpt + i spt) e^{-i alpha}
+  //                                 xi = -1: sZ/sqrt2 (-ct cpt + i spt) e^{-i alpha}, again
+  //                                 (-Re, Im) of the xi = +1 factor
   const double z1 = sZ * r2;
   const double pr = ct * cpt, pi_ = spt;
-  c[col_at(16, e, ld)] = (T)(z1 * (pr * ca - pi_ * sa));
-  c[col_at(17, e, ld)] = (T)(z1 * (pr * sa + pi_ * ca));
-  c[col_at(18, e, ld)] = (T)(z1 * (-pr * ca + pi_ * sa));
-  c[col_at(19, e, ld)] = (T)(z1 * (pr * sa + pi_ * ca));
+  c[col_at(14, e, ld)] = (T)(z1 * (pr * ca - pi_ * sa));
+  c[col_at(15, e, ld)] = (T)(z1 * (pr * sa + pi_ * ca));
 }
 
 // ------------------------------------------------------------------ cross-lane exchange
@@ -574,9 +573,10 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
       if (a.cnt[5] > 0) {
         const T mz2 = g2.y;
         gzv = g2.w;
-        const V4 g3 = ldoff(gb + 3 * ld, ob4), g4 = ldoff(gb + 4 * ld, ob4);
-        za[0] = g3.x; za[1] = g3.y; za[2] = g3.z; za[3] = g3.w;
-        za[4] = g4.x; za[5] = g4.y; za[6] = g4.z; za[7] = g4.w;
+        // Zang[l'][xi]: xi = -1 is (-Re, Im) of xi = +1
+        const V4 g3 = ldoff(gb + 3 * ld, ob4);
+        za[0] = g3.x; za[1] = g3.y; za[2] = -g3.x; za[3] = g3.y;
+        za[4] = g3.z; za[5] = g3.w; za[6] = -g3.z; za[7] = g3.w;
         Cx<T> T0{T(0), T(0)}, T1{T(0), T(0)};
 #pragma unroll
         for (int z = 0; z < NZ; ++z) {

@@ -113,12 +113,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void im
 
   // The event columns of this lane's event in the next tile are fetched before the matrix phase
   // of the current one, so their latency hides behind it.  Column groups of four (K* chain:
-  // 0-11; Z chain: 12-19, present when the model has Z states).
+  // 0-11; Z angular factors: 12-15, present when the model has Z states).
   using V4 = T __attribute__((ext_vector_type(4)));
   const V4* __restrict__ gcol = reinterpret_cast<const V4*>(a.cols);
   const int64_t ld = a.ld;
   const bool zon = NZ > 0 && a.cnt[5] > 0;
-  V4 g0{}, g1{}, g2{}, g3{}, g4{};
+  V4 g0{}, g1{}, g2{}, g3{};
   T wv = T(0);
   auto fetch = [&](int64_t tile) {
     const int64_t e = tile * 32 + (lane & 31);
@@ -126,10 +126,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void im
       g0 = gcol[e];
       g1 = gcol[ld + e];
       g2 = gcol[2 * ld + e];
-      if (zon) {
-        g3 = gcol[3 * ld + e];
-        g4 = gcol[4 * ld + e];
-      }
+      if (zon) g3 = gcol[3 * ld + e];
       wv = a.eps ? a.eps[e] : T(1);
     }
   };
@@ -242,9 +239,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void im
         if (zon) {
           // (the angular columns za carry the Z barrier factor n_Z)
           const T mz2 = g2.y, gz = g2.w;
-          // this row's Zang[l'][xi]: xi = +1 columns 12-13 (l' = 0) and 16-17 (l' = 1), xi = -1 14-15, 18-19
-          const T z0r = xm ? g3.z : g3.x, z0i = xm ? g3.w : g3.y;
-          const T z1r = xm ? g4.z : g4.x, z1i = xm ? g4.w : g4.y;
+          // this row's Zang[l'][xi]: xi = +1 columns 12-13 (l' = 0) and 14-15 (l' = 1); xi = -1 is
+          // (-Re, Im) of xi = +1
+          const T z0r = xm ? -g3.x : g3.x, z0i = g3.y;
+          const T z1r = xm ? -g3.z : g3.z, z1i = g3.w;
           constexpr int zc0 = comp_base<Sh>(5);
 #pragma unroll
           for (int z = 0; z < NZ; ++z) {

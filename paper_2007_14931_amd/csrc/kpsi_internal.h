@@ -10,7 +10,7 @@ constexpr int BLOCK = 256;      // threads per block (4 wavefronts of 64)
 constexpr int NACC = 64;        // doubles per block partial (one per lane of a wavefront)
 constexpr int NFL = 2;          // floating (M, Gamma0) slots in the adjoint
 constexpr int NCOL_KSTAR = 9;   // per-event columns of the K* chain
-constexpr int NCOL_Z = 11;      // extra per-event columns of the Z chain
+constexpr int NCOL_Z = 7;       // extra per-event columns of the Z chain
 constexpr int NCOL_MAX = NCOL_KSTAR + NCOL_Z;
 // Per-event columns are stored in groups of four: column k of event e sits at element
 // ((k / 4) * ld + e) * 4 + k % 4, so one 16-byte (FP32) or 32-byte (FP64) load per lane
