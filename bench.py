@@ -287,7 +287,7 @@ def main() -> int:
                     help="also run one plain 512 MiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported on this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the per-call work shards by events with one small all-reduce of the reduced sums)", file=sys.stderr)
         return 2
 

@@ -475,7 +475,7 @@ kpsi_status gram_build_t(kpsi_ctx* c, const double* par, bool with_eps, bool wit
   for (int k = 0; k < (Sh::NZ > 0 ? Sh::NZ : 1); ++k) {
     a.zs[k] = pa.zs[k];
   }
-  if (!with_deriv) {   // no derivative columns: mark every lineshape as fixed for this build
+  if (!with_deriv) {   // no derivative columns: every lineshape counts as fixed in this matrix
     for (int k = 0; k < (Sh::NK > 0 ? Sh::NK : 1); ++k) a.ks[k].flt = -1;
     for (int k = 0; k < (Sh::NZ > 0 ? Sh::NZ : 1); ++k) a.zs[k].flt = -1;
   }

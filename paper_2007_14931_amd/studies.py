@@ -10,7 +10,7 @@
 Each prints one JSON line.  All events are synthetic, from the library's seeded generators:
 flat phase space, accept labels under the seeded analytic acceptance (the paper's
 efficiency templates are 2D x 2D histograms of simulated events; here the truth is known
-exactly, so the efficiency models can be judged against it), and accept-reject data from
+exactly, so the efficiency models can be compared with it), and accept-reject data from
 the model times the acceptance.
 """
 from __future__ import annotations
