@@ -51,9 +51,13 @@ __device__ __forceinline__ double log_(double x) { return log(x); }
 
 template <typename T> __device__ __forceinline__ T ldnt(const T* p) { return __builtin_nontemporal_load(p); }
 // Load at a uniform base plus a 32-bit per-lane byte offset: this maps onto the
-// scalar-base + vector-offset address form, so no per-lane 64-bit address arithmetic.
+// scalar-base + vector-offset address form, so no per-lane 64-bit address arithmetic.  The
+// 32-byte FP64 column groups are loaded non-temporally; everything else with plain loads, which
+// measured 3% faster than non-temporal ones in the FP32 kernel (and 1% slower in the FP64 one).
 template <typename T> __device__ __forceinline__ T ldoff(const T* base, uint32_t off_bytes) {
-  return __builtin_nontemporal_load((const T*)((const char*)base + off_bytes));
+  const T* p = (const T*)((const char*)base + off_bytes);
+  if constexpr (sizeof(T) == 4 * sizeof(double)) return __builtin_nontemporal_load(p);
+  else return *p;
 }
 
 // Opaque copy of a pointer to uniform kernel-argument data.  Re-deriving it inside the

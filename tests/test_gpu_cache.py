@@ -1,4 +1,5 @@
-"""Normalisation through the cached interference matrix (FP64 matrix-core Gram build).
+"""Normalisation through the cached interference matrix (matrix-core Gram build: FP32 products
+with FP64 tile sums in the FP32 context, FP64 products in the FP64 context).
 
 The cached path must give the same NLL and gradient as evaluating every normalisation
 event (and as the FP64 oracle), rebuild when masses or widths change, and serve
@@ -33,7 +34,8 @@ def _setup(model, prec, floating, nd=6007, nm=30011, eps=False):
 
 
 @pytest.mark.parametrize("model,floating", [("full", ("K*(1410)", "Z(4430)")), ("kstar892", ("K*(892)",)),
-                                            ("full2z", ("K0*(800)", "Z(4240)"))])
+                                            ("full2z", ("K0*(800)", "Z(4240)")),
+                                            ("full2z", ("K*(892)", "K*(1410)"))])   # 80 columns
 def test_cached_matches_direct_and_oracle_fp64(model, floating):
     res, data, mc, e, _ = _setup(model, "fp64", floating)
     par = W.params(res, seed=5) + 0.03 * W.free_mask(res, floating)
@@ -63,6 +65,29 @@ def test_cached_matches_direct_and_oracle_fp64(model, floating):
     v3 = e.nll(p3)
     assert e.norm_cache_stats()[0] == 2
     assert v3 == pytest.approx(O.nll(K, res, p3, data, mc)[1], rel=1e-10)
+
+
+@pytest.mark.parametrize("model,floating", [("kstar892", ("K*(892)",)),            # 18 columns
+                                            ("kstar10", ()),                        # 48 columns
+                                            ("full2z", ("K*(892)", "K*(1410)"))])   # 80 columns
+def test_cached_fp32_matches_oracle_across_tile_shapes(model, floating):
+    res, data, mc, e, _ = _setup(model, "fp32", floating)
+    par = W.params(res, seed=8) + 0.03 * W.free_mask(res, floating)
+    e.set_norm_cache(1)
+    v, g = e.nll_and_grad(par)
+    assert e.norm_cache_stats()[0] == 1
+    free = np.flatnonzero(W.free_mask(res, floating))
+    st, ref, gref = O.nll(K, res, par, data, mc, dirs=free)
+    assert st == 0
+    assert abs(v - ref) <= 1e-6 * max(abs(ref), 2.0 * data.shape[1])
+    assert np.max(np.abs(g[free] - gref)) / np.max(np.abs(gref)) < 2e-5
+    # couplings only: served from the cache
+    p2 = par.copy()
+    p2[1] += 0.05
+    v2 = e.nll(p2)
+    assert e.norm_cache_stats()[1] >= 1
+    ref2 = O.nll(K, res, p2, data, mc)[1]
+    assert abs(v2 - ref2) <= 1e-6 * max(abs(ref2), 2.0 * data.shape[1])
 
 
 def test_cached_fp32_and_efficiency():
