@@ -18,9 +18,12 @@
  *    keeps them alive and unchanged until the context is destroyed or the set is
  *    reloaded; the library never frees them.
  *  - All device work runs on the context's stream (the one given to kpsi_create, or a
- *    stream the library creates).  Calls returning results to the host synchronise
- *    that stream once.  A context is not thread-safe; separate contexts are
- *    independent.
+ *    stream the library creates).  Calls returning results to the host wait once for the
+ *    work they enqueued: kpsi_nll and kpsi_nll_and_grad poll a completion word that the
+ *    stream writes into pinned host memory after their last kernel (bounded at 50 ms, then
+ *    a stream synchronize, which also reports kernel errors); the others synchronize the
+ *    stream.  When a call returns, the work it enqueued has completed.  A context is not
+ *    thread-safe; separate contexts are independent.
  *
  * Observables (Eq. 1, with theta_K* in place of m_J/psi pi, which it determines at
  * fixed m_Kpi): per event m_Kpi, cos theta_K*, cos theta_J/psi and phi (Eq. 4 and
