@@ -273,8 +273,11 @@ kpsi_status kpsi_set_background(kpsi_ctx* ctx, double purity, const double* eps_
  *   x^(s) = (m, cos theta_K*, cos theta_J/psi, s phi),  N_q = (1 - w) I(q) + w I(-q),
  *   I(s) = (1/N_MC) sum_j eps_j S(y_j^(s))
  * (n_q the number of data events tagged q; the data efficiencies dropped as for the signal
- * likelihood).  Each call evaluates the normalisation events at +phi and at -phi, so the
- * interference-matrix normalisation is not used while tags are set.
+ * likelihood).  A direct call evaluates the normalisation events at +phi and at -phi.  With
+ * the interference-matrix cache on (kpsi_set_norm_cache), both come from the +phi matrix:
+ * reversing phi gives the density of the original event with the lambda = -1 and +1
+ * couplings of every K* of spin >= 1 exchanged, so I(-phi) is the +phi form at the exchanged
+ * couplings.
  *   tags:   n doubles (host, copied), n = the number of loaded data events; NULL switches the
  *           tags off (every event a B0).
  *   mistag: w in [0, 1/2].

@@ -610,8 +610,7 @@ void cached_norm_record(const kpsi_ctx* c, const double* par, double* rm) {
 // Decide whether this call uses the cache (building it when the policy says so).
 kpsi_status use_cache(kpsi_ctx* c, const double* par, bool* use) {
   *use = false;
-  // the interference matrix holds the normalisation at +phi only
-  if (c->cache_mode == 0 || c->cc_on) return KPSI_OK;
+  if (c->cache_mode == 0) return KPSI_OK;
   const std::vector<double> ls = lineshape_params(c, par);
   if (c->cache_valid && ls == c->cache_ls) { *use = true; c->cache_hits++; return KPSI_OK; }
   if (ls == c->last_ls) {
@@ -630,8 +629,37 @@ kpsi_status use_cache(kpsi_ctx* c, const double* par, bool* use) {
 
 // Normalisation record from the interference matrix into the host record; with the Eq. 14
 // mixture also into the device copy that the data pass reads.
+//
+// With flavour tags the second record is the normalisation at -phi.  Reversing phi of an event
+// gives the density of the original event with the lambda = -1 and lambda = +1 couplings of
+// every K* of spin >= 1 exchanged (the d^1_{lambda xi} symmetry takes e^{-i lambda phi} to the
+// opposite helicities; the Z-chain terms of the two xi swap, with a common sign), so
+// I(-phi; H) = I(+phi; H') with H' the exchanged couplings, and the +phi matrix serves both
+// records: record 2 is the +phi record at H', its coupling entries mapped back through the
+// same exchange (its lineshape-derivative entries need no mapping).
 kpsi_status put_cached_record(kpsi_ctx* c, const double* params) {
   cached_norm_record(c, params, c->red_host + NACC);
+  if (c->cc_on) {
+    std::vector<double> sw(params, params + c->nparams);
+    int off = 0;
+    for (const kpsi_resonance& r : c->res) {
+      if (r.chain == 0 && r.spin > 0) {
+        std::swap(sw[off], sw[off + 4]);
+        std::swap(sw[off + 1], sw[off + 5]);
+      }
+      off += 2 * ncoup(r);
+    }
+    double* r2 = c->red_host + 2 * NACC;
+    cached_norm_record(c, sw.data(), r2);
+    for (size_t i = 0; i < c->res.size(); ++i) {
+      const kpsi_resonance& r = c->res[i];
+      if (r.chain != 0 || r.spin == 0) continue;
+      int k0, nk;
+      components_of(c, i, &k0, &nk);
+      std::swap(r2[3 + 2 * k0], r2[3 + 2 * (k0 + 2)]);
+      std::swap(r2[3 + 2 * k0 + 1], r2[3 + 2 * (k0 + 2) + 1]);
+    }
+  }
   if (c->bkg_on)
     HIPCHECK(c, hipMemcpyAsync(c->red_dev + NACC, c->red_host + NACC, 2 * sizeof(double), hipMemcpyHostToDevice,
                                c->stream));

@@ -1,6 +1,6 @@
 """Flavour-tagged charge-conjugate likelihood with mistag (text after Eq. 12) in the HIP path
 against the FP64 oracle: NLL and gradient for random tags with and without mistag, the
-interference-matrix cache staying out of the way, the tag independence at w = 1/2, the
+normalisation served from the interference matrix, the tag independence at w = 1/2, the
 reduction to the B0 likelihood, and the error paths of kpsi_set_flavour."""
 import numpy as np
 import pytest
@@ -61,16 +61,34 @@ def test_cc_nll_and_gradient_match_oracle(model, prec, w, tv, tg):
     assert _nll_close(e.nll(par), ref, tv, nd)
 
 
-def test_cc_ignores_the_interference_matrix_cache():
+@pytest.mark.parametrize("prec,tv,tg", [("fp64", 1e-10, 1e-9), ("fp32", 1e-6, 2e-5)])
+def test_cc_normalisation_from_the_interference_matrix(prec, tv, tg):
+    # the -phi normalisation comes from the +phi matrix at exchanged lambda = +-1 couplings
+    floating = ("K*(1410)", "Z(4430)")
     res, data, mc, eps_m, tag = _inputs("full", 3001, 9001)
-    e = _engine("fp64", res, data, mc, eps_m)
+    e = _engine(prec, res, data, mc, eps_m, floating)
     e.set_flavour(tag, 0.03)
     e.set_norm_cache(1)
-    par = W.params(res, seed=84)
-    _, ref, _ = O.nll_cc(K, res, par, data, tag, mc, 0.03, eps_m)
-    assert e.nll(par) == pytest.approx(ref, rel=1e-10)
-    assert e.nll_and_grad(par)[0] == pytest.approx(ref, rel=1e-10)
-    assert e.norm_cache_stats()[0] == 0
+    dirs = np.flatnonzero(W.free_mask(res, floating))
+    nd = data.shape[1]
+    par = W.params(res, seed=84) + 0.03 * W.free_mask(res, floating)
+    st, ref, gref = O.nll_cc(K, res, par, data, tag, mc, 0.03, eps_m, dirs)
+    assert st == 0
+    v, g = e.nll_and_grad(par)
+    assert e.norm_cache_stats()[0] == 1
+    assert _nll_close(v, ref, tv, nd), (v, ref)
+    assert np.max(np.abs(g[dirs] - gref)) / np.max(np.abs(gref)) < tg
+    # couplings only (the lambda = -1 coupling of K*(892) among them): served from the matrix
+    p2 = par.copy()
+    p2[2] += 0.07
+    p2[9] -= 0.05
+    st, ref2, gref2 = O.nll_cc(K, res, p2, data, tag, mc, 0.03, eps_m, dirs)
+    v2, g2 = e.nll_and_grad(p2)
+    b, h, _ = e.norm_cache_stats()
+    assert b == 1 and h >= 1
+    assert _nll_close(v2, ref2, tv, nd)
+    assert np.max(np.abs(g2[dirs] - gref2)) / np.max(np.abs(gref2)) < tg
+    assert _nll_close(e.nll(p2), ref2, tv, nd)
 
 
 def test_cc_tags_off_and_b0_tags_give_the_signal_likelihood():

@@ -830,6 +830,33 @@ def test_conjugate_density_of_the_z_chain_alone_is_phi_even_and_the_full_model_i
     assert np.max(np.abs(sm - s) / s) > 1e-2
 
 
+def _swap_helicities(res, par):
+    """The lambda = -1 and lambda = +1 couplings of every K* of spin >= 1 exchanged."""
+    p = np.array(par, dtype=float, copy=True)
+    k = 0
+    for r in res:
+        if r.n_coup == 3:
+            p[k:k + 2], p[k + 4:k + 6] = par[k + 4:k + 6], par[k:k + 2]
+        k += 2 * r.n_coup
+    return p
+
+
+@pytest.mark.parametrize("model", ["full", "full2z", "lass_full2z"])
+def test_reversing_phi_exchanges_the_kstar_helicity_couplings(model):
+    # d^1_{lambda xi} = (-1)^(lambda - xi) d^1_{-lambda,-xi} and d^J_{-lambda 0} = (-1)^lambda d^J_{lambda 0}
+    # turn e^{-i lambda phi} into the opposite helicity: a_xi(-phi; H) = -a_{-xi}(phi; H') with
+    # H'_lambda = H_{-lambda} for the K* chain, and the Z-chain terms of xi = +-1 swap with the
+    # same sign (Eq. 11), so S(-phi; H) = S(phi; H') event by event.
+    res = W.model(model)
+    par = W.params(res, seed=9)
+    ev = W.neutral_events(200, 73)
+    ev[0] = np.clip(ev[0], W.M_LO + 1e-3, W.M_HI - 1e-3)
+    sw = _swap_helicities(res, par)
+    np.testing.assert_allclose(O.density(K, res, par, _mirror(ev)), O.density(K, res, sw, ev), rtol=1e-12)
+    # not a symmetry of S itself: exchanging the couplings alone changes the density
+    assert np.max(np.abs(O.density(K, res, sw, ev) / O.density(K, res, par, ev) - 1.0)) > 1e-2
+
+
 def _cc_inputs(n_d=300, n_m=1500, model="full"):
     res = W.model(model)
     par = W.params(res, seed=61)
