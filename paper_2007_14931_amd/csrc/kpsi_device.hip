@@ -239,6 +239,23 @@ template <int D> __device__ __forceinline__ void swap_halves(float& lo, float& h
   lo = __builtin_bit_cast(float, n0);
   hi = __builtin_bit_cast(float, n1);
 }
+// The value of the partner lane in a butterfly step of width H = 8, 4, 2, 1 within each 16-lane
+// row, by DPP: row_mirror (lane i <-> 15 - i), row_half_mirror (i <-> 7 - i in each half row),
+// and the quad permutations (i <-> i ^ 2, i <-> i ^ 1).  Each pairs lanes whose bit log2(H)
+// differs and whose higher bits agree, which is what the transposed butterfly needs.
+template <int H> __device__ __forceinline__ unsigned dpp_partner(unsigned x) {
+  static_assert(H == 8 || H == 4 || H == 2 || H == 1, "butterfly width");
+  constexpr int ctrl = H == 8 ? 0x140 : (H == 4 ? 0x141 : (H == 2 ? 0x4E : 0xB1));
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, ctrl, 0xF, 0xF, false);
+}
+template <int H> __device__ __forceinline__ float dpp_partner(float x) {
+  return __builtin_bit_cast(float, dpp_partner<H>(__builtin_bit_cast(unsigned, x)));
+}
+template <int H> __device__ __forceinline__ double dpp_partner(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint64_t lo = dpp_partner<H>((unsigned)b), hi = dpp_partner<H>((unsigned)(b >> 32));
+  return __builtin_bit_cast(double, (hi << 32) | lo);
+}
 
 // ------------------------------------------------------------------ compensated sums
 __device__ __forceinline__ void neumaier(double& s, double& c, double x) {
@@ -811,8 +828,8 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     };
     // Transpose butterfly: after the step of width h, lane l keeps h values, each summed
     // with its partner lane's; after the last step lane l holds the wave sum of value l.
-    // The steps of width 32 and 16 use the lane-swap instructions (swap_halves), the rest
-    // lane shuffles.  Slots 0 and 1 carry the FP64 likelihood sums and every value merged into
+    // The steps of width 32 and 16 use the lane-swap instructions (swap_halves), the rest DPP
+    // row permutations (dpp_partner).  Slots 0 and 1 carry the FP64 likelihood sums and every value merged into
     // them (as double); the other slots move the accumulators at their own type (FP32 sums of
     // the wave's FP32 thread accumulators in the FP32 kernel).
     double d[2];
@@ -842,17 +859,16 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
         v[i] = lo + hi;
       }
     }
-#pragma unroll
-    for (int s = 3; s >= 0; --s) {
-      const int half = 1 << s;
-      const bool up = (lane >> s) & 1;
+    auto narrow = [&](auto Hc) {
+      constexpr int half = decltype(Hc)::value;
+      const bool up = lane & half;
 #pragma unroll
       for (int i = 0; i < half; ++i) {
         if (i < 2) {
           const double hv = (i + half < 2) ? d[i + half] : (double)v[i + half];
           const double keep = up ? hv : d[i];
           const double send = up ? d[i] : hv;
-          d[i] = keep + __shfl_xor(send, half, 64);
+          d[i] = keep + dpp_partner<half>(send);
         } else {
           // (the empty asm keeps the two slots as values, so that the selects below stay
           // selects instead of becoming a lane-dependent index into the slot array)
@@ -860,10 +876,14 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
           asm("" : "+v"(a0), "+v"(a1));
           const A_t keep = up ? a1 : a0;
           const A_t send = up ? a0 : a1;
-          v[i] = keep + __shfl_xor(send, half, 64);
+          v[i] = keep + dpp_partner<half>(send);
         }
       }
-    }
+    };
+    narrow(std::integral_constant<int, 8>{});
+    narrow(std::integral_constant<int, 4>{});
+    narrow(std::integral_constant<int, 2>{});
+    narrow(std::integral_constant<int, 1>{});
     red[wave][lane] = d[0];
   } else {
     double v0 = ms, v1 = -mc, v2 = (double)nbad;
