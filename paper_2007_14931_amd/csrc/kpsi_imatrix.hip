@@ -16,62 +16,12 @@
 #include <type_traits>
 
 #include "kpsi_internal.h"
+#include "kpsi_math.h"
 
 namespace kpsi {
 
 namespace im {
 
-__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp_(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-__device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
-__device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
-__device__ __forceinline__ double rsq_(double x) {
-  double r = __builtin_amdgcn_rsq(x);
-  double h = 0.5 * x;
-  double e = __builtin_fma(-h * r, r, 0.5);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-h * r, r, 0.5);
-  return __builtin_fma(r, e, r);
-}
-template <int L, typename T> __device__ __forceinline__ T bpoly(T z) {
-  if constexpr (L == 0) return T(1);
-  else if constexpr (L == 1) return T(1) + z;
-  else if constexpr (L == 2) return T(9) + z * (T(3) + z);
-  else if constexpr (L == 3) return T(225) + z * (T(45) + z * (T(6) + z));
-  else return T(11025) + z * (T(1575) + z * (T(135) + z * (T(10) + z)));
-}
-template <typename T, int n> __device__ __forceinline__ T ipow(T x) {
-  T r = T(1);
-#pragma unroll
-  for (int i = 0; i < n; ++i) r *= x;
-  return r;
-}
-template <int J, typename T> __device__ __forceinline__ T d00(T c) {
-  if constexpr (J == 0) return T(1);
-  else if constexpr (J == 1) return c;
-  else if constexpr (J == 2) return T(1.5) * c * c - T(0.5);
-  else if constexpr (J == 3) return c * (T(2.5) * c * c - T(1.5));
-  else { T c2 = c * c; return (T(35) * c2 * c2 - T(30) * c2 + T(3)) * T(0.125); }
-}
-template <int J, typename T> __device__ __forceinline__ T d10(T c, T s) {
-  if constexpr (J == 1) return -s * T(0.70710678118654752440);
-  else if constexpr (J == 2) return -s * c * T(1.22474487139158904910);
-  else if constexpr (J == 3) return -s * (T(15) * c * c - T(3)) * T(0.14433756729740644113);
-  else if constexpr (J == 4) return -s * c * (T(35) * c * c - T(15)) * T(0.11180339887498948482);
-  else return T(0);
-}
-template <class Sh> __host__ __device__ constexpr int slot_base(int J) {
-  int b = 0;
-  for (int j = 0; j < J; ++j) b += Sh::N[j];
-  return b;
-}
 template <class Sh> __host__ __device__ constexpr int comp_base(int J) {   // first component of spin J
   int b = 0;
   for (int j = 0; j < J; ++j) b += Sh::N[j] * (j == 0 ? 1 : 3);
@@ -161,7 +111,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void im
       auto do_spin = [&](auto Jc) {
         constexpr int J = decltype(Jc)::value;
         if constexpr (Sh::N[J] > 0) {
-          constexpr int LB = (J == 0) ? 1 : J - 1;
+          constexpr int LB = LBof<J>::v;
           const T BR = bpoly<J>(zR), BB = bpoly<LB>(zB);
           // n_J with the row weight sqrt(eps) folded in
           const T nJ = ipow<T, LB>(pbm) * ipow<T, J>(qm) * rsq_(BR * BB) * sw;

@@ -88,6 +88,7 @@ struct kpsi_ctx {
   double t_ms = 0.0;
   int64_t t_n = 0;
   std::vector<float> t_samples;  // the first kTimingSamples timed durations since the last reset
+  int64_t t_dropped = 0;         // timed calls whose duration could not be read
   int ept_override = 0;
   int n_cu = 0;                                                   // compute units of the device
   int blocks_per_cu[2][3][2] = {{{-1, -1}, {-1, -1}, {-1, -1}}, {{-1, -1}, {-1, -1}, {-1, -1}}};   // [shape][mode][cc]
@@ -676,10 +677,16 @@ kpsi_status wait_stream(kpsi_ctx* c) {
   if (c->done_flag) {
     const uint64_t want = ++c->done_seq;
     if (hipStreamWriteValue64(c->stream, c->done_dev, want, 0) == hipSuccess) {
-      volatile const uint64_t* f = c->done_host;
       const auto t0 = std::chrono::steady_clock::now();
       for (unsigned k = 1;; ++k) {
-        if (*f == want) return KPSI_OK;
+        // acquire: the reduced record the GPU wrote before the sequence number is read after it
+        if (__atomic_load_n(c->done_host, __ATOMIC_ACQUIRE) == want) {
+          // a launch error of this call's kernels (their asynchronous faults stop the stream,
+          // so the word never changes and the synchronisation below reports them)
+          const hipError_t le = hipGetLastError();
+          if (le != hipSuccess) return fail(c, KPSI_E_HIP, "kernel launch: %s", hipGetErrorString(le));
+          return KPSI_OK;
+        }
         if ((k & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) break;
       }
     } else {
@@ -786,11 +793,15 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   if (mode == MODE_DENSITY) return KPSI_OK;
   if (kpsi_status ws = wait_stream(c)) return ws;
   if (c->timing) {
+    // the polled completion word can change before the runtime marks ev1 complete: wait for it,
+    // so that no timed sample is lost
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) {
+    if (hipEventSynchronize(c->ev1) == hipSuccess && hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) {
       c->t_ms += ms;
       c->t_n += 1;
       if (c->t_samples.size() < kTimingSamples) c->t_samples.push_back(ms);
+    } else {
+      c->t_dropped += 1;
     }
   }
   return KPSI_OK;
@@ -1623,7 +1634,7 @@ kpsi_status kpsi_timing(kpsi_ctx* c, double* ms, int64_t* n, int reset) {
   if (!c) return KPSI_E_ARG;
   if (ms) *ms = c->t_ms;
   if (n) *n = c->t_n;
-  if (reset) { c->t_ms = 0.0; c->t_n = 0; c->t_samples.clear(); }
+  if (reset) { c->t_ms = 0.0; c->t_n = 0; c->t_dropped = 0; c->t_samples.clear(); }
   return KPSI_OK;
 }
 
