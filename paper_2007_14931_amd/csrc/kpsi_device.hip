@@ -445,7 +445,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
           for (int j = 0; j < Sh::N[J]; ++j) {
             {
               const auto& rc = ka.ks[sb + j];
-              const T dre = rc.M2 - m2;
+              const T dre = pole_gap(rc, m2);
               const T dim = rc.P * gJ;   // M Gamma(m)
               const T inv = rcp_(fma_(dre, dre, dim * dim));
               const T br = dre * inv, bi = dim * inv;
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
         for (int z = 0; z < NZ; ++z) {
           if (z < a.cnt[5]) {
             const auto& rc = ka.zs[z];
-            const T dre = rc.M2 - mz2;
+            const T dre = pole_gap(rc, mz2);
             const T dim = rc.P * gzv;
             const T inv = rcp_(fma_(dre, dre, dim * dim));
             AZ[z] = Cx<T>{dre * inv, dim * inv};

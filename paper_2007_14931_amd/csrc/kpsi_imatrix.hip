@@ -121,7 +121,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void im
           for (int j = 0; j < Sh::N[J]; ++j) {
             if (j >= a.cnt[J]) continue;
             const auto& rc = a.ks[slot_base<Sh>(J) + j];
-            const T dre = rc.M2 - m2, dim = -rc.P * gJ;
+            const T dre = pole_gap(rc, m2), dim = -rc.P * gJ;
             const T inv = rcp_(dre * dre + dim * dim);
             const T sc = rc.K * nJ * inv;
             const T br = sc * dre, bi = -sc * dim;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void im
           for (int z = 0; z < NZ; ++z) {
             if (z >= a.cnt[5]) continue;
             const auto& rc = a.zs[z];
-            const T dre = rc.M2 - mz2, dim = -rc.P * gz;
+            const T dre = pole_gap(rc, mz2), dim = -rc.P * gz;
             const T inv = rcp_(dre * dre + dim * dim);
             const T sc = rc.K * inv * sw;
             const T Ar = sc * dre, Ai = -sc * dim;

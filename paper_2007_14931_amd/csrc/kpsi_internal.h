@@ -26,6 +26,7 @@ enum { MODE_DENSITY = 0, MODE_NLL = 1, MODE_GRAD = 2 };
 //   den(m) = M2 - m^2 - i P g(m),  A(m) = K n(m) / den(m)
 template <typename T> struct RC {
   T M2, P, K;
+  T M2lo;             // M^2 - M2 (FP32 constants: the rounding remainder of M^2; FP64: 0)
   T hr[3], hi[3];     // K*: lambda = -1, 0, +1; Z: [0] lambda' = 0, [1] lambda' = +-1
   T kap, twoM, dP, PoG;   // d ln K/dM, 2M, dP/dM, P/Gamma0
   int flt;            // floating slot or -1

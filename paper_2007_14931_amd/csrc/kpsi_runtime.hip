@@ -199,6 +199,7 @@ LsConst lineshape_consts(const kpsi_kinematics& k, const kpsi_resonance& r, doub
 // accumulators come out divided by K (undone in kpsi_nll_and_grad).
 template <typename T> void fill_rc(RC<T>& rc, const LsConst& c, const double* hr, const double* hi, int nl, int flt) {
   rc.M2 = (T)c.M2; rc.P = (T)c.P; rc.K = (T)c.K;
+  rc.M2lo = (T)(c.M2 - (double)rc.M2);
   for (int l = 0; l < 3; ++l) {
     rc.hr[l] = (T)(l < nl ? c.K * hr[l] : 0.0);
     rc.hi[l] = (T)(l < nl ? c.K * hi[l] : 0.0);

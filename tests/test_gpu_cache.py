@@ -11,6 +11,7 @@ import pytest
 from oracle import oracle as O
 from paper_2007_14931_amd import kpsi
 from paper_2007_14931_amd import workloads as W
+from parity_bars import check_grad, check_nll
 
 K = W.KIN
 pytestmark = pytest.mark.gpu
@@ -79,15 +80,15 @@ def test_cached_fp32_matches_oracle_across_tile_shapes(model, floating):
     free = np.flatnonzero(W.free_mask(res, floating))
     st, ref, gref = O.nll(K, res, par, data, mc, dirs=free)
     assert st == 0
-    assert abs(v - ref) <= 1e-6 * max(abs(ref), 2.0 * data.shape[1])
-    assert np.max(np.abs(g[free] - gref)) / np.max(np.abs(gref)) < 2e-5
+    check_nll(v, ref, "fp32", data.shape[1], f"cached {model}")
+    check_grad(g[free], gref, "fp32", f"cached {model}")
     # couplings only: served from the cache
     p2 = par.copy()
     p2[1] += 0.05
     v2 = e.nll(p2)
     assert e.norm_cache_stats()[1] >= 1
     ref2 = O.nll(K, res, p2, data, mc)[1]
-    assert abs(v2 - ref2) <= 1e-6 * max(abs(ref2), 2.0 * data.shape[1])
+    check_nll(v2, ref2, "fp32", data.shape[1], f"cached {model} couplings-only")
 
 
 def test_cached_fp32_and_efficiency():
@@ -98,8 +99,8 @@ def test_cached_fp32_and_efficiency():
     v, g = e.nll_and_grad(par)
     free = np.flatnonzero(W.free_mask(res, floating))
     st, ref, gref = O.nll(K, res, par, data, mc, eps=eps, dirs=free)
-    assert v == pytest.approx(ref, rel=1e-6)
-    assert np.max(np.abs(g[free] - gref)) / np.max(np.abs(gref)) < 2e-5
+    check_nll(v, ref, "fp32", 0, "cached with efficiency")   # plain relative bar
+    check_grad(g[free], gref, "fp32", "cached with efficiency")
 
 
 def test_auto_mode_builds_on_repeated_lineshape_point():

@@ -1,7 +1,7 @@
 """Parity at the benchmark's full size and launch configuration: 1,000,000 data events and
 2,000,000 normalisation events, ten K* + Z(4430), K*(1410) and Z(4430) lineshapes floating.
 
-The oracle evaluates the full NLL over all 3e6 events, the gradient along a subset of
+The oracle evaluates the full NLL over all 3e6 events, the gradient along all 54 free
 directions (dual numbers over all events), and per-event densities on a sample.
 """
 import numpy as np
@@ -10,6 +10,7 @@ import pytest
 from oracle import oracle as O
 from paper_2007_14931_amd import kpsi
 from paper_2007_14931_amd import workloads as W
+from parity_bars import check_grad, check_nll
 
 K = W.KIN
 pytestmark = pytest.mark.gpu
@@ -38,26 +39,26 @@ def _engine(res, prec, data, mc):
     return e
 
 
-@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-10), ("fp32", 1e-6)])
-def test_full_size_nll(full, prec, rtol):
+@pytest.fixture(scope="module")
+def full_grad(full):
     res, data, mc, par, ref = full
-    e = _engine(res, prec, data, mc)
-    assert e.nll(par) == pytest.approx(ref, rel=rtol)
-    v, g = e.nll_and_grad(par)
-    assert v == pytest.approx(ref, rel=rtol)
-
-
-def test_full_size_gradient_subset(full):
-    res, data, mc, par, ref = full
-    nc = sum(2 * r.n_coup for r in res)
-    i1410 = [r.name for r in res].index("K*(1410)")
-    iz = [r.name for r in res].index("Z(4430)")
-    dirs = [0, 5, W.coupling_offset(res, iz) + 3, nc + 2 * i1410, nc + 2 * i1410 + 1, nc + 2 * iz + 1]
+    dirs = np.flatnonzero(W.free_mask(res, FLOATING))
     st, v, gref = O.nll(K, res, par, data, mc, dirs=dirs)
-    for prec, tol in (("fp64", 1e-8), ("fp32", 3e-4)):
-        v, g = _engine(res, prec, data, mc).nll_and_grad(par)
-        err = np.abs(g[dirs] - gref) / np.max(np.abs(gref))
-        assert np.all(err < tol), (prec, err)
+    assert st == 0
+    return dirs, v, gref
+
+
+@pytest.mark.parametrize("prec,gtol", [("fp64", 1e-8), ("fp32", None)])
+def test_full_size_nll_and_gradient(full, full_grad, prec, gtol):
+    res, data, mc, par, ref = full
+    dirs, vref, gref = full_grad
+    assert len(dirs) == 54
+    e = _engine(res, prec, data, mc)
+    nd = data.shape[1]
+    check_nll(e.nll(par), ref, prec, nd, "full size nll-only")
+    v, g = e.nll_and_grad(par)
+    check_nll(v, vref, prec, nd, "full size")
+    check_grad(g[dirs], gref, prec, "full size", norm=gtol)
 
 
 def test_full_size_sampled_densities(full):

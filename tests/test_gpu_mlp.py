@@ -9,6 +9,7 @@ import pytest
 from oracle import oracle as O
 from paper_2007_14931_amd import kpsi
 from paper_2007_14931_amd import workloads as W
+from parity_bars import check_probabilities
 
 K = W.KIN
 pytestmark = pytest.mark.gpu
@@ -43,25 +44,7 @@ def test_network_gradient_and_output_match_reference(n):
     for blk in (slice(0, 256), slice(256, 320), slice(320, 4416), slice(4416, 4480), slice(4480, 4545)):
         assert np.linalg.norm(g[blk] - ref_g[blk]) <= 1e-3 * np.linalg.norm(ref_g[blk]) + 1e-9
     p = e.mlp_eval(par, _cuda(ev)).cpu().numpy()
-    _check_probabilities(p, ref_p, par, u)
-
-
-def _check_probabilities(p, ref_p, par, u):
-    """The device rounds silu(z1) to BF16 from an FP32 value, the reference from an FP64 one.
-    Where the two straddle a BF16 rounding boundary, one hidden unit differs by one BF16 ulp
-    (at most 2^-8 of its value). Through the 64x64 layer (|silu'| < 1.1) and the sigmoid
-    (slope <= 1/4) that moves p by at most
-        (1/4) * max_i sum_o |w3_o| 1.1 |W2_oi| * 2^-8 max|h1|   per flipped unit.
-    Every other event must agree to FP32 accuracy, and flips must be rare."""
-    W1, b1 = par[:256].reshape(64, 4).astype(np.float64), par[256:320].astype(np.float64)
-    W2, w3 = par[320:4416].reshape(64, 64).astype(np.float64), par[4480:4544].astype(np.float64)
-    z1 = u @ W1.T + b1
-    h1max = np.max(np.abs(z1 / (1 + np.exp(-z1))))
-    one_flip = 0.25 * np.max(np.abs(w3) @ (1.1 * np.abs(W2))) * 2.0 ** -8 * h1max
-    d = np.abs(p - ref_p)
-    tight = d <= 1e-5 * np.abs(ref_p) + 1e-6
-    assert tight.mean() >= 0.995, f"{(~tight).sum()} of {d.size} events outside FP32 agreement"
-    assert d.max() <= 2 * one_flip, f"max difference {d.max():.3g} exceeds two BF16 flips ({2 * one_flip:.3g})"
+    check_probabilities(p, ref_p, par, u)
 
 
 def test_labels_and_histogram():
