@@ -136,6 +136,18 @@ kpsi_status kpsi_nll(kpsi_ctx* ctx, const double* params, double* nll);
 /* NLL and its gradient with respect to every coupling entry and the (M, Gamma0) of the
  * resonances selected with kpsi_set_floating, in one pass (hand-written adjoint). */
 kpsi_status kpsi_nll_and_grad(kpsi_ctx* ctx, const double* params, double* nll, double* grad);
+/* kpsi_nll_and_grad for callers that cannot allocate device memory during the call (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation).  Same arguments,
+ * layout, results and errors as kpsi_nll_and_grad, with every data and normalisation event
+ * evaluated directly: the interference-matrix cache is neither built nor consulted, and no
+ * timing sample is recorded.  The call allocates nothing: its block partials live in a static
+ * device array of the library (8 MiB per device, held until the process ends) instead of a
+ * buffer the context grows.  A call needing more than 16384 block partials (events per block:
+ * 256 x the events per thread) returns KPSI_E_ARG before any work is enqueued.  The array is
+ * shared by every context on a device and keeps the last call's contents (each call writes
+ * every partial it reads): calls that overlap on one device, from different streams or
+ * threads, race on it and must be serialised by the caller. */
+kpsi_status kpsi_nll_and_grad_noalloc(kpsi_ctx* ctx, const double* params, double* nll, double* grad);
 
 /* Diagnostics (not on the fit path).  Per-event density S of a loaded set into a host
  * array of n doubles (S of Eq. 12 at the event as loaded: flavour tags and the background

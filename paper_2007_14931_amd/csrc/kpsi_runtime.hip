@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,7 +22,36 @@
 
 using namespace kpsi;
 
+// Block partials of kpsi_nll_and_grad_noalloc: a fixed device array in place of the buffer a
+// context allocates (16384 block partials of NACC doubles, 8 MiB).  Each device holds its own
+// copy for the life of the process; host code reaches it only through the address looked up
+// per device (scratch_ptr), never through the array's name.
+constexpr size_t kScratchDoubles = (size_t)16384 * NACC;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_looked_up[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with that device current
+// (kpsi_create); null when the lookup failed or the device index is beyond the table.
+void lookup_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_looked_up[device]) return;
+  g_scratch_looked_up[device] = true;
+  double* ptr = nullptr;
+  if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[device] = ptr;
+  else (void)hipGetLastError();
+}
+double* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 struct DevSet {
   int64_t n = 0;
@@ -699,8 +729,11 @@ kpsi_status wait_stream(kpsi_ctx* c) {
   return KPSI_OK;
 }
 
+// `fixed` (may be null): a caller-provided block-partial buffer of `fixed_cap` doubles used in place
+// of the context's own (which may grow by allocation); calls that would need more fail.
 template <typename T, class Sh>
-kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: both*/, double** dens_out) {
+kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: both*/, double** dens_out,
+                    double* fixed, size_t fixed_cap) {
   AmpArgs<T, Sh> a{};
   for (int s = 0; s < 2; ++s) {
     a.cols[s] = (const T*)c->set[s].cols;
@@ -719,7 +752,7 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
     a.bkg_coef = c->bkg_coef;
     a.purity = (T)c->purity;
   }
-  c->timing = mode != MODE_DENSITY && c->timing_every > 0 && (c->timing_calls++ % c->timing_every) == 0;
+  c->timing = !fixed && mode != MODE_DENSITY && c->timing_every > 0 && (c->timing_calls++ % c->timing_every) == 0;
   if (c->timing) hipEventRecord(c->ev0, c->stream);
   // Launches over the events of [nd data, nm normalisation] write block partials (rows of
   // nbd + nbm blocks, data first); one reduction then writes the record of each set covered
@@ -744,11 +777,21 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
     chunk_d = BLOCK * pick_ept<T, Sh>(c, mode, nd, 0);
   }
   const int nbd = (int)((nd + chunk_d - 1) / chunk_d), nbm = (int)((nm + chunk_m - 1) / chunk_m);
+  double* part = c->partial;
   if (mode != MODE_DENSITY) {
-    kpsi_status st = ensure_partial(c, (size_t)(nbd + nmsets * nbm));
-    if (st) return st;
+    const size_t rows = (size_t)(nbd + nmsets * nbm);
+    if (fixed) {
+      if (rows * NACC > fixed_cap)
+        return fail(c, KPSI_E_ARG, "%zu block partials of %d doubles exceed the static scratch of %zu doubles "
+                    "(at most %zu blocks)", rows, NACC, fixed_cap, fixed_cap / NACC);
+      part = fixed;
+    } else {
+      kpsi_status st = ensure_partial(c, rows);
+      if (st) return st;
+      part = c->partial;
+    }
   }
-  a.partial = c->partial;
+  a.partial = part;
   a.pstride = nbd + nmsets * nbm;
   a.nb_mc = nbm;
   auto launch = [&](const AmpArgs<T, Sh>& b, int nblocks) -> kpsi_status {
@@ -777,7 +820,7 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
       b.nb_data = nbd;
       b.poff = 0;
       if (nm > 0) {
-        b.mc_part = c->partial + nbd;
+        b.mc_part = part + nbd;
         b.mc_nb = nbm;
       }
       st = launch(b, nbd);
@@ -786,7 +829,7 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   if (st) return st;
   if (c->timing) hipEventRecord(c->ev1, c->stream);   // end of the per-event work
   if (mode != MODE_DENSITY) {
-    hipError_t e = launch_reduce_final(c->partial, nbd, nbm, nmsets, nv, c->red, nd > 0 ? 0 : 1,
+    hipError_t e = launch_reduce_final(part, nbd, nbm, nmsets, nv, c->red, nd > 0 ? 0 : 1,
                                        (nd > 0) + (nm > 0) * nmsets, c->stream);
     if (e != hipSuccess) return fail(c, KPSI_E_HIP, "reduction kernel: %s", hipGetErrorString(e));
   }
@@ -808,13 +851,14 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   return KPSI_OK;
 }
 
-kpsi_status dispatch(kpsi_ctx* c, int mode, const double* par, int which, double** dens) {
+kpsi_status dispatch(kpsi_ctx* c, int mode, const double* par, int which, double** dens, double* fixed = nullptr,
+                     size_t fixed_cap = 0) {
   if (c->prec == KPSI_FP32) {
-    return c->shape == 0 ? run_amp<float, ShapeSmall>(c, mode, par, which, dens)
-                         : run_amp<float, ShapeFull>(c, mode, par, which, dens);
+    return c->shape == 0 ? run_amp<float, ShapeSmall>(c, mode, par, which, dens, fixed, fixed_cap)
+                         : run_amp<float, ShapeFull>(c, mode, par, which, dens, fixed, fixed_cap);
   }
-  return c->shape == 0 ? run_amp<double, ShapeSmall>(c, mode, par, which, dens)
-                       : run_amp<double, ShapeFull>(c, mode, par, which, dens);
+  return c->shape == 0 ? run_amp<double, ShapeSmall>(c, mode, par, which, dens, fixed, fixed_cap)
+                       : run_amp<double, ShapeFull>(c, mode, par, which, dens, fixed, fixed_cap);
 }
 
 kpsi_status check_ready(kpsi_ctx* c, const double* params) {
@@ -850,6 +894,7 @@ kpsi_status kpsi_create(int device, void* stream, kpsi_precision prec, kpsi_ctx*
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(nullptr, KPSI_E_HIP, "no HIP device");
   if (device < 0 || device >= ndev) return fail(nullptr, KPSI_E_ARG, "device %d out of range", device);
   if (hipSetDevice(device) != hipSuccess) return fail(nullptr, KPSI_E_HIP, "hipSetDevice failed");
+  lookup_scratch(device);
   kpsi_ctx* c = new kpsi_ctx();
   c->device = device;
   c->prec = prec;
@@ -1353,20 +1398,9 @@ kpsi_status kpsi_nll(kpsi_ctx* c, const double* params, double* nll) {
   return KPSI_OK;
 }
 
-kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, double* grad) {
-  kpsi_status st = check_ready(c, params);
-  if (st) return st;
-  if (!nll || !grad) return fail(c, KPSI_E_ARG, "nll/grad is NULL");
-  hipSetDevice(c->device);
-  bool cached = false;
-  st = use_cache(c, params, &cached);
-  if (st) return st;
-  if (cached) {
-    st = put_cached_record(c, params);
-    if (st) return st;
-  }
-  st = dispatch(c, MODE_GRAD, params, cached ? 0 : -1, nullptr);
-  if (st) return st;
+// -2 ln L and its gradient from the reduced records of a gradient-mode pass (the normalisation
+// record from the interference matrix when `cached`).
+static kpsi_status assemble_grad(kpsi_ctx* c, const double* params, bool cached, double* nll, double* grad) {
   const double* rd = c->red_host;
   const double* rm = c->red_host + NACC;
   const double* rm2 = c->red_host + 2 * NACC;
@@ -1416,6 +1450,38 @@ kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, do
   }
   *nll += add_constraints(c, params, grad);
   return KPSI_OK;
+}
+
+kpsi_status kpsi_nll_and_grad(kpsi_ctx* c, const double* params, double* nll, double* grad) {
+  kpsi_status st = check_ready(c, params);
+  if (st) return st;
+  if (!nll || !grad) return fail(c, KPSI_E_ARG, "nll/grad is NULL");
+  hipSetDevice(c->device);
+  bool cached = false;
+  st = use_cache(c, params, &cached);
+  if (st) return st;
+  if (cached) {
+    st = put_cached_record(c, params);
+    if (st) return st;
+  }
+  st = dispatch(c, MODE_GRAD, params, cached ? 0 : -1, nullptr);
+  if (st) return st;
+  return assemble_grad(c, params, cached, nll, grad);
+}
+
+// The same pass with its block partials in the static device array: nothing is allocated.  Every
+// partial the final reduction reads is written by the per-event launch of the same call, so the
+// array needs no clearing between calls.
+kpsi_status kpsi_nll_and_grad_noalloc(kpsi_ctx* c, const double* params, double* nll, double* grad) {
+  kpsi_status st = check_ready(c, params);
+  if (st) return st;
+  if (!nll || !grad) return fail(c, KPSI_E_ARG, "nll/grad is NULL");
+  double* scr = scratch_ptr(c->device);
+  if (!scr) return fail(c, KPSI_E_HIP, "the static scratch array has no address on device %d", c->device);
+  hipSetDevice(c->device);
+  st = dispatch(c, MODE_GRAD, params, -1, nullptr, scr, kScratchDoubles);
+  if (st) return st;
+  return assemble_grad(c, params, false, nll, grad);
 }
 
 kpsi_status kpsi_density(kpsi_ctx* c, kpsi_set set, const double* params, double* out) {

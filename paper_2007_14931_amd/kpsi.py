@@ -29,7 +29,7 @@ EXPORTS = [
     "kpsi_fit_default_options", "kpsi_migrad", "kpsi_hesse", "kpsi_set_norm_cache", "kpsi_norm_cache_stats",
     "kpsi_mlp_default_options", "kpsi_accept_labels", "kpsi_hist_efficiency", "kpsi_mlp_grad", "kpsi_mlp_train",
     "kpsi_mlp_eval", "kpsi_set_efficiency_mlp", "kpsi_fit_fractions", "kpsi_measure_peaks", "kpsi_set_background",
-    "kpsi_template_values", "kpsi_set_flavour", "kpsi_set_constraints",
+    "kpsi_template_values", "kpsi_set_flavour", "kpsi_set_constraints", "kpsi_nll_and_grad_noalloc",
 ]
 MLP_NP = 4545
 
@@ -107,6 +107,7 @@ def lib() -> C.CDLL:
         # path passes ndarray.ctypes.data integers; ctypes pointer objects are accepted too)
         L.kpsi_nll.argtypes = [vp, vp, vp]
         L.kpsi_nll_and_grad.argtypes = [vp, vp, vp, vp]
+        L.kpsi_nll_and_grad_noalloc.argtypes = [vp, vp, vp, vp]
         L.kpsi_density.argtypes = [vp, C.c_int, dp, dp]
         L.kpsi_invariants.argtypes = [vp, C.c_int, dp]
         L.kpsi_generate_phsp.argtypes = [vp, C.c_uint64, i64, C.c_double, vp, vp, vp, vp]
@@ -263,6 +264,15 @@ class Engine:
         p = _f64(params)
         g = np.empty(self.n_params)
         st = self.L.kpsi_nll_and_grad(self.h, p.ctypes.data, self._out_addr, g.ctypes.data)
+        if st:
+            self._chk(st)
+        return self._out.value, g
+
+    def nll_and_grad_noalloc(self, params) -> tuple[float, np.ndarray]:
+        """kpsi_nll_and_grad_noalloc: the same pass with no device allocation (static scratch)."""
+        p = _f64(params)
+        g = np.empty(self.n_params)
+        st = self.L.kpsi_nll_and_grad_noalloc(self.h, p.ctypes.data, self._out_addr, g.ctypes.data)
         if st:
             self._chk(st)
         return self._out.value, g
