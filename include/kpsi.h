@@ -114,7 +114,9 @@ kpsi_status kpsi_set_floating(kpsi_ctx* ctx, const int* flags, int n_res);
  * host arrays of n doubles each (copied).  Replaces a previously loaded set. */
 kpsi_status kpsi_load_events(kpsi_ctx* ctx, kpsi_set set, int64_t n, const double* m_kpi, const double* cos_k,
                              const double* cos_j, const double* phi);
-/* Same from device arrays (borrowed; see ownership above). */
+/* Same from device arrays (borrowed; see ownership above).  The library reads them on the
+ * context's stream: work that writes them on another stream (a torch stream, say) must have
+ * completed before the call, or the context must be created on that stream. */
 kpsi_status kpsi_load_events_device(kpsi_ctx* ctx, kpsi_set set, int64_t n, const double* m_kpi,
                                     const double* cos_k, const double* cos_j, const double* phi);
 
@@ -128,6 +130,24 @@ kpsi_status kpsi_set_efficiency_values(kpsi_ctx* ctx, const double* eps, int64_t
  * normalisation event on the device. */
 kpsi_status kpsi_set_efficiency_hist(kpsi_ctx* ctx, const float* eff, const int nb[4], const double lo[4],
                                      const double hi[4]);
+/* Importance-sampled normalisation (the normalisation integral of Eq. 12-14 estimated over
+ * phase-space points that are not all flat; State-of-the-art section: the normalisation is
+ * evaluated numerically over millions of phase-space points).  The loaded normalisation set is
+ * taken as a mixture: its first n_flat events drawn flat in phase space, the other n - n_flat
+ * drawn from the density S(y; params0) (for instance by kpsi_generate_model at params0, without
+ * an efficiency).  Each event then gets the weight
+ *   w_j = 1 / (alpha + (1 - alpha) S(y_j; params0) / Z0),   alpha = n_flat / n,
+ * Z0 = the flat events' mean of S(y; params0): the ratio of flat phase space to the mixture's
+ * density, so that weighted sums over the set estimate flat phase-space integrals for any
+ * parameters.  The weights multiply the efficiency in every normalisation sum (the per-event
+ * kernel, the interference matrix), weight the efficiency-free fit-fraction integrals and the
+ * background normalisation of kpsi_set_background, and survive later kpsi_set_efficiency_*
+ * calls.  n_flat = n removes them.  Events placed under a narrow peak this way lower the
+ * statistical error of the normalisation (and of the fitted parameters it moves) where the
+ * data are.  Errors: KPSI_E_STATE without a model or normalisation set, or when a background
+ * is already set (set the mixture first); KPSI_E_ARG for n_flat outside [1, n], non-finite
+ * params0, or a density that is negative or not finite. */
+kpsi_status kpsi_set_norm_mixture(kpsi_ctx* ctx, const double* params0, int64_t n_flat);
 
 /* -2 ln L (Eq. 14 signal part, purity 1):
  *   NLL = -2 sum_data ln S(x_i) + 2 N_data ln( (1/N_norm) sum_norm eps_j S(y_j) )

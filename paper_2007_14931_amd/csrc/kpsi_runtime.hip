@@ -83,7 +83,13 @@ struct kpsi_ctx {
   bool has_z = false;
   std::vector<int> fslot;       // table index -> floating slot or -1
   DevSet set[2];
-  void* eps = nullptr;          // T array over the normalisation set, or null (flat)
+  void* eps = nullptr;          // T array over the normalisation set, or null (flat): the
+                                // efficiency times the importance weight of each event
+  double* eps_f64 = nullptr;    // FP64 efficiency over the normalisation set, or null (flat)
+  // importance weights of a mixed normalisation set (kpsi_set_norm_mixture), or null (flat set)
+  double* norm_w = nullptr;     // FP64, device
+  void* wcol = nullptr;         // the same as a T column (efficiency-free integrals)
+  std::vector<double> norm_w_host;
   double* partial = nullptr;
   size_t partial_cap = 0;       // in doubles
   // Completion flag of a call: the stream writes done_seq into done_host (mapped pinned memory)
@@ -381,6 +387,26 @@ template <typename T> __global__ void to_t_kernel(const double* in, T* out, int6
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = (T)in[i];
 }
+// out = a * b elementwise (a or b null: 1), as T
+template <typename T> __global__ void prod_t_kernel(const double* a, const double* b, T* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (T)((a ? a[i] : 1.0) * (b ? b[i] : 1.0));
+}
+
+// A T column a * b over the normalisation set (either factor may be null), replacing *col.
+kpsi_status product_column(kpsi_ctx* c, const double* a, const double* b, void** col) {
+  const int64_t n = c->set[1].n;
+  void* e = nullptr;
+  if (hipMalloc(&e, (size_t)n * tsize(c)) != hipSuccess) return fail(c, KPSI_E_OOM, "per-event column");
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (c->prec == KPSI_FP32) hipLaunchKernelGGL(prod_t_kernel<float>, dim3(nb), dim3(256), 0, c->stream, a, b, (float*)e, n);
+  else hipLaunchKernelGGL(prod_t_kernel<double>, dim3(nb), dim3(256), 0, c->stream, a, b, (double*)e, n);
+  hipError_t er = hipStreamSynchronize(c->stream);
+  if (er != hipSuccess) { hipFree(e); return fail(c, KPSI_E_HIP, "column product: %s", hipGetErrorString(er)); }
+  if (*col) hipFree(*col);
+  *col = e;
+  return KPSI_OK;
+}
 
 kpsi_status validate(kpsi_ctx* c, int64_t n, const double* const* obs) {
   if (n == 0) return KPSI_OK;
@@ -503,7 +529,7 @@ kpsi_status gram_build_t(kpsi_ctx* c, const double* par, bool with_eps, bool wit
   a.cols = (const T*)d.cols;
   a.ld = d.ld;
   a.n = d.n;
-  a.eps = with_eps ? (const T*)c->eps : nullptr;
+  a.eps = with_eps ? (const T*)c->eps : (const T*)c->wcol;   // wcol: importance weights or null
   a.partial = c->cache_partial;
   a.ncols = ncols;
   a.skip_last = (NT > 1 && 16 * (NT - 1) >= 2 * ncomp) ? 1 : 0;
@@ -936,6 +962,9 @@ kpsi_status kpsi_destroy(kpsi_ctx* c) {
     if (c->set[s].cols) hipFree(c->set[s].cols);
   }
   if (c->eps) hipFree(c->eps);
+  if (c->eps_f64) hipFree(c->eps_f64);
+  if (c->norm_w) hipFree(c->norm_w);
+  if (c->wcol) hipFree(c->wcol);
   if (c->partial) hipFree(c->partial);
   if (c->cache_partial) hipFree(c->cache_partial);
   if (c->cache_out) hipFree(c->cache_out);
@@ -1110,10 +1139,12 @@ kpsi_status kpsi_set_background(kpsi_ctx* c, double purity, const double* eps_da
     if (eps_data && (!(eps_data[i] >= 0.0) || !std::isfinite(eps_data[i])))
       return fail(c, KPSI_E_ARG, "eps_data[%lld] invalid", (long long)i);
   }
-  double s = 0.0, comp = 0.0;   // Neumaier sum of b over the normalisation events
+  // Neumaier sum of b over the normalisation events (times their importance weights, if any)
+  double s = 0.0, comp = 0.0;
+  const bool wtd = !c->norm_w_host.empty();
   for (int64_t j = 0; j < nm; ++j) {
-    const double x = b_norm[j];
-    if (!(x >= 0.0) || !std::isfinite(x)) return fail(c, KPSI_E_ARG, "b_norm[%lld] invalid", (long long)j);
+    if (!(b_norm[j] >= 0.0) || !std::isfinite(b_norm[j])) return fail(c, KPSI_E_ARG, "b_norm[%lld] invalid", (long long)j);
+    const double x = wtd ? b_norm[j] * c->norm_w_host[j] : b_norm[j];
     const double t = s + x;
     comp += (std::fabs(s) >= std::fabs(x)) ? (s - t) + x : (x - t) + s;
     s = t;
@@ -1193,6 +1224,15 @@ kpsi_status kpsi_template_values(kpsi_ctx* c, kpsi_set set, const float* t_mass,
   return KPSI_OK;
 }
 
+// The efficiency, importance weights and their columns belong to the loaded normalisation set.
+static void drop_norm_columns(kpsi_ctx* c) {
+  for (void** p : {&c->eps, (void**)&c->eps_f64, (void**)&c->norm_w, &c->wcol}) {
+    if (*p) hipFree(*p);
+    *p = nullptr;
+  }
+  c->norm_w_host.clear();
+}
+
 kpsi_status kpsi_load_events(kpsi_ctx* c, kpsi_set set, int64_t n, const double* m, const double* ck,
                              const double* cj, const double* phi) {
   kpsi_status st = load_common(c, set, n);
@@ -1212,7 +1252,7 @@ kpsi_status kpsi_load_events(kpsi_ctx* c, kpsi_set set, int64_t n, const double*
   st = validate(c, n, d.obs);
   if (st) return st;
   d.n = n;
-  if (set == KPSI_NORM && c->eps) { hipFree(c->eps); c->eps = nullptr; }
+  if (set == KPSI_NORM) drop_norm_columns(c);
   if (set == KPSI_NORM) invalidate_cache(c);
   st = derive_columns(c, set);
   if (st) return st;
@@ -1235,7 +1275,7 @@ kpsi_status kpsi_load_events_device(kpsi_ctx* c, kpsi_set set, int64_t n, const 
   if (st) return st;
   for (int j = 0; j < 4; ++j) d.obs[j] = src[j];
   d.n = n;
-  if (set == KPSI_NORM && c->eps) { hipFree(c->eps); c->eps = nullptr; }
+  if (set == KPSI_NORM) drop_norm_columns(c);
   if (set == KPSI_NORM) invalidate_cache(c);
   st = derive_columns(c, set);
   if (st) return st;
@@ -1243,26 +1283,33 @@ kpsi_status kpsi_load_events_device(kpsi_ctx* c, kpsi_set set, int64_t n, const 
   return KPSI_OK;
 }
 
+// The per-event column the kernels read: efficiency times importance weight (null when both are 1).
+static kpsi_status rebuild_eps(kpsi_ctx* c) {
+  invalidate_cache(c);
+  if (!c->eps_f64 && !c->norm_w) {
+    if (c->eps) hipFree(c->eps);
+    c->eps = nullptr;
+    return KPSI_OK;
+  }
+  return product_column(c, c->eps_f64, c->norm_w, &c->eps);
+}
+
 kpsi_status kpsi_set_efficiency_flat(kpsi_ctx* c) {
   if (!c) return KPSI_E_ARG;
-  invalidate_cache(c);
-  if (c->eps) hipFree(c->eps);
-  c->eps = nullptr;
-  return KPSI_OK;
+  hipSetDevice(c->device);
+  if (c->eps_f64) hipFree(c->eps_f64);
+  c->eps_f64 = nullptr;
+  return rebuild_eps(c);
 }
 
 static kpsi_status eps_from_device_f64(kpsi_ctx* c, const double* d_eps, int64_t n) {
-  void* e = nullptr;
-  if (hipMalloc(&e, (size_t)n * tsize(c)) != hipSuccess) return fail(c, KPSI_E_OOM, "efficiency column");
-  const unsigned nb = (unsigned)((n + 255) / 256);
-  if (c->prec == KPSI_FP32) hipLaunchKernelGGL(to_t_kernel<float>, dim3(nb), dim3(256), 0, c->stream, d_eps, (float*)e, n);
-  else hipLaunchKernelGGL(to_t_kernel<double>, dim3(nb), dim3(256), 0, c->stream, d_eps, (double*)e, n);
-  hipError_t er = hipStreamSynchronize(c->stream);
-  if (er != hipSuccess) { hipFree(e); return fail(c, KPSI_E_HIP, "efficiency conversion: %s", hipGetErrorString(er)); }
-  if (c->eps) hipFree(c->eps);
-  c->eps = e;
-  invalidate_cache(c);
-  return KPSI_OK;
+  double* e = nullptr;
+  if (hipMalloc(&e, (size_t)n * sizeof(double)) != hipSuccess) return fail(c, KPSI_E_OOM, "efficiency column");
+  hipError_t er = hipMemcpyAsync(e, d_eps, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  if (er != hipSuccess) { hipFree(e); return fail(c, KPSI_E_HIP, "efficiency copy: %s", hipGetErrorString(er)); }
+  if (c->eps_f64) hipFree(c->eps_f64);
+  c->eps_f64 = e;
+  return rebuild_eps(c);
 }
 
 kpsi_status kpsi_set_efficiency_values(kpsi_ctx* c, const double* eps, int64_t n) {
@@ -1311,6 +1358,69 @@ kpsi_status kpsi_set_efficiency_hist(kpsi_ctx* c, const float* eff, const int nb
   kpsi_status st = er == hipSuccess ? eps_from_device_f64(c, vals, n) : fail(c, KPSI_E_HIP, "histogram lookup");
   hipFree(table);
   hipFree(vals);
+  return st;
+}
+
+kpsi_status kpsi_set_norm_mixture(kpsi_ctx* c, const double* params0, int64_t n_flat) {
+  if (!c) return KPSI_E_ARG;
+  if (!params0) return fail(c, KPSI_E_ARG, "params0 is NULL");
+  if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set");
+  const int64_t n = c->set[1].n;
+  if (n <= 0) return fail(c, KPSI_E_STATE, "load the normalisation set first");
+  if (n_flat < 1 || n_flat > n) return fail(c, KPSI_E_ARG, "n_flat %lld outside [1, %lld]", (long long)n_flat, (long long)n);
+  if (c->bkg_on) return fail(c, KPSI_E_STATE, "set the normalisation mixture before the background");
+  for (int i = 0; i < c->nparams; ++i)
+    if (!std::isfinite(params0[i])) return fail(c, KPSI_E_ARG, "params0[%d] is not finite", i);
+  hipSetDevice(c->device);
+  auto drop = [&]() {
+    for (void** p : {(void**)&c->norm_w, &c->wcol}) {
+      if (*p) hipFree(*p);
+      *p = nullptr;
+    }
+    c->norm_w_host.clear();
+  };
+  drop();
+  if (n_flat == n) return rebuild_eps(c);   // a flat set: no weights
+  // S(y; params0) of every normalisation event
+  double* d = nullptr;
+  if (hipMalloc(&d, (size_t)n * sizeof(double)) != hipSuccess) return fail(c, KPSI_E_OOM, "density output");
+  double* outs[2] = {nullptr, d};
+  std::vector<double> s0((size_t)n);
+  kpsi_status st = dispatch(c, MODE_DENSITY, params0, 1, outs);
+  if (!st) {
+    hipError_t e = hipMemcpyAsync(s0.data(), d, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) st = fail(c, KPSI_E_HIP, "density copy: %s", hipGetErrorString(e));
+  }
+  hipFree(d);
+  if (st) return st;
+  // Z0: the flat events' mean of S0 (compensated sum)
+  double sum = 0.0, comp = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    if (!(s0[j] >= 0.0) || !std::isfinite(s0[j])) return fail(c, KPSI_E_ARG, "density of normalisation event %lld is %g",
+                                                          (long long)j, s0[j]);
+    if (j >= n_flat) continue;
+    const double t = sum + s0[j];
+    comp += (std::fabs(sum) >= std::fabs(s0[j])) ? (sum - t) + s0[j] : (s0[j] - t) + sum;
+    sum = t;
+  }
+  const double z0 = (sum + comp) / (double)n_flat;
+  if (!(z0 > 0.0)) return fail(c, KPSI_E_ARG, "mean density of the flat events is %g", z0);
+  // density of the mixture relative to flat phase space: alpha + (1 - alpha) S0 / Z0
+  const double alpha = (double)n_flat / (double)n;
+  c->norm_w_host.resize((size_t)n);
+  for (int64_t j = 0; j < n; ++j) c->norm_w_host[j] = 1.0 / (alpha + (1.0 - alpha) * (s0[j] / z0));
+  if (hipMalloc(&c->norm_w, (size_t)n * sizeof(double)) != hipSuccess) {
+    c->norm_w = nullptr;
+    drop();
+    return fail(c, KPSI_E_OOM, "importance weights");
+  }
+  hipError_t e = hipMemcpyAsync(c->norm_w, c->norm_w_host.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice,
+                                c->stream);
+  if (e != hipSuccess) { drop(); return fail(c, KPSI_E_HIP, "weight upload: %s", hipGetErrorString(e)); }
+  st = product_column(c, c->norm_w, nullptr, &c->wcol);
+  if (!st) st = rebuild_eps(c);
+  if (st) { drop(); rebuild_eps(c); }
   return st;
 }
 

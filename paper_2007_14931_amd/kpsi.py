@@ -30,6 +30,7 @@ EXPORTS = [
     "kpsi_mlp_default_options", "kpsi_accept_labels", "kpsi_hist_efficiency", "kpsi_mlp_grad", "kpsi_mlp_train",
     "kpsi_mlp_eval", "kpsi_set_efficiency_mlp", "kpsi_fit_fractions", "kpsi_measure_peaks", "kpsi_set_background",
     "kpsi_template_values", "kpsi_set_flavour", "kpsi_set_constraints", "kpsi_nll_and_grad_noalloc",
+    "kpsi_set_norm_mixture",
 ]
 MLP_NP = 4545
 
@@ -103,6 +104,7 @@ def lib() -> C.CDLL:
         L.kpsi_set_efficiency_flat.argtypes = [vp]
         L.kpsi_set_efficiency_values.argtypes = [vp, dp, i64]
         L.kpsi_set_efficiency_hist.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int), dp, dp]
+        L.kpsi_set_norm_mixture.argtypes = [vp, dp, i64]
         # pointer arguments of the per-call entry points are plain addresses (the binding's fast
         # path passes ndarray.ctypes.data integers; ctypes pointer objects are accepted too)
         L.kpsi_nll.argtypes = [vp, vp, vp]
@@ -252,6 +254,12 @@ class Engine:
         lo, hi = _f64(lo), _f64(hi)
         self._chk(self.L.kpsi_set_efficiency_hist(self.h, t.ctypes.data_as(C.POINTER(C.c_float)),
                                                   nb.ctypes.data_as(C.POINTER(C.c_int)), _dp(lo), _dp(hi)))
+
+    def set_norm_mixture(self, params0, n_flat: int) -> None:
+        """kpsi_set_norm_mixture: the first n_flat normalisation events are flat, the rest drawn
+        from S(y; params0); the library weights them back to flat phase space."""
+        p = _f64(params0)
+        self._chk(self.L.kpsi_set_norm_mixture(self.h, _dp(p), int(n_flat)))
 
     def nll(self, params) -> float:
         p = _f64(params)

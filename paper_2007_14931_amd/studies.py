@@ -210,6 +210,31 @@ def large_fit(args) -> dict:
     return result
 
 
+def cartesian_pulls(res, x, cov, truth, mask) -> np.ndarray:
+    """Pulls of the free parameters with every free coupling taken as (Re H, Im H) instead of
+    (magnitude, phase): near a small magnitude the likelihood is close to quadratic in H but not
+    in (r, phi).  The HESSE covariance is carried over with the Jacobian of H = r e^{i phi} at the
+    fitted point (exact for the Hessian at a minimum).  cov is over the free parameters."""
+    nc = W.n_params(res) - 2 * len(res)
+    free = np.flatnonzero(mask)
+    out = []
+    k = 0
+    while k < len(free):
+        i = free[k]
+        if i < nc and i % 2 == 0 and k + 1 < len(free) and free[k + 1] == i + 1:
+            r, ph = x[i], x[i + 1]
+            J = np.array([[math.cos(ph), -r * math.sin(ph)], [math.sin(ph), r * math.cos(ph)]])
+            C2 = J @ cov[np.ix_([k, k + 1], [k, k + 1])] @ J.T
+            h = r * complex(math.cos(ph), math.sin(ph))
+            h0 = truth[i] * complex(math.cos(truth[i + 1]), math.sin(truth[i + 1]))
+            out += [(h.real - h0.real) / math.sqrt(abs(C2[0, 0])), (h.imag - h0.imag) / math.sqrt(abs(C2[1, 1]))]
+            k += 2
+        else:
+            out.append((x[i] - truth[i]) / math.sqrt(abs(cov[k, k])))
+            k += 1
+    return np.array(out)
+
+
 def pulls(args) -> dict:
     """Pseudo-experiments of the 1M-event benchmark fit: each seed draws a new data sample at
     the truth point, fits it (FP32, device adjoint gradient, MIGRAD + HESSE) from a perturbed
@@ -228,15 +253,25 @@ def pulls(args) -> dict:
     gen.load(kpsi.DATA, scan)
     smax = 1.5 * float(gen.density(kpsi.DATA, truth).max())
     n_mc = int(args.norm_events) if args.norm_events else wl.n_mc
-    mc = gen.generate_phsp(wl.mc_seed, n_mc, W.PHSP_WMAX)
+    n_flat = n_mc if args.flat_fraction >= 1.0 else int(round(args.flat_fraction * n_mc))
+    mc = gen.generate_phsp(wl.mc_seed, n_flat, W.PHSP_WMAX)
+    if n_flat < n_mc:
+        # the rest of the normalisation set drawn from the model at the truth point (importance sampling)
+        mc_m, _, _ = gen.generate_model(truth, wl.mc_seed + 1, n_mc - n_flat, W.PHSP_WMAX, smax)
+        mc = torch.cat([mc, mc_m], dim=1).contiguous()
+        torch.cuda.synchronize()   # written on torch's stream, read on the engine's stream
+        del mc_m
     e = kpsi.Engine(0, "fp32", stream)
     e.set_model(W.KIN, res)
     e.set_floating(flags)
     e.load(kpsi.NORM, mc)
+    if n_flat < n_mc:
+        e.set_norm_mixture(truth, n_flat)
     ct = W.canonical(res, truth)
-    P, statuses, walls = [], [], []
+    P, PC, statuses, walls = [], [], [], []
+    n_data = int(args.data_events)
     for s in range(args.seeds):
-        data, _, _ = gen.generate_model(truth, 5000 + s, wl.n_data, W.PHSP_WMAX, smax)
+        data, _, _ = gen.generate_model(truth, 5000 + s, n_data, W.PHSP_WMAX, smax)
         e.load(kpsi.DATA, data)
         rng = np.random.default_rng(100 + s)
         x0 = truth + 0.02 * rng.standard_normal(truth.size) * mask
@@ -248,6 +283,10 @@ def pulls(args) -> dict:
             if i < nc and i % 2 == 1:
                 d[k] = math.remainder(d[k], 2 * math.pi)
         P.append(d / sig)
+        PC.append(cartesian_pulls(res, x, cov, truth, mask))
+        if not np.all(np.isfinite(d / sig)):
+            log(f"seed {s}: non-finite pulls at {free[~np.isfinite(d / sig)].tolist()}; "
+                f"diag cov there {np.diag(cov)[~np.isfinite(d / sig)].tolist()}")
         statuses.append(r.status)
         walls.append(r.wall_seconds)
         log(f"seed {s}: status {r.status} wall {r.wall_seconds:.3f} s  rms pull {np.sqrt(np.mean((d / sig) ** 2)):.2f}")
@@ -255,8 +294,21 @@ def pulls(args) -> dict:
     e.close()
     gen.close()
     P = np.array(P)
+    PC = np.array(PC)
+    mc_, sdc = PC.mean(0), PC.std(0, ddof=1)
+    log(f"cartesian pulls: max |mean| {np.max(np.abs(mc_)):.2f}, rms of means {np.sqrt(np.mean(mc_ ** 2)):.2f}, "
+        f"widths {sdc.min():.2f} - {sdc.max():.2f} (median {np.median(sdc):.2f}); statuses {sorted(set(statuses))}")
+    m, sd = P.mean(0), P.std(0, ddof=1)
+    log(f"pulls: {n_data} data, {n_mc} normalisation ({n_flat} flat): max |mean| {np.max(np.abs(m)):.2f}, "
+        f"rms of means {np.sqrt(np.mean(m ** 2)):.2f} (expected {1 / math.sqrt(args.seeds):.2f}), "
+        f"widths {sd.min():.2f} - {sd.max():.2f} (median {np.median(sd):.2f})")
     return {"study": "pulls", "workload": "full_grad_1m", "seeds": args.seeds, "free_params": int(mask.sum()),
-            "data_events": wl.n_data, "norm_events": n_mc,
+            "data_events": n_data, "norm_events": n_mc, "flat_norm_events": n_flat,
+            "max_abs_param_mean": float(np.max(np.abs(m))), "rms_param_mean": float(np.sqrt(np.mean(m ** 2))),
+            "cartesian_per_param_mean": [float(v) for v in mc_], "cartesian_per_param_std": [float(v) for v in sdc],
+            "cartesian_max_abs_mean": float(np.max(np.abs(mc_))),
+            "cartesian_rms_mean": float(np.sqrt(np.mean(mc_ ** 2))), "cartesian_median_width": float(np.median(sdc)),
+            "median_param_width": float(np.median(sd)),
             "fit_status": statuses, "median_fit_wall_s": float(np.median(walls)),
             "pull_mean_over_params": float(P.mean()), "pull_rms_over_params": float(np.sqrt((P ** 2).mean())),
             "per_param_mean": [float(v) for v in P.mean(0)], "per_param_std": [float(v) for v in P.std(0)],
@@ -537,6 +589,9 @@ def main() -> int:
     ap.add_argument("--data-events", type=float, default=1e6)
     ap.add_argument("--norm-events", type=float, default=0, help="normalisation events of the pull study "
                     "(default: the workload's)")
+    ap.add_argument("--flat-fraction", type=float, default=1.0,
+                    help="fraction of the pull study's normalisation events drawn flat; the rest are drawn from "
+                         "the model at the truth point and weighted back (kpsi_set_norm_mixture)")
     args = ap.parse_args()
     out = {"learned_eff": learned_eff, "large_fit": large_fit, "pulls": pulls,
            "z_sensitivity": z_sensitivity, "real_life": real_life, "flavour_tags": flavour_tags}[args.study](args)
