@@ -29,7 +29,13 @@ sys.path.insert(0, ROOT)
 # (fused multiply-add = 2, other arithmetic and reciprocal/rsqrt/log = 1), from the op count
 # of the per-call formulation (bare Breit-Wigner per resonance, resonance constants in the
 # couplings, barrier factors in the d functions): forward 530, adjoint 384.
-TIMING_EVERY = 10
+TIMING_EVERY = 10     # in the timed region: HIP events on every 10th call (cross-check)
+POST_CALLS = 400      # host-timed calls of each post-loop leg
+KERNEL_REPS = 100     # back-to-back launches per HIP-event pair (kpsi_time_kernel)
+KERNEL_BATCHES = 5
+# Algorithmic bytes per event: the four observables of each event in the arithmetic's type
+# (m_Kpi, cos theta_K*, cos theta_J/psi, phi), read once per call.
+ALG_BYTES_PER_EVENT = {"f32": 16, "f64": 32}
 FLOP_PER_EVENT = {"full_grad": 914}
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}        # MI355X published vector peaks
 PEAK_TFLOPS_UNPACKED = {"f32": 78.6, "f64": 78.6}  # without packed-FP32 instructions
@@ -49,6 +55,24 @@ def measured_traffic(kernel_source: str) -> float | None:
     if not sha.startswith(rec["source_sha256_prefix"]):
         return None
     return float(rec["traffic_bytes"])
+
+
+def timed_leg(e, par, grad: bool, calls: int = 0) -> dict:
+    """Kernel time and host rate of NLL(+gradient) calls.  Kernel: KERNEL_BATCHES batches of
+    KERNEL_REPS back-to-back launches of the per-event work between one pair of HIP events on the
+    library's stream (kpsi_time_kernel); mean and median of the batches' per-launch times.  Host:
+    `calls` (at least POST_CALLS) ordinary calls."""
+    calls = max(calls, POST_CALLS)
+    f = e.nll_and_grad if grad else e.nll
+    for _ in range(20):
+        f(par)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        f(par)
+    dt = time.perf_counter() - t0
+    b = [e.time_kernel(par, grad=grad, reps=KERNEL_REPS) for _ in range(KERNEL_BATCHES)]
+    return {"timed_launches": KERNEL_REPS * KERNEL_BATCHES, "kernel_ms_mean": float(np.mean(b)),
+            "kernel_ms_median": float(np.median(b)), "host_ms_per_call": dt / calls * 1e3}
 
 
 def log(msg: str) -> None:
@@ -222,16 +246,15 @@ def extension_legs(stream, data, mc, par, res, floating, steps: int = 1000, warm
     def timed(e, p):
         for _ in range(warmup):
             e.nll_and_grad(p)
-        e.set_timing(TIMING_EVERY)
-        e.timing(reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             e.nll_and_grad(p)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / steps * 1e3
-        kms, kn = e.timing(reset=True)
-        return {"ms_per_step": ms, "evals_per_s": 1e3 / ms, "kernel_ms": kms / max(kn, 1)}
+        leg = timed_leg(e, p, grad=True)
+        return {"ms_per_step": ms, "evals_per_s": 1e3 / ms, "kernel_ms": leg["kernel_ms_mean"],
+                "kernel_ms_median": leg["kernel_ms_median"]}
 
     out = {}
     e = kpsi.Engine(0, "fp32", stream)
@@ -356,11 +379,13 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     host_med_ms = float(np.median(np.diff(stamps))) * 1e3
-    kmed = eng.timing_median()
-    kms, kn = eng.timing(reset=True)
-    eng.set_timing(False)
+    kmed_region = eng.timing_median()
+    kms_region, kn_region = eng.timing(reset=True)
     ms_step = wall / args.steps * 1e3
-    kernel_ms = kms / max(kn, 1)
+    # kernel time: back-to-back launches of the same per-event work between HIP events on the
+    # library's stream (the timed region's own every-10th-call events are kept as a cross-check)
+    leg = timed_leg(eng, par, grad=True)
+    kernel_ms, kmed, kn = leg["kernel_ms_mean"], leg["kernel_ms_median"], leg["timed_launches"]
     n_ev = wl.n_data + wl.n_mc
     dt = "f32" if args.precision == "fp32" else "f64"
     flops = FLOP_PER_EVENT["full_grad"] * n_ev
@@ -370,17 +395,16 @@ def main() -> int:
     # the other precision, for the record (same events, same parameters)
     other = "fp64" if args.precision == "fp32" else "fp32"
     e2 = make(other)
-    for _ in range(50):
-        e2.nll_and_grad(par)
-    e2.set_timing(TIMING_EVERY)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    n2 = max(20, args.steps // 5)
-    for _ in range(n2):
-        v2, g2 = e2.nll_and_grad(par)
-    torch.cuda.synchronize()
-    ms2 = (time.perf_counter() - t1) / n2 * 1e3
-    k2, kn2 = e2.timing(reset=True)
+    v2, g2 = e2.nll_and_grad(par)
+    leg2 = timed_leg(e2, par, grad=True)
+    # likelihood-only calls (what every finite-difference step and cached data-only call runs)
+    nll_legs = {}
+    for prec, e_ in ((args.precision, eng), (other, e2)):
+        lg = timed_leg(e_, par, grad=False)
+        dtp = "f32" if prec == "fp32" else "f64"
+        lg["achieved_gbs_algorithmic"] = ALG_BYTES_PER_EVENT[dtp] * n_ev / (lg["kernel_ms_mean"] * 1e-3) / 1e9
+        nll_legs[prec] = lg
+        log(f"{prec} likelihood-only: kernel {lg['kernel_ms_mean']:.4f} ms, host {lg['host_ms_per_call']:.4f} ms")
     e2.close()
 
     out = {
@@ -404,11 +428,17 @@ def main() -> int:
         "events_per_s": n_ev / (kernel_ms * 1e-3),
         "kernel_ms": kernel_ms,
         "kernel_ms_median": kmed,
+        "kernel_timed_launches": kn,
+        "kernel_ms_timed_region": kms_region / max(kn_region, 1),
+        "kernel_ms_timed_region_median": kmed_region,
+        "kernel_timed_calls_timed_region": kn_region,
         "host_ms_median": host_med_ms,
-        "timed_kernel_calls": kn,
         "nll": v,
-        "other_precision": {"precision": other, "ms_per_step": ms2, "kernel_ms": k2 / max(kn2, 1),
-                            "evals_per_s": 1e3 / ms2, "nll": v2, "rel_nll_diff": abs(v2 - v) / abs(v)},
+        "other_precision": {"precision": other, "ms_per_step": leg2["host_ms_per_call"],
+                            "kernel_ms": leg2["kernel_ms_mean"], "kernel_ms_median": leg2["kernel_ms_median"],
+                            "evals_per_s": 1e3 / leg2["host_ms_per_call"], "nll": v2,
+                            "rel_nll_diff": abs(v2 - v) / abs(v)},
+        "likelihood_only": nll_legs,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[dt],
                      "traffic": measured_traffic("paper_2007_14931_amd/csrc/kpsi_device.hip") if dt == "f32" else None,

@@ -189,6 +189,13 @@ kpsi_status kpsi_generate_model(kpsi_ctx* ctx, const double* params, uint64_t se
                                 double smax, const double* acc_coef, double* m_kpi, double* cos_k, double* cos_j,
                                 double* phi, int64_t* n_prop, int64_t* n_over);
 
+/* Duration of the per-event work of one call, for measurement: the per-event kernel launches of
+ * a kpsi_nll_and_grad (grad != 0) or kpsi_nll (grad == 0) call over every loaded event are
+ * enqueued `reps` times back to back on the context stream between one pair of HIP events,
+ * followed by one final reduction; *ms_per_launch receives the events' interval divided by reps
+ * (launch gaps included, the reduction and host work excluded).  reps in [1, 100000].  The
+ * interference-matrix cache is not used.  Same errors as kpsi_nll_and_grad. */
+kpsi_status kpsi_time_kernel(kpsi_ctx* ctx, const double* params, int grad, int reps, double* ms_per_launch);
 /* Device timing of the per-event kernel: with every = k > 0, every k-th nll /
  * nll_and_grad call (counting from the first after this call) records HIP events around
  * the kernel on the context stream; every = 0 turns timing off.  kpsi_timing returns the

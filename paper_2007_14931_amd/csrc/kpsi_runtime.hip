@@ -125,6 +125,8 @@ struct kpsi_ctx {
   int64_t t_n = 0;
   std::vector<float> t_samples;  // the first kTimingSamples timed durations since the last reset
   int64_t t_dropped = 0;         // timed calls whose duration could not be read
+  int bench_reps = 0;             // kpsi_time_kernel: back-to-back launches of the per-event work
+  double bench_ms = 0.0;          // their duration per launch
   int ept_override = 0;
   int n_cu = 0;                                                   // compute units of the device
   int blocks_per_cu[2][3][2] = {{{-1, -1}, {-1, -1}, {-1, -1}}, {{-1, -1}, {-1, -1}, {-1, -1}}};   // [shape][mode][cc]
@@ -778,7 +780,8 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
     a.bkg_coef = c->bkg_coef;
     a.purity = (T)c->purity;
   }
-  c->timing = !fixed && mode != MODE_DENSITY && c->timing_every > 0 && (c->timing_calls++ % c->timing_every) == 0;
+  c->timing = !fixed && c->bench_reps == 0 && mode != MODE_DENSITY && c->timing_every > 0 &&
+              (c->timing_calls++ % c->timing_every) == 0;
   if (c->timing) hipEventRecord(c->ev0, c->stream);
   // Launches over the events of [nd data, nm normalisation] write block partials (rows of
   // nbd + nbm blocks, data first); one reduction then writes the record of each set covered
@@ -826,6 +829,10 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
     return KPSI_OK;
   };
   kpsi_status st = KPSI_OK;
+  // kpsi_time_kernel: the per-event launches repeated back to back between one pair of events
+  const int reps = (c->bench_reps > 0 && mode != MODE_DENSITY) ? c->bench_reps : 1;
+  if (reps > 1 || c->bench_reps > 0) hipEventRecord(c->ev0, c->stream);
+  for (int rep = 0; rep < reps && !st; ++rep) {
   if (!mix) {
     AmpArgs<T, Sh> b = a;
     b.chunk = chunk_d;
@@ -852,8 +859,9 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
       st = launch(b, nbd);
     }
   }
+  }
   if (st) return st;
-  if (c->timing) hipEventRecord(c->ev1, c->stream);   // end of the per-event work
+  if (c->timing || c->bench_reps > 0) hipEventRecord(c->ev1, c->stream);   // end of the per-event work
   if (mode != MODE_DENSITY) {
     hipError_t e = launch_reduce_final(part, nbd, nbm, nmsets, nv, c->red, nd > 0 ? 0 : 1,
                                        (nd > 0) + (nm > 0) * nmsets, c->stream);
@@ -862,6 +870,13 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   if (st) return st;
   if (mode == MODE_DENSITY) return KPSI_OK;
   if (kpsi_status ws = wait_stream(c)) return ws;
+  if (c->bench_reps > 0) {
+    float ms = 0.f;
+    if (hipEventSynchronize(c->ev1) != hipSuccess || hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess)
+      return fail(c, KPSI_E_HIP, "kernel timing events");
+    c->bench_ms = (double)ms / reps;
+    return KPSI_OK;
+  }
   if (c->timing) {
     // the polled completion word can change before the runtime marks ev1 complete: wait for it,
     // so that no timed sample is lost
@@ -1796,6 +1811,20 @@ kpsi_status kpsi_generate_model(kpsi_ctx* c, const double* params, uint64_t seed
   *n_prop = e0;
   *n_over = novr;
   return st;
+}
+
+kpsi_status kpsi_time_kernel(kpsi_ctx* c, const double* params, int grad, int reps, double* ms_per_launch) {
+  kpsi_status st = check_ready(c, params);
+  if (st) return st;
+  if (!ms_per_launch) return fail(c, KPSI_E_ARG, "ms_per_launch is NULL");
+  if (reps < 1 || reps > 100000) return fail(c, KPSI_E_ARG, "reps %d outside [1, 100000]", reps);
+  hipSetDevice(c->device);
+  c->bench_reps = reps;
+  st = dispatch(c, grad ? MODE_GRAD : MODE_NLL, params, -1, nullptr);
+  c->bench_reps = 0;
+  if (st) return st;
+  *ms_per_launch = c->bench_ms;
+  return KPSI_OK;
 }
 
 kpsi_status kpsi_set_timing(kpsi_ctx* c, int every) {

@@ -30,7 +30,7 @@ EXPORTS = [
     "kpsi_mlp_default_options", "kpsi_accept_labels", "kpsi_hist_efficiency", "kpsi_mlp_grad", "kpsi_mlp_train",
     "kpsi_mlp_eval", "kpsi_set_efficiency_mlp", "kpsi_fit_fractions", "kpsi_measure_peaks", "kpsi_set_background",
     "kpsi_template_values", "kpsi_set_flavour", "kpsi_set_constraints", "kpsi_nll_and_grad_noalloc",
-    "kpsi_set_norm_mixture",
+    "kpsi_set_norm_mixture", "kpsi_time_kernel",
 ]
 MLP_NP = 4545
 
@@ -118,6 +118,7 @@ def lib() -> C.CDLL:
         L.kpsi_set_timing.argtypes = [vp, C.c_int]
         L.kpsi_timing.argtypes = [vp, dp, C.POINTER(i64), C.c_int]
         L.kpsi_timing_median.argtypes = [vp, dp]
+        L.kpsi_time_kernel.argtypes = [vp, dp, C.c_int, C.c_int, dp]
         L.kpsi_set_events_per_thread.argtypes = [vp, C.c_int]
         L.kpsi_fit_default_options.argtypes = [C.POINTER(FitOptions)]
         L.kpsi_migrad.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(FitOptions), C.POINTER(FitResult), dp]
@@ -339,6 +340,14 @@ class Engine:
         """Median kernel milliseconds of the timed calls since the last reset (NaN if none)."""
         ms = C.c_double()
         self._chk(self.L.kpsi_timing_median(self.h, C.byref(ms)))
+        return ms.value
+
+    def time_kernel(self, params, grad: bool = True, reps: int = 200) -> float:
+        """kpsi_time_kernel: milliseconds per launch of the per-event work, `reps` launches back to
+        back between one pair of HIP events."""
+        p = _f64(params)
+        ms = C.c_double()
+        self._chk(self.L.kpsi_time_kernel(self.h, _dp(p), 1 if grad else 0, int(reps), C.byref(ms)))
         return ms.value
 
     def fit_options(self, **kw) -> FitOptions:

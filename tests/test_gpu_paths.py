@@ -115,3 +115,24 @@ def test_mlp_efficiency_likelihood_matches_oracle(trained_network, prec, tg):
     print(f"[parity] network efficiency vs FP64 network: |dNLL| {abs(v - ref2):.3e} bound {bound:.3e}", flush=True)
     assert abs(v - ref2) <= bound + 1e-6 * max(abs(ref2), 2.0 * nd)
     e.close()
+
+
+def test_time_kernel_reports_a_duration_and_leaves_results_unchanged():
+    res = W.model("full")
+    data = W.neutral_events(20011, 81, peaked=True)
+    data[0] = np.clip(data[0], W.M_LO + 1e-6, W.M_HI - 1e-6)
+    mc = O.gen_phsp(K, 82, 60013, W.PHSP_WMAX)
+    par = W.params(res, seed=83) + 0.04 * W.free_mask(res, FLOAT)
+    e = _engine("fp32", res, data, mc)
+    v0, g0 = e.nll_and_grad(par)
+    for grad in (True, False):
+        ms = e.time_kernel(par, grad=grad, reps=50)
+        assert 0.0 < ms < 50.0
+    v1, g1 = e.nll_and_grad(par)
+    fin = np.isfinite(g0)
+    assert v1 == v0 and np.array_equal(g1[fin], g0[fin])
+    st, _ = e.nll_status(par)
+    assert st == kpsi.KPSI_OK
+    with pytest.raises(kpsi.KpsiError):
+        e.time_kernel(par, reps=0)
+    e.close()
