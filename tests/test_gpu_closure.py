@@ -135,9 +135,10 @@ def test_norm_mixture_matches_oracle(setup):
             ff, tot = e.fit_fractions(par)
             rt = 1e-9 if prec == "fp64" else 2e-5
             np.testing.assert_allclose(ff, ff_ref, rtol=rt, atol=rt * 1e-3)
-            # efficiency reset after the weights: the weights stay
+            # efficiency reset after the weights: the weights stay (the same likelihood-only value)
+            v_nll = e.nll(par)
             e.set_efficiency_values(eps)
-            assert e.nll(par) == pytest.approx(v, rel=1e-12 if prec == "fp64" else 1e-9)
+            assert e.nll(par) == pytest.approx(v_nll, rel=1e-12)
             e.close()
 
 
