@@ -168,10 +168,12 @@ template <typename T, class Sh> struct ImArgs {
   RC<T> zs[Sh::NZ > 0 ? Sh::NZ : 1];
 };
 
+constexpr int MLP_NV = 4546;     // values per block record of the network gradient: 4545 parameters and the loss
 struct MlpArgs {
   const double* obs[4];
   const uint8_t* label;   // accept labels (training) or null
   const float* params;    // FP32 master parameters (4545)
+  const unsigned short* w2h;   // BF16 W2 [o][i] then [i][o] (8192, 16-byte aligned; launch_mlp_bf16)
   float* partial;         // value-major block gradients (4546 values x blocks)
   double* out;            // probabilities (evaluation)
   double lo, hi;          // m_Kpi range of the input map
@@ -199,10 +201,11 @@ struct HistCountArgs {
 };
 
 size_t mlp_smem_bytes();
+hipError_t launch_mlp_bf16(const float* params, unsigned short* w2h, hipStream_t st);
 hipError_t launch_mlp_grad(const MlpArgs& a, int nb, hipStream_t st);
 hipError_t launch_mlp_reduce(const float* partial, int nb, int nv, double scale, double* out, hipStream_t st);
 hipError_t launch_adam(float* p, float* m, float* v, const double* g, int n, float lr, float b1, float b2, float eps,
-                       float c1, float c2, hipStream_t st);
+                       float c1, float c2, unsigned short* w2h, hipStream_t st);
 hipError_t launch_mlp_eval(const MlpArgs& a, int nb, hipStream_t st);
 hipError_t launch_labels(const LabelArgs& a, hipStream_t st);
 hipError_t launch_hist_count(const HistCountArgs& a, hipStream_t st);

@@ -1,9 +1,10 @@
 // Learned efficiency: a 4 -> 64 -> 64 -> 1 network (SiLU, SiLU, sigmoid) trained on accept
 // labels with binary cross-entropy and Adam, and evaluated once per normalisation event.
 // The 64x64 layer (forward, weight gradient and input gradient) runs on BF16 matrix cores
-// (v_mfma_f32_16x16x16bf16_1k) with FP32 accumulation; the 4-wide input layer and the
-// output layer run on the vector ALUs in FP32.  Master weights are FP32; their BF16 copies
-// are made when a block stages them into LDS.
+// (v_mfma_f32_16x16x32_bf16: 16x16 outputs, 32-deep products, 8 operands per lane) with FP32
+// accumulation; the 4-wide input layer and the output layer run on the vector ALUs in FP32.
+// Master weights are FP32; a small kernel writes the BF16 copies of the 64x64 layer in both
+// layouts once per parameter update, and blocks stage them into LDS with 16-byte copies.
 //
 // Parameter layout (4545 floats): W1[64][4], b1[64], W2[64][64] (row = output), b2[64],
 // w3[64], b3.  Network input: u = (2 (m - lo)/(hi - lo) - 1, cos theta_K*, cos theta_J/psi,
@@ -20,7 +21,7 @@ namespace nn {
 constexpr int P_W1 = 0, P_B1 = 256, P_W2 = 320, P_B2 = 4416, P_W3 = 4480, P_B3 = 4544;
 constexpr int TE = 64;   // events per tile
 
-typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
 // float -> bf16 bits, round to nearest even (finite inputs)
@@ -36,8 +37,8 @@ __device__ __forceinline__ float dsilu(float z) {
   return s * (1.0f + z * (1.0f - s));
 }
 
-struct Smem {
-  unsigned short W2[64 * 64];    // [o][i] bf16
+struct __align__(16) Smem {
+  unsigned short W2[64 * 64];    // [o][i] bf16 (W2 and W2T adjacent: staged as one copy)
   unsigned short W2T[64 * 64];   // [i][o] bf16
   unsigned short H1[TE * 64];    // [e][i]
   unsigned short H1T[64 * TE];   // [i][e]
@@ -49,11 +50,21 @@ struct Smem {
   float red[256];
 };
 
-// four consecutive bf16 of an LDS row as an MFMA operand
-__device__ __forceinline__ s4_t ld4(const unsigned short* p) {
-  s4_t v;
-  v[0] = (short)p[0]; v[1] = (short)p[1]; v[2] = (short)p[2]; v[3] = (short)p[3];
-  return v;
+// eight consecutive bf16 of an LDS row (16-byte aligned) as an MFMA operand: one 16-byte read
+__device__ __forceinline__ bf8_t ld8(const unsigned short* p) { return *reinterpret_cast<const bf8_t*>(p); }
+
+// One 64 x 64 x (64 deep) product tile row for the wave: acc += A[16 rows][64] B[64][16 cols], with
+// A's rows at a + 64 * (lane % 16) and B's columns at b + 64 * (lane % 16) (both row-major in k).
+// Lane l supplies A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16] for each 32-deep half.
+__device__ __forceinline__ f4_t mm16x64(const unsigned short* a, const unsigned short* b, int l16, int lg) {
+  f4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk) {
+    const bf8_t av = ld8(a + 64 * l16 + 32 * kk + 8 * lg);
+    const bf8_t bv = ld8(b + 64 * l16 + 32 * kk + 8 * lg);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
 }
 
 __device__ __forceinline__ float input_of(const MlpArgs& a, int k, int64_t e) {
@@ -63,14 +74,12 @@ __device__ __forceinline__ float input_of(const MlpArgs& a, int k, int64_t e) {
   return (float)x;
 }
 
-// Stage weights into LDS (BF16 copies of W2 in both layouts, FP32 small layers).
+// Stage weights into LDS: the BF16 copies of W2 in both layouts (8192 values, from w2h), and the
+// FP32 small layers (W1 and w3 rounded to BF16 like W2).
 __device__ void stage_weights(const MlpArgs& a, Smem& s) {
-  for (int i = threadIdx.x; i < 4096; i += 256) {
-    const int o = i >> 6, in = i & 63;
-    const unsigned short h = bf16(a.params[P_W2 + i]);
-    s.W2[i] = h;
-    s.W2T[in * 64 + o] = h;
-  }
+  const uint4* src = reinterpret_cast<const uint4*>(a.w2h);
+  uint4* dst = reinterpret_cast<uint4*>(s.W2);
+  for (int i = threadIdx.x; i < 2 * 4096 * 2 / 16; i += 256) dst[i] = src[i];
   for (int i = threadIdx.x; i < 256; i += 256) s.W1[i] = from_bf16(bf16(a.params[P_W1 + i]));
   if (threadIdx.x < 64) {
     s.B1[threadIdx.x] = a.params[P_B1 + threadIdx.x];
@@ -106,27 +115,18 @@ __device__ void forward_tile(const MlpArgs& a, Smem& s, int64_t e0, f4_t z2[4]) 
     }
   }
   __syncthreads();
-  // layer 2 (MFMA): wave w computes events 16 w .. 16 w + 15 for all 64 outputs
+  // layer 2 (MFMA): wave w computes events 16 w .. 16 w + 15 for all 64 outputs:
+  // A[m = event][k = input] = h1 (rows of H1), B[k = input][n = output] = W2[output][input]
   const int l16 = lane & 15, lg = lane >> 4;
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    f4_t acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      // A[m = event][k = input]: lane supplies A[l16][4 lg + j] = h1[16 w + l16][16 kk + 4 lg + j]
-      const s4_t av = ld4(&s.H1[(16 * w + l16) * 64 + 16 * kk + 4 * lg]);
-      // B[k = input][n = output]: lane supplies B[4 lg + j][l16] = W2[16 nt + l16][16 kk + 4 lg + j]
-      const s4_t bv = ld4(&s.W2[(16 * nt + l16) * 64 + 16 * kk + 4 * lg]);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-    }
-    z2[nt] = acc;
-  }
+  for (int nt = 0; nt < 4; ++nt) z2[nt] = mm16x64(&s.H1[(16 * w) * 64], &s.W2[(16 * nt) * 64], l16, lg);
 }
 
 }  // namespace nn
 
 // Per-block gradient of the summed BCE (no 1/n) over the events [blk*per, (blk+1)*per),
-// written value-major to partial[v * gridDim.x + block]; v = 4545 is the loss.
+// written block-major to partial[block * 4546 + v] (one contiguous record per block, so the
+// writes are coalesced); v = 4545 is the loss.
 __global__ __launch_bounds__(256) void mlp_grad_kernel(MlpArgs a) {
   using namespace nn;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -199,33 +199,20 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(MlpArgs a) {
       }
     }
     __syncthreads();
-    // dW2[o][i] += sum_e dz2[e][o] h1[e][i]: wave w owns o-tile w
+    // dW2[o][i] += sum_e dz2[e][o] h1[e][i]: wave w owns o-tile w;
+    // A[m = o][k = e] = dz2[e][o] (rows of DZT), B[k = e][n = i] = h1[e][i] (rows of H1T)
+    static_assert(TE == 64, "tile rows are 64 deep");
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      f4_t acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        // A[m = o][k = e] = dz2[e][o]: DZT[16 w + l16][16 kk + 4 lg + j]
-        const s4_t av = nn::ld4(&s.DZT[(16 * w + l16) * TE + 16 * kk + 4 * lg]);
-        // B[k = e][n = i] = h1[e][i]: H1T[16 nt + l16][16 kk + 4 lg + j]
-        const s4_t bv = nn::ld4(&s.H1T[(16 * nt + l16) * TE + 16 * kk + 4 * lg]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-      }
+      const f4_t acc = nn::mm16x64(&s.DZT[(16 * w) * TE], &s.H1T[(16 * nt) * TE], l16, lg);
 #pragma unroll
       for (int r = 0; r < 4; ++r) gW2[nt][r] += acc[r];
     }
-    // dh1[e][i] = sum_o dz2[e][o] W2[o][i]: wave w owns events 16 w ..
+    // dh1[e][i] = sum_o dz2[e][o] W2[o][i]: wave w owns events 16 w ..;
+    // A[m = e][k = o] = dz2 (rows of DZ), B[k = o][n = i] = W2[o][i] (rows of W2T)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      f4_t acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        // A[m = e][k = o] = DZ[16 w + l16][16 kk + 4 lg + j]
-        const s4_t av = nn::ld4(&s.DZ[(16 * w + l16) * 64 + 16 * kk + 4 * lg]);
-        // B[k = o][n = i] = W2[o][i] = W2T[16 nt + l16][16 kk + 4 lg + j]
-        const s4_t bv = nn::ld4(&s.W2T[(16 * nt + l16) * 64 + 16 * kk + 4 * lg]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-      }
+      const f4_t acc = nn::mm16x64(&s.DZ[(16 * w) * 64], &s.W2T[(16 * nt) * 64], l16, lg);
       const int i = 16 * nt + l16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -241,8 +228,8 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(MlpArgs a) {
     __syncthreads();
   }
   // ---- block partials (value-major).  dW2 entries have a unique owner lane.
-  const int nb = gridDim.x;
-  auto put = [&](int v, float x) { a.partial[(int64_t)v * nb + blockIdx.x] = x; };
+  float* rec = a.partial + (int64_t)blockIdx.x * (MLP_NV);
+  auto put = [&](int v, float x) { rec[v] = x; };
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -274,43 +261,54 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(MlpArgs a) {
       if (t < 16) put(P_W1 + 4 * (16 * nt + t) + k, ((s.red[t] + s.red[64 + t]) + s.red[128 + t]) + s.red[192 + t]);
       __syncthreads();
     }
-  // b3 and loss: per-lane sums over the whole block in fixed order
-  s.red[t] = gb3;
-  __syncthreads();
+  // b3 and loss: a butterfly in each wavefront, then the four wavefronts in order
+  auto block_sum = [&](float x) -> float {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) s.red[w] = x;
+    __syncthreads();
+    const float r = ((s.red[0] + s.red[1]) + s.red[2]) + s.red[3];
+    __syncthreads();
+    return r;
+  };
+  const float sb3 = block_sum(gb3), sloss = block_sum(loss);
   if (t == 0) {
-    float x = 0.f;
-    for (int i = 0; i < 256; ++i) x += s.red[i];
-    put(P_B3, x);
-  }
-  __syncthreads();
-  s.red[t] = loss;
-  __syncthreads();
-  if (t == 0) {
-    float x = 0.f;
-    for (int i = 0; i < 256; ++i) x += s.red[i];
-    put(4545, x);
+    put(P_B3, sb3);
+    put(4545, sloss);
   }
 }
 
-// Sum of value-major block partials in FP64, fixed order; out[v] = scale * sum_b p[v][b].
-// out[v] = scale * sum_b partial[v * nb + b]: one wavefront per value (coalesced reads of the
-// value's nb block partials), lane sums in a fixed order, then a fixed butterfly.
+// Sum of block-major partials in FP64, fixed order: out[v] = scale * sum_b partial[b * nv + v].
+// A workgroup takes 64 consecutive values; its four wavefronts take the blocks b = s mod 4
+// (s = 0..3), each lane keeping four sums (blocks 16 k + s, + 4, + 8, + 12) so four reads are in
+// flight, and the 4 x 4 sums are combined in a fixed order.  A wavefront reads 64 consecutive
+// values of one block record: every read is coalesced.
 __global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ partial, int nb, int nv,
                                                          double scale, double* __restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (v >= nv) return;   // whole wavefronts exit together
-  const float* __restrict__ p = partial + (int64_t)v * nb;
-  double x = 0.0;
-  for (int b = lane; b < nb; b += 64) x += (double)p[b];
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-  if (lane == 0) out[v] = scale * x;
+  __shared__ double red[4][64];
+  const int vl = threadIdx.x & 63, seg = threadIdx.x >> 6;
+  const int v = blockIdx.x * 64 + vl;
+  double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+  if (v < nv) {
+    int b = seg;
+    for (; b + 12 < nb; b += 16) {
+      x0 += (double)partial[(int64_t)b * nv + v];
+      x1 += (double)partial[(int64_t)(b + 4) * nv + v];
+      x2 += (double)partial[(int64_t)(b + 8) * nv + v];
+      x3 += (double)partial[(int64_t)(b + 12) * nv + v];
+    }
+    for (; b < nb; b += 4) x0 += (double)partial[(int64_t)b * nv + v];
+  }
+  red[seg][vl] = (x0 + x1) + (x2 + x3);
+  __syncthreads();
+  if (seg == 0 && v < nv) out[v] = scale * (((red[0][vl] + red[1][vl]) + red[2][vl]) + red[3][vl]);
 }
 
-// Adam step on the FP32 master parameters.
+// Adam step on the FP32 master parameters; with w2h, also the BF16 copies of the updated 64x64
+// layer in both layouts (as launch_mlp_bf16 writes them).
 __global__ __launch_bounds__(256) void adam_kernel(float* p, float* m, float* v, const double* g, int n, float lr,
-                                                   float b1, float b2, float eps, float c1, float c2) {
+                                                   float b1, float b2, float eps, float c1, float c2,
+                                                   unsigned short* w2h) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = (float)g[i];
@@ -318,7 +316,14 @@ __global__ __launch_bounds__(256) void adam_kernel(float* p, float* m, float* v,
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  const float pi = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  p[i] = pi;
+  const int k = i - nn::P_W2;
+  if (w2h && k >= 0 && k < 4096) {
+    const unsigned short h = nn::bf16(pi);
+    w2h[k] = h;
+    w2h[4096 + (k & 63) * 64 + (k >> 6)] = h;
+  }
 }
 
 // Probabilities of the network for n events.
@@ -410,19 +415,35 @@ __global__ __launch_bounds__(256) void hist_count_kernel(HistCountArgs a) {
   if (a.label[e]) atomicAdd(&a.acc[idx], 1u);
 }
 
+// BF16 copies of the 64x64 layer's weights: w2h[0, 4096) = W2[o][i], w2h[4096, 8192) = W2[o][i] at [i][o].
+__global__ __launch_bounds__(256) void mlp_bf16_kernel(const float* __restrict__ params, unsigned short* __restrict__ w2h) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= 4096) return;
+  const unsigned short h = nn::bf16(params[nn::P_W2 + i]);
+  w2h[i] = h;
+  w2h[4096 + (i & 63) * 64 + (i >> 6)] = h;
+}
+
 size_t mlp_smem_bytes() { return sizeof(nn::Smem); }
+
+hipError_t launch_mlp_bf16(const float* params, unsigned short* w2h, hipStream_t st) {
+  hipLaunchKernelGGL(mlp_bf16_kernel, dim3(16), dim3(256), 0, st, params, w2h);
+  return hipGetLastError();
+}
 
 hipError_t launch_mlp_grad(const MlpArgs& a, int nb, hipStream_t st) {
   hipLaunchKernelGGL(mlp_grad_kernel, dim3(nb), dim3(256), sizeof(nn::Smem), st, a);
   return hipGetLastError();
 }
 hipError_t launch_mlp_reduce(const float* partial, int nb, int nv, double scale, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((nv + 3) / 4), dim3(256), 0, st, partial, nb, nv, scale, out);
+  if (nv != MLP_NV) return hipErrorInvalidValue;   // the block records are MLP_NV values long
+  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((nv + 63) / 64), dim3(256), 0, st, partial, nb, nv, scale, out);
   return hipGetLastError();
 }
 hipError_t launch_adam(float* p, float* m, float* v, const double* g, int n, float lr, float b1, float b2, float eps,
-                       float c1, float c2, hipStream_t st) {
-  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, m, v, g, n, lr, b1, b2, eps, c1, c2);
+                       float c1, float c2, unsigned short* w2h, hipStream_t st) {
+  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, m, v, g, n, lr, b1, b2, eps, c1, c2,
+                     w2h);
   return hipGetLastError();
 }
 hipError_t launch_mlp_eval(const MlpArgs& a, int nb, hipStream_t st) {

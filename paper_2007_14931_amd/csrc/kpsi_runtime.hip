@@ -125,6 +125,7 @@ struct kpsi_ctx {
   int64_t t_n = 0;
   std::vector<float> t_samples;  // the first kTimingSamples timed durations since the last reset
   int64_t t_dropped = 0;         // timed calls whose duration could not be read
+  unsigned short* mlp_w2h = nullptr;   // BF16 copies of the network's 64x64 layer (8192 values)
   int bench_reps = 0;             // kpsi_time_kernel: back-to-back launches of the per-event work
   double bench_ms = 0.0;          // their duration per launch
   int ept_override = 0;
@@ -977,6 +978,7 @@ kpsi_status kpsi_destroy(kpsi_ctx* c) {
     if (c->set[s].cols) hipFree(c->set[s].cols);
   }
   if (c->eps) hipFree(c->eps);
+  if (c->mlp_w2h) hipFree(c->mlp_w2h);
   if (c->eps_f64) hipFree(c->eps_f64);
   if (c->norm_w) hipFree(c->norm_w);
   if (c->wcol) hipFree(c->wcol);
@@ -1943,19 +1945,32 @@ kpsi_status kpsi_hist_efficiency(kpsi_ctx* c, int64_t n, const double* m, const 
 
 // Mean BCE gradient over events [0, n) into the device array g (MLP_NP doubles) and the mean
 // loss into g[MLP_NP].
+// BF16 copies of the 64x64 layer of the parameters at dparams (device), for the network kernels.
+static hipError_t prep_w2h(kpsi_ctx* c, const float* dparams) {
+  if (!c->mlp_w2h) {
+    hipError_t e = hipMalloc(&c->mlp_w2h, 8192 * sizeof(unsigned short));
+    if (e != hipSuccess) { c->mlp_w2h = nullptr; return e; }
+  }
+  return launch_mlp_bf16(dparams, c->mlp_w2h, c->stream);
+}
+
+// w2h_current: the BF16 copies already match dparams (the Adam kernel of the previous step wrote them)
 static hipError_t mlp_grad_device(kpsi_ctx* c, const float* dparams, int64_t n, const double* m, const double* ck,
                                   const double* cj, const double* phi, const uint8_t* label, float* partial,
-                                  int nbmax, double* g) {
+                                  int nbmax, double* g, bool w2h_current = false) {
   MlpArgs a = mlp_args(c, n, m, ck, cj, phi);
   a.label = label;
   a.params = dparams;
+  if (!w2h_current || !c->mlp_w2h)
+    if (hipError_t e = prep_w2h(c, dparams)) return e;
+  a.w2h = c->mlp_w2h;
   a.partial = partial;
   const int64_t tiles = (n + 63) / 64;
   const int nb = (int)std::min<int64_t>(tiles, nbmax);
   a.per_block = (tiles + nb - 1) / nb * 64;
   hipError_t e = launch_mlp_grad(a, nb, c->stream);
   if (e != hipSuccess) return e;
-  return launch_mlp_reduce(partial, nb, MLP_NP + 1, 1.0 / (double)n, g, c->stream);
+  return launch_mlp_reduce(partial, nb, MLP_NV, 1.0 / (double)n, g, c->stream);
 }
 
 kpsi_status kpsi_mlp_grad(kpsi_ctx* c, const float* params, int64_t n, const double* m, const double* ck,
@@ -2016,13 +2031,13 @@ kpsi_status kpsi_mlp_train(kpsi_ctx* c, float* params, int64_t n, const double* 
     double eloss = 0.0;
     for (int64_t b = 0; b < nbatch && e == hipSuccess; ++b) {
       const int64_t off = b * B, cnt = std::min(B, n - off);
-      e = mlp_grad_device(c, dp, cnt, m + off, ck + off, cj + off, phi + off, label + off, part, nbmax, g);
+      e = mlp_grad_device(c, dp, cnt, m + off, ck + off, cj + off, phi + off, label + off, part, nbmax, g, step > 0);
       ++step;
       const float c1 = (float)(1.0 / (1.0 - std::pow(o->beta1, (double)step)));
       const float c2 = (float)(1.0 / (1.0 - std::pow(o->beta2, (double)step)));
       if (e == hipSuccess)
         e = launch_adam(dp, mm, vv, g, MLP_NP, (float)o->lr, (float)o->beta1, (float)o->beta2, (float)o->eps, c1, c2,
-                        c->stream);
+                        c->mlp_w2h, c->stream);
       if (ep == o->epochs - 1 && e == hipSuccess) {
         double lb = 0.0;
         e = hipMemcpyAsync(&lb, g + MLP_NP, sizeof(double), hipMemcpyDeviceToHost, c->stream);
@@ -2045,6 +2060,8 @@ static hipError_t mlp_eval_device(kpsi_ctx* c, const float* dparams, int64_t n, 
   MlpArgs a = mlp_args(c, n, m, ck, cj, phi);
   a.params = dparams;
   a.out = out;
+  if (hipError_t e = prep_w2h(c, dparams)) return e;
+  a.w2h = c->mlp_w2h;
   const int64_t tiles = (n + 63) / 64;
   const int nb = (int)std::min<int64_t>(tiles, 2048);
   a.per_block = (tiles + nb - 1) / nb * 64;
