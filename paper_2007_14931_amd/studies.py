@@ -116,11 +116,62 @@ def learned_eff(args) -> dict:
     for name in ("histogram", "network"):
         d = np.abs(fits[name][0][free] - xt[free]) / st
         shifts[name] = {"mean_abs_shift_sigma": float(d.mean()), "max_abs_shift_sigma": float(d.max())}
+    response = normalisation_response(res, data, mc, eps_mc.cpu().numpy(), par, table, coef, args, stream)
     return {"study": "learned_efficiency", "workload": "learned_eff_1m", "data_events": wl.n_data,
             "data_proposals": nprop, "norm_events": wl.n_mc, "free_params": int(mask.sum()),
             "training": train_info, "efficiency_errors": errs,
             "fit_status": {k: v[2].as_dict() for k, v in fits.items()},
-            "fitted_parameter_shift_vs_true_efficiency": shifts}
+            "fitted_parameter_shift_vs_true_efficiency": shifts,
+            "normalisation_response": response}
+
+
+def normalisation_response(res, data, mc, eps_true, par, table, coef, args, stream) -> dict:
+    """How an efficiency estimate moves the fit, separated from the fit itself.  The data term of
+    -2 ln L does not depend on the efficiency (ln eps(x_i) is dropped), so with the data fixed an
+    estimate eps_X changes only the normalisation term: at the minimum x0 of the fit with the true
+    efficiency the gradient changes by dg_X = g_X(x0) - g_true(x0), which moves the minimum by
+    -(C/2) dg_X (C: that fit's HESSE covariance of -2 ln L), and the NLL by
+    2 N_d ln(N_X / N_true).  Evaluated for the histogram and the network of the study and for a
+    second histogram and network trained on an independent labelled sample: estimates whose errors
+    are independent from bin to bin move the fit differently from sample to sample, while a smooth
+    bias of the network moves it the same way."""
+    mask = W.free_mask(res)
+    free = np.flatnonzero(mask)
+    e = kpsi.Engine(0, "fp64", stream)
+    e.set_model(W.KIN, res)
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    e.set_efficiency_values(eps_true)
+    x0, C, r = e.migrad(W.params(res, W.WORKLOADS["learned_eff_1m"].coup_seed), mask)
+    sig = np.sqrt(np.abs(np.diag(C)))
+    v_true, g_true = e.nll_and_grad(x0)
+    nd = data.shape[1]
+    gen = kpsi.Engine(0, "fp64", stream)
+    gen.set_model(W.KIN, res)
+    par2, table2, _ = train_efficiency(gen, coef, args.train, 2141, epochs=args.epochs)
+    gen.close()
+    lo, hi = _lohi()
+    out, moved = {"fit_status": r.status}, {}
+    for name, kind, obj in (("histogram", "hist", table), ("network", "mlp", par),
+                            ("histogram_2", "hist", table2), ("network_2", "mlp", par2)):
+        if kind == "hist":
+            e.set_efficiency_hist(obj, lo, hi)
+        else:
+            e.set_efficiency_mlp(obj)
+        v, g = e.nll_and_grad(x0)
+        dg = (g - g_true)[free]
+        shift = -(C @ dg) / 2.0 / sig
+        moved[name] = shift
+        out[name] = {"rel_normalisation_change": float(math.expm1((v - v_true) / (2.0 * nd))),
+                     "rms_shift_sigma": float(np.sqrt(np.mean(shift ** 2))),
+                     "max_abs_shift_sigma": float(np.max(np.abs(shift)))}
+    e.close()
+    corr = lambda a, b: float(np.dot(a, b) / np.sqrt(np.dot(a, a) * np.dot(b, b)))
+    out["shift_correlation_histogram_vs_histogram_2"] = corr(moved["histogram"], moved["histogram_2"])
+    out["shift_correlation_network_vs_network_2"] = corr(moved["network"], moved["network_2"])
+    out["shift_correlation_histogram_vs_network"] = corr(moved["histogram"], moved["network"])
+    log(f"normalisation response: {out}")
+    return out
 
 
 def large_fit(args) -> dict:
