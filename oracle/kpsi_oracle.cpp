@@ -17,7 +17,7 @@
 //   Eq. (4)  K* helicity amplitude;  Eq. (5) K*-only signal density
 //   Eq. (6)  H_0 of K*(892) fixed to 1 (done by the caller through the free mask)
 //   Eq. (10) Z -> J/psi pi helicity amplitude, angles defined in the text below it
-//   Eq. (11) parity relation of the Z helicity couplings
+//   Eq. (11) parity relation of the Z helicity couplings (or, per resonance, none: Discussion)
 //   Eq. (12) full signal density (K* + Z coherent sum)
 //   Eq. (14) efficiency-weighted PDF (signal part), normalised by phase-space MC
 //   text after Eq. (12): charge-conjugate decays (phi -> -phi) with a flavour mistag rate
@@ -87,7 +87,10 @@ struct Kin { double mB, mJ, mK, mPi, rB, rR; };
 // chain: 0 = K* (K pi), 1 = Z (J/psi pi); lb/lr < 0 => lowest allowed.
 // shape: 0 relativistic Breit-Wigner (Eq. 2-3); 1 LASS S-wave (Eq. 7-8) with effective-range
 // parameters a, b (GeV^-1) for a spin-0 K*.
-struct Res { int chain, spin, parity, lb, lr; double mass, width; int shape; double lass_a, lass_b; };
+// hel_free (Z only): H'_{+1} and H'_{-1} are independent couplings instead of being tied by the
+// parity relation of Eq. (11) (the Discussion states that the Z part can also be fitted with its
+// couplings unconstrained).  Parameter order of such a Z: lambda' = 0, +1, -1.
+struct Res { int chain, spin, parity, lb, lr; double mass, width; int shape; double lass_a, lass_b; int hel_free; };
 
 // Lowest orbital momenta (text below Eq. 3 for the K*; angular momentum and
 // parity for the Z, which decays strongly to J/psi(1-) pi(0-)).
@@ -104,7 +107,7 @@ static int res_LB(const Res& r) {
 // Number of independent complex helicity couplings of a resonance.
 static int res_ncoup(const Res& r) {
   if (r.chain == 0) return r.spin == 0 ? 1 : 3;   // lambda in {-1,0,1}, only 0 for spin 0 (Eq. 4)
-  return 2;                                      // Z 1+: lambda' = 0 and +1 (H_-1 from Eq. 11)
+  return r.hel_free ? 3 : 2;                     // Z: lambda' = 0, +1 (H_-1 from Eq. 11), or 0, +1, -1
 }
 
 // Two-body breakup momentum of M -> m1 m2 in the M rest frame.
@@ -354,12 +357,14 @@ T density(const Kin& k, const std::vector<Res>& rs, const T* par, const Event& e
     } else {
       // Eq. (10): H'_l A^Z(m_Jpsi pi) d^J_{0 l}(theta_Z) e^{i l phi~} d^1_{l xi}(theta~) e^{i xi alpha}
       Cx<T> A = lineshape(k, r, M, G, za.mJpi);
-      // Eq. (11): H'_{-l} = -P (-1)^J H'_{l}
+      // Eq. (11): H'_{-l} = -P (-1)^J H'_{l}, unless the resonance leaves H'_{-1} free
       double eta = -(double)r.parity * ((r.spin % 2 == 0) ? 1.0 : -1.0);
       Cx<T> H0{par[ip] * tcos(par[ip + 1]), par[ip] * tsin(par[ip + 1])};
       Cx<T> H1{par[ip + 2] * tcos(par[ip + 3]), par[ip + 2] * tsin(par[ip + 3])};
+      Cx<T> Hm1 = r.hel_free ? Cx<T>{par[ip + 4] * tcos(par[ip + 5]), par[ip + 4] * tsin(par[ip + 5])}
+                             : Cx<T>{H1.re * eta, H1.im * eta};
       for (int lam = -1; lam <= 1; ++lam) {
-        Cx<T> H = (lam == 0) ? H0 : (lam == 1 ? H1 : Cx<T>{H1.re * eta, H1.im * eta});
+        Cx<T> H = (lam == 0) ? H0 : (lam == 1 ? H1 : Hm1);
         double dz = wigner_d(r.spin, 0, lam, za.thZ);
         Cx<T> HA = cmul(H, A);
         for (int x = 0; x < 2; ++x) {
@@ -368,7 +373,7 @@ T density(const Kin& k, const std::vector<Res>& rs, const T* par, const Event& e
           a[x] = cadd(a[x], cmul(HA, ctoT<T>(cscale(e, dz * dj))));
         }
       }
-      ip += 4;
+      ip += 2 * res_ncoup(r);
     }
   }
   return cnorm2(a[0]) + cnorm2(a[1]);
@@ -393,13 +398,13 @@ using namespace orc;
 extern "C" {
 
 struct oracle_kin { double mB, mJ, mK, mPi, rB, rR; };
-struct oracle_res { int chain, spin, parity, lb, lr; double mass, width; int shape; double lass_a, lass_b; };
+struct oracle_res { int chain, spin, parity, lb, lr; double mass, width; int shape; double lass_a, lass_b; int hel_free; };
 
 static std::vector<Res> to_res(const oracle_res* r, int n) {
   std::vector<Res> v;
   for (int i = 0; i < n; ++i)
     v.push_back(Res{r[i].chain, r[i].spin, r[i].parity, r[i].lb, r[i].lr, r[i].mass, r[i].width, r[i].shape,
-                    r[i].lass_a, r[i].lass_b});
+                    r[i].lass_a, r[i].lass_b, r[i].chain == 1 ? r[i].hel_free : 0});
   return v;
 }
 static Kin to_kin(const oracle_kin* k) { return Kin{k->mB, k->mJ, k->mK, k->mPi, k->rB, k->rR}; }
@@ -413,7 +418,7 @@ double oracle_breakup(double M, double m1, double m2) { return breakup(M, m1, m2
 void oracle_lineshape(const oracle_kin* kin, const oracle_res* res, double M, double G0, double m, double* out_re_im) {
   Kin k = to_kin(kin);
   Res r{res->chain, res->spin, res->parity, res->lb, res->lr, res->mass, res->width, res->shape, res->lass_a,
-        res->lass_b};
+        res->lass_b, 0};
   Cx<double> a = lineshape<double>(k, r, M, G0, m);
   out_re_im[0] = a.re; out_re_im[1] = a.im;
 }

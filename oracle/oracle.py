@@ -34,7 +34,7 @@ class Kin(C.Structure):
 class Res(C.Structure):
     _fields_ = [("chain", C.c_int), ("spin", C.c_int), ("parity", C.c_int), ("lb", C.c_int), ("lr", C.c_int),
                 ("mass", C.c_double), ("width", C.c_double), ("shape", C.c_int), ("lass_a", C.c_double),
-                ("lass_b", C.c_double)]
+                ("lass_b", C.c_double), ("hel_free", C.c_int)]
 
 
 _lib = None
@@ -43,8 +43,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
+        # a library older than its source (say, a changed struct layout) is rebuilt, never loaded
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
         L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)
         kp, rp = C.POINTER(Kin), C.POINTER(Res)
@@ -88,7 +89,8 @@ def kin(d: dict) -> Kin:
 def res_array(res) -> C.Array:
     arr = (Res * len(res))()
     for i, r in enumerate(res):
-        arr[i] = Res(r.chain, r.spin, r.parity, r.lb, r.lr, r.mass, r.width, r.shape, r.lass_a, r.lass_b)
+        arr[i] = Res(r.chain, r.spin, r.parity, r.lb, r.lr, r.mass, r.width, r.shape, r.lass_a, r.lass_b,
+                     int(getattr(r, "hel_free", False)))
     return arr
 
 

@@ -12,7 +12,8 @@ U[0.1, 1], phase in U[-pi, pi]); H_0 of K*(892) is fixed to 1 (Eq. 6).
 
 Canonical parameter vector (the C ABI's layout): for each resonance in table order
 its coupling (magnitude, phase) pairs -- K*: lambda = -1, 0, +1 (spin 0: lambda = 0
-only); Z (1+): lambda' = 0, +1 (lambda' = -1 follows from Eq. 11) -- then
+only); Z (1+): lambda' = 0, +1 (lambda' = -1 follows from Eq. 11), or lambda' = 0, +1, -1
+for a Z whose helicity couplings are left free of that relation (hel_free) -- then
 (M, Gamma0) for every resonance in table order.
 """
 from __future__ import annotations
@@ -46,12 +47,13 @@ class Resonance:
     shape: int = 0           # 0 relativistic Breit-Wigner, 1 LASS S-wave (spin-0 K* only)
     lass_a: float = 1.95     # LASS effective-range parameters (GeV^-1)
     lass_b: float = 1.76
+    hel_free: bool = False   # Z only: H'_{+1} and H'_{-1} independent (no Eq. 11 relation)
 
     @property
     def n_coup(self) -> int:
         if self.chain == KSTAR:
             return 1 if self.spin == 0 else 3
-        return 2
+        return 3 if self.hel_free else 2
 
 
 KSTARS = [
@@ -84,6 +86,8 @@ def model(name: str) -> list[Resonance]:
         return list(KSTARS) + [Z4430]
     if name == "full2z":
         return list(KSTARS) + [Z4430, Z4240]
+    if name == "full_zfree":
+        return list(KSTARS) + [dataclasses.replace(Z4430, hel_free=True)]
     if name in ("kstar_lass", "lass_full2z"):
         ks = [LASS] + [r for r in KSTARS if r.name not in ("K0*(800)", "K0*(1430)")]
         return ks if name == "kstar_lass" else ks + [Z4430, Z4240]

@@ -8,6 +8,7 @@ Eq. (4)-(5), the angle-integrated spin orthogonality of Eq. (5), Dalitz-plot
 identities, an independent polarisation-vector construction of Eq. (12) in the
 J/psi rest frame, and quadrature of the phase-space density.
 """
+import dataclasses
 import math
 import os
 
@@ -391,9 +392,11 @@ def _S_polarisation(res, par, ev):
             A = O.lineshape(K, r, M, G, mz)
             h0 = par[ip] * np.exp(1j * par[ip + 1])
             h1 = par[ip + 2] * np.exp(1j * par[ip + 3])
-            for lam, h in ((0, h0), (1, h1), (-1, h1)):
+            # a 1+ Z: H'_{-1} = H'_{+1} (Eq. 11), unless the resonance leaves it free
+            hm = par[ip + 4] * np.exp(1j * par[ip + 5]) if r.hel_free else h1
+            for lam, h in ((0, h0), (1, h1), (-1, hm)):
                 eps += h * A * (-1) ** lam * _dm0(1, lam, cz) * e2[lam]   # d^1_{0 l} = (-1)^l d^1_{l 0}
-            ip += 4
+            ip += 2 * r.n_coup
     return float((np.vdot(eps, eps) - abs(mu @ eps) ** 2).real)
 
 
@@ -419,6 +422,58 @@ def test_z_only_model_independent_of_alpha_and_frame():
     S = O.density(K, res, par, ev)
     ref = np.array([_S_polarisation(res, par, ev[:, i]) for i in range(ev.shape[1])])
     np.testing.assert_allclose(S, ref, rtol=1e-11)
+
+
+def _free_from_constrained(par, res_c, res_f, rng=None):
+    """Parameter vector of the free-helicity model holding the constrained model's couplings,
+    with H'_{-1} = H'_{+1} (rng None) or a random H'_{-1}."""
+    out, ip, jf = [], 0, 0
+    nc = sum(2 * r.n_coup for r in res_c)
+    for rc, rf in zip(res_c, res_f):
+        c = list(par[ip: ip + 2 * rc.n_coup])
+        if rf.hel_free:
+            c += c[2:4] if rng is None else [rng.uniform(0.1, 1.0), rng.uniform(-math.pi, math.pi)]
+        out += c
+        ip += 2 * rc.n_coup
+    return np.array(out + list(par[nc:]))
+
+
+def test_free_z_couplings_reduce_to_the_parity_relation():
+    """With H'_{-1} set to H'_{+1} (the relation Eq. 11 gives a 1+ state) the free-helicity model
+    is the constrained one, event by event; with H'_{-1} moved away it is not."""
+    res_c, res_f = W.model("full"), W.model("full_zfree")
+    assert [r.n_coup for r in res_f][-1] == 3 and W.n_params(res_f) == W.n_params(res_c) + 2
+    par = W.params(res_c, seed=19)
+    ev = W.neutral_events(200, 20)
+    Sc = O.density(K, res_c, par, ev)
+    Sf = O.density(K, res_f, _free_from_constrained(par, res_c, res_f), ev)
+    np.testing.assert_allclose(Sf, Sc, rtol=1e-13)
+    Sx = O.density(K, res_f, _free_from_constrained(par, res_c, res_f, np.random.default_rng(5)), ev)
+    assert np.max(np.abs(Sx - Sc) / Sc) > 1e-2
+
+
+@pytest.mark.parametrize("model,seed", [("full_zfree", 13), ("full_zfree", 29)])
+def test_free_z_couplings_match_the_polarisation_construction(model, seed):
+    """Independent H'_{+1} and H'_{-1}: the oracle's angle-based Eq. (10)-(12) equals the
+    frame-free polarisation-vector construction, which attaches each coupling to its own
+    spherical basis vector of the Z-chain helicity frame.  A coupling put on the other helicity,
+    or the wrong sign of d^1_{0,-1}, fails this."""
+    res = W.model(model)
+    par = W.params(res, seed=seed)
+    ev = W.neutral_events(40, seed)
+    S = O.density(K, res, par, ev)
+    ref = np.array([_S_polarisation(res, par, ev[:, i]) for i in range(ev.shape[1])])
+    np.testing.assert_allclose(S, ref, rtol=1e-11)
+    # a Z alone with only H'_{-1}: |A^Z|^2 n_Z^2 sin^2(theta_Z)/2 sum_xi d^1_{-1 xi}(theta~)^2,
+    # i.e. sin^2(theta_Z) (1 + cos^2 theta~)/4 times the lineshape squared
+    z = dataclasses.replace(W.Z4430, hel_free=True)
+    pz = np.array([0.0, 0.0, 0.0, 0.0, 0.7, 0.4, z.mass, z.width])
+    za = O.z_angles(K, ev)
+    Sz = O.density(K, [z], pz, ev)
+    A2 = np.array([abs(O.lineshape(K, z, z.mass, z.width, m)) ** 2 for m in za[:, 0]])
+    closed = 0.49 * A2 * np.sin(za[:, 1]) ** 2 * (1 + np.cos(za[:, 2]) ** 2) / 4
+    np.testing.assert_allclose(Sz, closed, rtol=1e-11)
+    np.testing.assert_allclose(Sz, np.array([_S_polarisation([z], pz, ev[:, i]) for i in range(40)]), rtol=1e-11)
 
 
 # ---------------------------------------------------------------- NLL and gradient
@@ -450,7 +505,7 @@ def test_nll_nonfinite_status():
     assert st == -5 and v == math.inf
 
 
-@pytest.mark.parametrize("model", ["kstar892", "full"])
+@pytest.mark.parametrize("model", ["kstar892", "full", "full_zfree"])
 def test_dual_gradient_matches_central_differences(model):
     res, par, data, mc = _small_sets(model, 200, 600)
     dirs = list(range(len(par)))
