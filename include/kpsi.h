@@ -34,7 +34,8 @@
  * Parameter vector (double, length from kpsi_n_params): for each resonance in the
  * order given to kpsi_set_model, its helicity couplings as (magnitude, phase) pairs --
  * K* (Eq. 4): lambda = -1, 0, +1, or only lambda = 0 for spin 0; Z (Eq. 10, spin-parity
- * 1+): lambda' = 0 and lambda' = +1, with H'_-1 = H'_+1 from Eq. (11) -- followed by
+ * 1+): lambda' = 0 and lambda' = +1, with H'_-1 = H'_+1 from Eq. (11), or lambda' = 0, +1, -1
+ * for a Z with hel_free set -- followed by
  * (M, Gamma0) of every resonance in table order (Eq. 2-3).  The overall phase and
  * magnitude convention of Eq. (6) is the caller's business (fix those entries).
  */
@@ -86,6 +87,11 @@ typedef struct {
                     with cot d = 1/(a q) + b q/2 and Gamma(m) = Gamma0 (q/q0)(M/m) */
   double lass_a; /* LASS scattering length a in GeV^-1 (> 0); ignored when shape = 0 */
   double lass_b; /* LASS effective range b in GeV^-1 (finite); ignored when shape = 0 */
+  int hel_free;  /* Z only (0 for a K*): 1 leaves H'_+1 and H'_-1 independent instead of tied by
+                    Eq. 11 (the Discussion's unconstrained Z couplings); the Z then has three
+                    couplings, lambda' = 0, +1, -1 in that order.  Supported for a model with
+                    exactly one Z, without flavour tags, the normalisation cache or fit
+                    fractions (those calls return KPSI_E_UNSUPPORTED) */
 } kpsi_resonance;
 
 typedef struct {

@@ -63,6 +63,9 @@ template <typename P> __device__ __forceinline__ kconst_ptr<P> kernarg_laundered
 //               combined through Eq. 11 (columns 14-15), each multiplied by
 //               nZ = (p_B/M_B) / sqrt(1 + (r_B p_B)^2), the factor common to every Z amplitude.
 //               The xi = -1 factors are (-Re, Im) of the xi = +1 ones and are not stored.
+//               With free Z helicities (zfree), columns 14-15 hold F++ = Zang[+1][+1] and
+//               16-17 F+- = Zang[+1][-1]; the l' = -1 factors are Zang[-1][+1] = -conj(F+-)
+//               and Zang[-1][-1] = -conj(F++).
 // All arithmetic in double; stored in T.
 template <typename T>
 __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
@@ -180,6 +183,16 @@ __global__ __launch_bounds__(256) void invariants_kernel(InvArgs<T> a) {
   //                                 xi = -1: sZ/sqrt2 (-ct cpt + i spt) e^{-i alpha}, again
   //                                 (-Re, Im) of the xi = +1 factor
   const double z1 = sZ * r2;
+  if (a.zfree) {
+    // l' = +1 alone: d^1_{0,1}(theta_Z) = sZ/sqrt2, d^1_{1,xi}(theta~) = (1 + xi ct)/2, phases
+    // e^{i (phi~ + xi alpha)}
+    const double up = 0.5 * z1 * (1.0 + ct), dn = 0.5 * z1 * (1.0 - ct);
+    c[col_at(14, e, ld)] = (T)(up * (cpt * ca - spt * sa));
+    c[col_at(15, e, ld)] = (T)(up * (spt * ca + cpt * sa));
+    c[col_at(16, e, ld)] = (T)(dn * (cpt * ca + spt * sa));
+    c[col_at(17, e, ld)] = (T)(dn * (spt * ca - cpt * sa));
+    return;
+  }
   const double pr = ct * cpt, pi_ = spt;
   c[col_at(14, e, ld)] = (T)(z1 * (pr * ca - pi_ * sa));
   c[col_at(15, e, ld)] = (T)(z1 * (pr * sa + pi_ * ca));
@@ -316,10 +329,13 @@ template <typename T, class Sh, int MODE> struct AmpWaves {
 // CC: flavour-tagged events (text after Eq. 12).  Data events carry a tag q = +-1 and are read
 // with phi -> q phi, plus the other flavour with the mistag weight; the normalisation events run
 // twice, as record 1 (phi) and record 2 (-phi), blocks [nb_data + nb_mc, nb_data + 2 nb_mc).
-template <typename T, class Sh, int MODE, bool CC>
+// ZF: one Z whose H'_{+1} and H'_{-1} are independent couplings (no Eq. 11 relation); its
+// lambda' = -1 accumulators use the record slots of the second Z.
+template <typename T, class Sh, int MODE, bool CC, bool ZF>
 __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(const AmpArgs<T, Sh> a) {
   constexpr int NK = Sh::NK;
-  constexpr int NZ = Sh::NZ;
+  static_assert(!ZF || (Sh::NZ >= 2 && !CC), "free Z helicities: one Z, untagged events");
+  constexpr int NZ = ZF ? 1 : Sh::NZ;   // Z slots evaluated
   constexpr bool GRAD = (MODE == MODE_GRAD);
   using A_t = typename AccType<T>::type;   // per-thread gradient accumulator type
 
@@ -377,14 +393,14 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     for (int i = 0; i < HI - LO; ++i) accl[i][threadIdx.x] = A_t(0);
   }
   A_t gk[Sh::NKACC > 0 ? Sh::NKACC : 1];
-  A_t gz[NZ > 0 ? 4 * NZ : 1];
+  A_t gz[NZ > 0 ? 4 * Sh::NZ : 1];
   static_assert(NFL == 2, "floating accumulators are named registers for two slots");
   A_t gM0 = 0, gG0 = 0, gM1 = 0, gG1 = 0;   // d/dM, d/dGamma0 of floating slots 0 and 1
   if constexpr (GRAD) {
 #pragma unroll
     for (int i = 0; i < Sh::NKACC; ++i) gk[i] = 0;
 #pragma unroll
-    for (int i = 0; i < 4 * NZ; ++i) gz[i] = 0;
+    for (int i = 0; i < 4 * Sh::NZ; ++i) gz[i] = 0;
   }
 
   using V4 = T __attribute__((ext_vector_type(4)));
@@ -516,12 +532,17 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
       ap_ = Cx<T>{hp * eUp.re + s0 * U0.re + hm * eUm.re, hp * eUp.im + s0 * U0.im + hm * eUm.im};
       am_ = Cx<T>{hm * eUp.re - s0 * U0.re + hp * eUm.re, hm * eUp.im - s0 * U0.im + hp * eUm.im};
     };
-    T za[8];
-    auto z_add = [&](T f, const Cx<T>& T0, const Cx<T>& T1, Cx<T>& ap_, Cx<T>& am_) {
+    // Zang[l'][xi] as (re, im) pairs: l' = 0 (xi = +1, -1), l' = +-1 or +1, then (ZF) l' = -1
+    T za[ZF ? 12 : 8];
+    auto z_add = [&](T f, const Cx<T>& T0, const Cx<T>& T1, const Cx<T>& T2, Cx<T>& ap_, Cx<T>& am_) {
       cmac(ap_, T0.re, T0.im, za[0], f * za[1]);
       cmac(am_, T0.re, T0.im, za[2], f * za[3]);
       cmac(ap_, T1.re, T1.im, za[4], f * za[5]);
       cmac(am_, T1.re, T1.im, za[6], f * za[7]);
+      if constexpr (ZF) {
+        cmac(ap_, T2.re, T2.im, za[8], f * za[9]);
+        cmac(am_, T2.re, T2.im, za[10], f * za[11]);
+      }
     };
     // flavour of this reading: the tag of a data event, + / - for the two normalisation records
     T f1 = T(1);
@@ -538,11 +559,18 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
       if (a.cnt[5] > 0) {
         const T mz2 = g2.y;
         gzv = g2.w;
-        // Zang[l'][xi]: xi = -1 is (-Re, Im) of xi = +1
+        // Zang[l'][xi]: for l' = 0 and the combined l' = +-1, xi = -1 is (-Re, Im) of xi = +1
         const V4 g3 = ldoff(gb + 3 * ld, ob4);
         za[0] = g3.x; za[1] = g3.y; za[2] = -g3.x; za[3] = g3.y;
-        za[4] = g3.z; za[5] = g3.w; za[6] = -g3.z; za[7] = g3.w;
-        Cx<T> T0{T(0), T(0)}, T1{T(0), T(0)};
+        if constexpr (ZF) {
+          // l' = +1: F++, F+-;  l' = -1: -conj(F+-), -conj(F++)
+          const V4 g4 = ldoff(gb + 4 * ld, ob4);
+          za[4] = g3.z; za[5] = g3.w; za[6] = g4.x; za[7] = g4.y;
+          za[8] = -g4.x; za[9] = g4.y; za[10] = -g3.z; za[11] = g3.w;
+        } else {
+          za[4] = g3.z; za[5] = g3.w; za[6] = -g3.z; za[7] = g3.w;
+        }
+        Cx<T> T0{T(0), T(0)}, T1{T(0), T(0)}, T2{T(0), T(0)};
 #pragma unroll
         for (int z = 0; z < NZ; ++z) {
           if (z < a.cnt[5]) {
@@ -553,9 +581,10 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
             AZ[z] = Cx<T>{dre * inv, dim * inv};
             cmac(T0, rc.hr[0], rc.hi[0], AZ[z].re, AZ[z].im);
             cmac(T1, rc.hr[1], rc.hi[1], AZ[z].re, AZ[z].im);
+            if constexpr (ZF) cmac(T2, rc.hr[2], rc.hi[2], AZ[z].re, AZ[z].im);
           }
         }
-        z_add(f1, T0, T1, ap, am);
+        z_add(f1, T0, T1, T2, ap, am);
         if constexpr (CC) {
           T0k = T0;
           T1k = T1;
@@ -581,7 +610,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
           // t = (1 - w) S(q phi) + w S(-q phi)
           kstar_at(-f1, ap2, am2);
           if constexpr (NZ > 0) {
-            if (a.cnt[5] > 0) z_add(-f1, T0k, T1k, ap2, am2);
+            if (a.cnt[5] > 0) z_add(-f1, T0k, T1k, T1k, ap2, am2);   // (no third sum: ZF excludes CC)
           }
           const T S2 = ap2.re * ap2.re + ap2.im * ap2.im + am2.re * am2.re + am2.im * am2.im;
           arg = fma_(a.keep, S, a.mistag * S2);
@@ -718,8 +747,12 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
             WZ1 = Cx<T>{za[4] * bp_.re - z5 * bp_.im + za[6] * bm_.re - z7 * bm_.im,
                         za[4] * bp_.im + z5 * bp_.re + za[6] * bm_.im + z7 * bm_.re};
           };
-          Cx<T> WZ0, WZ1;
+          Cx<T> WZ0, WZ1, WZ2{T(0), T(0)};
           wz(f1, bp, bm, WZ0, WZ1);
+          if constexpr (ZF) {
+            WZ2 = Cx<T>{za[8] * bp.re - za[9] * bp.im + za[10] * bm.re - za[11] * bm.im,
+                        za[8] * bp.im + za[9] * bp.re + za[10] * bm.im + za[11] * bm.re};
+          }
           if constexpr (CC) {
             if (two) {
               Cx<T> X0, X1;
@@ -735,11 +768,13 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
               A_t* g = gz + 4 * z;
               cacc(g[0], g[1], A, WZ0);
               cacc(g[2], g[3], A, WZ1);
+              if constexpr (ZF) cacc(g[4], g[5], A, WZ2);   // the second Z's lambda' = 0 slots
               const auto& rc = ka.zs[z];
               if (rc.flt >= 0) {
                 Cx<T> Q{T(0), T(0)};
                 cmac(Q, rc.hr[0], rc.hi[0], WZ0.re, WZ0.im);
                 cmac(Q, rc.hr[1], rc.hi[1], WZ1.re, WZ1.im);
+                if constexpr (ZF) cmac(Q, rc.hr[2], rc.hi[2], WZ2.re, WZ2.im);
                 flt_deriv(rc, A, Q, gzv, gM0, gG0, gM1, gG1);
               }
             }
@@ -761,8 +796,8 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
       if (i == 2) return (A_t)nbad;
       if (LDSACC && i >= 3 + LO && i < 3 + HI) return accl[i - 3 - LO][threadIdx.x];
       if (i < 3 + Sh::NKACC) return gk[i - 3];
-      if (i < 3 + Sh::NKACC + 4 * NZ) return gz[i - 3 - Sh::NKACC];
-      const int f = i - 3 - Sh::NKACC - 4 * NZ;
+      if (i < 3 + Sh::NKACC + 4 * Sh::NZ) return gz[i - 3 - Sh::NKACC];
+      const int f = i - 3 - Sh::NKACC - 4 * Sh::NZ;
       if (f == 0) return gM0;
       if (f == 1) return gG0;
       if (f == 2) return gM1;
@@ -1033,40 +1068,59 @@ template <typename T> hipError_t launch_invariants(const InvArgs<T>& a, hipStrea
 template hipError_t launch_invariants<float>(const InvArgs<float>&, hipStream_t);
 template hipError_t launch_invariants<double>(const InvArgs<double>&, hipStream_t);
 
-template <typename T, class Sh>
-hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st) {
-  if (nblocks <= 0) return hipSuccess;
-  const bool cc = a.tag != nullptr && mode != MODE_DENSITY;
+template <typename T, class Sh, bool ZF>
+hipError_t launch_amp_zf(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st) {
+  const bool cc = !ZF && a.tag != nullptr && mode != MODE_DENSITY;
   if (mode == MODE_GRAD) {
-    if (cc) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_GRAD, true>), dim3(nblocks), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_GRAD, false>), dim3(nblocks), dim3(256), 0, st, a);
+    if (cc) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_GRAD, true, false>), dim3(nblocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_GRAD, false, ZF>), dim3(nblocks), dim3(256), 0, st, a);
   } else if (mode == MODE_NLL) {
-    if (cc) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_NLL, true>), dim3(nblocks), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_NLL, false>), dim3(nblocks), dim3(256), 0, st, a);
+    if (cc) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_NLL, true, false>), dim3(nblocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_NLL, false, ZF>), dim3(nblocks), dim3(256), 0, st, a);
   } else {
-    hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_DENSITY, false>), dim3(nblocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_DENSITY, false, ZF>), dim3(nblocks), dim3(256), 0, st, a);
   }
   return hipGetLastError();
 }
+template <typename T, class Sh>
+hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if constexpr (Sh::NZ >= 2) {
+    if (a.zfree) {
+      if (a.tag != nullptr || a.cnt[5] != 1) return hipErrorInvalidValue;   // refused by the host API
+      return launch_amp_zf<T, Sh, true>(a, mode, nblocks, st);
+    }
+  } else {
+    if (a.zfree) return hipErrorInvalidValue;
+  }
+  return launch_amp_zf<T, Sh, false>(a, mode, nblocks, st);
+}
 // Blocks of the per-event kernel that can be resident on one compute unit at once (from its
 // register and LDS use), or 0 if the runtime cannot tell.
-template <typename T, class Sh>
-int amp_blocks_per_cu(int mode, bool cc) {
+template <typename T, class Sh, bool ZF>
+int amp_blocks_per_cu_zf(int mode, bool cc) {
   int nb = 0;
   hipError_t e;
   if (mode == MODE_GRAD)
-    e = cc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_GRAD, true>, 256, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_GRAD, false>, 256, 0);
+    e = cc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_GRAD, true, false>, 256, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_GRAD, false, ZF>, 256, 0);
   else if (mode == MODE_NLL)
-    e = cc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_NLL, true>, 256, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_NLL, false>, 256, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_DENSITY, false>, 256, 0);
+    e = cc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_NLL, true, false>, 256, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_NLL, false, ZF>, 256, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_DENSITY, false, ZF>, 256, 0);
   return (e == hipSuccess && nb > 0) ? nb : 0;
 }
-template int amp_blocks_per_cu<float, ShapeSmall>(int, bool);
-template int amp_blocks_per_cu<double, ShapeSmall>(int, bool);
-template int amp_blocks_per_cu<float, ShapeFull>(int, bool);
-template int amp_blocks_per_cu<double, ShapeFull>(int, bool);
+template <typename T, class Sh>
+int amp_blocks_per_cu(int mode, bool cc, bool zfree) {
+  if constexpr (Sh::NZ >= 2) {
+    if (zfree && !cc) return amp_blocks_per_cu_zf<T, Sh, true>(mode, false);
+  }
+  return amp_blocks_per_cu_zf<T, Sh, false>(mode, cc);
+}
+template int amp_blocks_per_cu<float, ShapeSmall>(int, bool, bool);
+template int amp_blocks_per_cu<double, ShapeSmall>(int, bool, bool);
+template int amp_blocks_per_cu<float, ShapeFull>(int, bool, bool);
+template int amp_blocks_per_cu<double, ShapeFull>(int, bool, bool);
 
 template hipError_t launch_amp<float, ShapeSmall>(const AmpArgs<float, ShapeSmall>&, int, int, hipStream_t);
 template hipError_t launch_amp<double, ShapeSmall>(const AmpArgs<double, ShapeSmall>&, int, int, hipStream_t);

@@ -11,7 +11,8 @@ constexpr int NACC = 64;        // doubles per block partial (one per lane of a 
 constexpr int NFL = 2;          // floating (M, Gamma0) slots in the adjoint
 constexpr int NCOL_KSTAR = 9;   // per-event columns of the K* chain
 constexpr int NCOL_Z = 7;       // extra per-event columns of the Z chain
-constexpr int NCOL_MAX = NCOL_KSTAR + NCOL_Z;
+constexpr int NCOL_ZFREE = 2;   // and of a Z whose H'_{+1}, H'_{-1} are independent
+constexpr int NCOL_MAX = 4 * ((NCOL_KSTAR + NCOL_Z + NCOL_ZFREE + 3) / 4);   // whole column groups
 // Per-event columns are stored in groups of four: column k of event e sits at element
 // ((k / 4) * ld + e) * 4 + k % 4, so one 16-byte (FP32) or 32-byte (FP64) load per lane
 // reads four columns of an event, and a wavefront's load is one contiguous span.
@@ -27,7 +28,8 @@ enum { MODE_DENSITY = 0, MODE_NLL = 1, MODE_GRAD = 2 };
 template <typename T> struct RC {
   T M2, P, K;
   T M2lo;             // M^2 - M2 (FP32 constants: the rounding remainder of M^2; FP64: 0)
-  T hr[3], hi[3];     // K*: lambda = -1, 0, +1; Z: [0] lambda' = 0, [1] lambda' = +-1
+  T hr[3], hi[3];     // K*: lambda = -1, 0, +1; Z: [0] lambda' = 0, [1] lambda' = +-1 (Eq. 11)
+                      // or, free helicities, [1] lambda' = +1 and [2] lambda' = -1
   T kap, twoM, dP, PoG;   // d ln K/dM, 2M, dP/dM, P/Gamma0
   int flt;            // floating slot or -1
   T f0, f1;           // 1 where flt is 0 (1), else 0
@@ -89,6 +91,10 @@ template <typename T, class Sh> struct AmpArgs {
   const double* norm_total;
   double bkg_coef;
   T purity;
+  // Free Z helicities (one Z, H'_{+1} and H'_{-1} independent): selects the kernel
+  // instantiation that reads the extra angular columns; its lambda' = -1 accumulators take the
+  // record slots of the (then unused) second Z.
+  int zfree;
 };
 // Record slot of sum_i w_i S_i over the data events of the mixture (gradient mode).
 template <class Sh> constexpr int ws_slot() { return 3 + Sh::NKACC + 4 * Sh::NZ + 2 * NFL; }
@@ -99,6 +105,7 @@ template <typename T> struct InvArgs {
   int64_t ld, n;
   double mB, mJ, mK, mPi, rB, rR;
   int with_z;
+  int zfree;              // with_z and free Z helicities: columns 14-17 hold the separate factors
   double* diag;           // optional (n, 5) output: m_Jpsi pi, cos theta_Z, cos theta~, phi~, alpha
 };
 
@@ -215,7 +222,7 @@ template <typename T, class Sh>
 hipError_t launch_imatrix(const ImArgs<T, Sh>& a, int ncols, int nb, double* out, hipStream_t st);
 template <typename T, class Sh> int imatrix_blocks_per_cu(int ncols);
 template <typename T, class Sh> hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st);
-template <typename T, class Sh> int amp_blocks_per_cu(int mode, bool cc);
+template <typename T, class Sh> int amp_blocks_per_cu(int mode, bool cc, bool zfree);
 // Fixed-order sums of the block partials of records first_set .. first_set + n_sets - 1 into
 // out[set * NACC + v] (record 0: data blocks; records 1 .. n_mc_sets: runs of nb_mc
 // normalisation blocks).

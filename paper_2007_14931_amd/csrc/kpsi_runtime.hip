@@ -81,6 +81,7 @@ struct kpsi_ctx {
   int cnt[6] = {0, 0, 0, 0, 0, 0};
   int nparams = 0;
   bool has_z = false;
+  bool zfree = false;   // the model's one Z has independent H'_{+1}, H'_{-1}
   std::vector<int> fslot;       // table index -> floating slot or -1
   DevSet set[2];
   void* eps = nullptr;          // T array over the normalisation set, or null (flat): the
@@ -130,7 +131,8 @@ struct kpsi_ctx {
   double bench_ms = 0.0;          // their duration per launch
   int ept_override = 0;
   int n_cu = 0;                                                   // compute units of the device
-  int blocks_per_cu[2][3][2] = {{{-1, -1}, {-1, -1}, {-1, -1}}, {{-1, -1}, {-1, -1}, {-1, -1}}};   // [shape][mode][cc]
+  int blocks_per_cu[2][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+                                {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}};   // [shape][mode][cc / zfree]
   // interference-matrix cache of the normalisation sum (mode 0 off, 1 on, 2 auto)
   int cache_mode = 0;
   bool cache_valid = false;
@@ -171,7 +173,7 @@ size_t tsize(const kpsi_ctx* c) { return c->prec == KPSI_FP32 ? sizeof(float) : 
 
 int lowest_lb(const kpsi_resonance& r) { return r.chain == 0 ? (r.spin == 0 ? 1 : r.spin - 1) : 1; }
 int lowest_lr(const kpsi_resonance& r) { return r.chain == 0 ? r.spin : 0; }
-int ncoup(const kpsi_resonance& r) { return r.chain == 0 ? (r.spin == 0 ? 1 : 3) : 2; }
+int ncoup(const kpsi_resonance& r) { return r.chain == 0 ? (r.spin == 0 ? 1 : 3) : (r.hel_free ? 3 : 2); }
 
 // ---------------------------------------------------------------- lineshape constants
 // A(m) = K n(m) / (M^2 - m^2 - i P g(m)) reproduces Eq. (2)-(3) with the per-event
@@ -283,11 +285,13 @@ template <typename T, class Sh> void pack(const kpsi_ctx* c, const double* par, 
         rc.lhb = (T)(0.5 * r.lass_b);
       }
     } else {
-      for (int l = 0; l < 2; ++l) { hr[l] = p[2 * l] * std::cos(p[2 * l + 1]); hi[l] = p[2 * l] * std::sin(p[2 * l + 1]); }
-      nl = 2;
+      // lambda' = 0, +1 (standing for +-1 through Eq. 11), and -1 when the helicities are free
+      nl = ncoup(r);
+      for (int l = 0; l < nl; ++l) { hr[l] = p[2 * l] * std::cos(p[2 * l + 1]); hi[l] = p[2 * l] * std::sin(p[2 * l + 1]); }
       fill_rc(a.zs[c->slot[i]], lc, hr, hi, nl, c->fslot[i]);
     }
   }
+  a.zfree = c->zfree ? 1 : 0;
   for (int j = 0; j < 6; ++j) a.cnt[j] = c->cnt[j];
   a.rR = (T)c->kin.r_r;
   a.rB = (T)c->kin.r_b;
@@ -331,8 +335,8 @@ template <typename T, class Sh>
 int pick_ept(kpsi_ctx* c, int mode, int64_t nd, int64_t nm) {
   if (c->ept_override > 0) return c->ept_override;
   const bool cc = c->cc_on && mode != MODE_DENSITY;
-  int& bpc = c->blocks_per_cu[c->shape][mode][cc ? 1 : 0];
-  if (bpc < 0) bpc = amp_blocks_per_cu<T, Sh>(mode, cc);
+  int& bpc = c->blocks_per_cu[c->shape][mode][cc ? 1 : (c->zfree ? 2 : 0)];
+  if (bpc < 0) bpc = amp_blocks_per_cu<T, Sh>(mode, cc, c->zfree);
   const int64_t cap = (int64_t)(c->n_cu > 0 ? c->n_cu : 256) * (bpc > 0 ? bpc : 3);
   auto blocks = [&](int64_t ept) {
     const int64_t ch = (int64_t)BLOCK * ept;
@@ -347,7 +351,7 @@ int pick_ept(kpsi_ctx* c, int mode, int64_t nd, int64_t nm) {
 kpsi_status derive_columns(kpsi_ctx* c, int s) {
   DevSet& d = c->set[s];
   if (d.n == 0 || !c->has_model) return KPSI_OK;
-  const int ncol = NCOL_KSTAR + (c->has_z ? NCOL_Z : 0);
+  const int ncol = NCOL_KSTAR + (c->has_z ? NCOL_Z : 0) + (c->zfree ? NCOL_ZFREE : 0);
   const int64_t ld = (d.n + 63) / 64 * 64;
   const size_t bytes = (size_t)ld * col_groups(ncol) * 4 * tsize(c);
   if (bytes > d.cols_cap) {
@@ -368,6 +372,7 @@ kpsi_status derive_columns(kpsi_ctx* c, int s) {
     a.mB = c->kin.m_b; a.mJ = c->kin.m_jpsi; a.mK = c->kin.m_k; a.mPi = c->kin.m_pi;
     a.rB = c->kin.r_b; a.rR = c->kin.r_r;
     a.with_z = c->has_z ? 1 : 0;
+    a.zfree = c->zfree ? 1 : 0;
     a.diag = nullptr;
     return launch_invariants<T>(a, c->stream);
   };
@@ -1005,15 +1010,18 @@ kpsi_status kpsi_set_model(kpsi_ctx* c, const kpsi_kinematics* kin, const kpsi_r
   if (!(k.m_b > k.m_jpsi + k.m_k + k.m_pi) || !(k.m_k > 0) || !(k.m_pi > 0) || !(k.m_jpsi > 0) || !(k.r_b >= 0) ||
       !(k.r_r >= 0))
     return fail(c, KPSI_E_ARG, "unphysical kinematics");
-  int counts[5] = {0, 0, 0, 0, 0}, nz = 0;
+  int counts[5] = {0, 0, 0, 0, 0}, nz = 0, nfree = 0;
   for (int i = 0; i < n_res; ++i) {
     const kpsi_resonance& r = res[i];
+    if (r.hel_free != 0 && r.hel_free != 1) return fail(c, KPSI_E_ARG, "resonance %d: hel_free must be 0 or 1", i);
+    if (r.chain == 0 && r.hel_free) return fail(c, KPSI_E_ARG, "resonance %d: hel_free applies to a Z only", i);
     if (r.chain == 0) {
       if (r.spin < 0 || r.spin > 4) return fail(c, KPSI_E_UNSUPPORTED, "K* spin %d not in 0..4", r.spin);
       counts[r.spin]++;
     } else if (r.chain == 1) {
       if (r.spin != 1 || r.parity != 1) return fail(c, KPSI_E_UNSUPPORTED, "only 1+ Z states are supported");
       nz++;
+      if (r.hel_free) nfree++;
     } else {
       return fail(c, KPSI_E_ARG, "resonance %d: chain must be 0 or 1", i);
     }
@@ -1028,6 +1036,10 @@ kpsi_status kpsi_set_model(kpsi_ctx* c, const kpsi_kinematics* kin, const kpsi_r
       return fail(c, KPSI_E_ARG, "resonance %d: shape must be 0 (Breit-Wigner) or 1 (LASS)", i);
     }
   }
+  if (nfree && nz != 1)
+    return fail(c, KPSI_E_UNSUPPORTED, "free Z helicity couplings need a model with exactly one Z (it has %d)", nz);
+  if (nfree && (c->cc_on || c->cache_mode != 0))
+    return fail(c, KPSI_E_UNSUPPORTED, "free Z helicity couplings: switch off flavour tags and the normalisation cache first");
   int shape = -1;
   const int small[5] = {0, 1, 0, 0, 0}, full[5] = {3, 3, 2, 1, 1};
   bool fits_small = nz == 0, fits_full = nz <= 2;
@@ -1045,6 +1057,7 @@ kpsi_status kpsi_set_model(kpsi_ctx* c, const kpsi_kinematics* kin, const kpsi_r
   shape_counts(shape, N, &NZ);
   int used[5] = {0, 0, 0, 0, 0}, zused = 0, off = 0;
   c->has_z = false;
+  c->zfree = nfree > 0;
   for (int i = 0; i < n_res; ++i) {
     const kpsi_resonance& r = res[i];
     c->coff[i] = off;
@@ -1184,6 +1197,7 @@ kpsi_status kpsi_set_flavour(kpsi_ctx* c, const double* tags, int64_t n, double 
   invalidate_cache(c);
   if (!tags) return KPSI_OK;   // B0 only
   if (c->bkg_on) return fail(c, KPSI_E_UNSUPPORTED, "the background mixture and flavour tags cannot be combined");
+  if (c->zfree) return fail(c, KPSI_E_UNSUPPORTED, "flavour tags with free Z helicity couplings are not supported");
   if (n != c->set[0].n || n <= 0) return fail(c, KPSI_E_ARG, "expected %lld tags (one per data event)", (long long)c->set[0].n);
   if (!(mistag >= 0.0 && mistag <= 0.5)) return fail(c, KPSI_E_ARG, "mistag %g outside [0, 1/2]", mistag);
   int64_t np = 0, nn = 0;
@@ -1746,6 +1760,7 @@ kpsi_status kpsi_generate_model(kpsi_ctx* c, const double* params, uint64_t seed
     ia.mB = c->kin.m_b; ia.mJ = c->kin.m_jpsi; ia.mK = c->kin.m_k; ia.mPi = c->kin.m_pi;
     ia.rB = c->kin.r_b; ia.rR = c->kin.r_r;
     ia.with_z = c->has_z ? 1 : 0;
+    ia.zfree = c->zfree ? 1 : 0;
     if (e == hipSuccess) e = launch_invariants<double>(ia, c->stream);
     if (e != hipSuccess) { st = fail(c, KPSI_E_HIP, "generator: %s", hipGetErrorString(e)); break; }
     // density of the proposals through the FP64 amplitude kernel
@@ -2102,6 +2117,8 @@ kpsi_status kpsi_set_efficiency_mlp(kpsi_ctx* c, const float* params) {
 kpsi_status kpsi_set_norm_cache(kpsi_ctx* c, int mode) {
   if (!c) return KPSI_E_ARG;
   if (mode < 0 || mode > 2) return fail(c, KPSI_E_ARG, "cache mode must be 0, 1 or 2");
+  if (mode != 0 && c->zfree)
+    return fail(c, KPSI_E_UNSUPPORTED, "the interference-matrix cache does not cover free Z helicity couplings");
   c->cache_mode = mode;
   invalidate_cache(c);
   return KPSI_OK;
@@ -2119,6 +2136,7 @@ kpsi_status kpsi_fit_fractions(kpsi_ctx* c, const double* params, double* ff, do
   if (!c) return KPSI_E_ARG;
   if (!params || !ff) return fail(c, KPSI_E_ARG, "NULL argument");
   if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set");
+  if (c->zfree) return fail(c, KPSI_E_UNSUPPORTED, "fit fractions with free Z helicity couplings are not supported");
   if (c->set[1].n <= 0) return fail(c, KPSI_E_STATE, "no normalisation events loaded");
   for (int i = 0; i < c->nparams; ++i)
     if (!std::isfinite(params[i])) return fail(c, KPSI_E_ARG, "parameter %d is not finite", i);

@@ -48,7 +48,7 @@ class Kinematics(C.Structure):
 class Resonance(C.Structure):
     _fields_ = [("chain", C.c_int), ("spin", C.c_int), ("parity", C.c_int), ("lb", C.c_int), ("lr", C.c_int),
                 ("mass", C.c_double), ("width", C.c_double), ("shape", C.c_int), ("lass_a", C.c_double),
-                ("lass_b", C.c_double)]
+                ("lass_b", C.c_double), ("hel_free", C.c_int)]
 
 
 class FitOptions(C.Structure):
@@ -162,7 +162,8 @@ def kinematics(d: dict) -> Kinematics:
 def resonances(res) -> C.Array:
     arr = (Resonance * len(res))()
     for i, r in enumerate(res):
-        arr[i] = Resonance(r.chain, r.spin, r.parity, r.lb, r.lr, r.mass, r.width, r.shape, r.lass_a, r.lass_b)
+        arr[i] = Resonance(r.chain, r.spin, r.parity, r.lb, r.lr, r.mass, r.width, r.shape, r.lass_a, r.lass_b,
+                           int(getattr(r, "hel_free", False)))
     return arr
 
 

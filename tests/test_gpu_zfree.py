@@ -1,0 +1,145 @@
+"""Z helicity couplings free of the parity relation (hel_free), through the C ABI, against the
+FP64 oracle.
+
+The Discussion states that the Z part can be fitted with its couplings unconstrained; with
+hel_free the one Z of the model carries H'_0, H'_{+1} and H'_{-1} as independent couplings
+instead of H'_{-1} = H'_{+1} (Eq. 11 for a 1+ state).  Checked here:
+
+* per-event densities, the NLL and its gradient (every coupling, and the floating masses and
+  widths of K*(1410) and the Z) at H'_{-1} != H'_{+1}, at sizes spanning several blocks with
+  ragged tails, on both precisions, at the parity bars of the other tests;
+* at H'_{-1} = H'_{+1} the free model is the constrained one: the same NLL, and the constrained
+  gradient of H'_{+1} is the sum of the free gradients of H'_{+1} and H'_{-1} (magnitude and
+  phase, by the chain rule);
+* the accept-reject generator draws the oracle's sample from the free model;
+* the calls that do not cover free helicities refuse them.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2007_14931_amd import kpsi
+from paper_2007_14931_amd import workloads as W
+from parity_bars import check_grad, check_nll
+
+K = W.KIN
+pytestmark = pytest.mark.gpu
+FLOAT = ("K*(1410)", "Z(4430)")
+
+
+def _sets(nd, nm, seed):
+    data = W.neutral_events(nd, seed, peaked=True)
+    data[0] = np.clip(data[0], W.M_LO + 1e-6, W.M_HI - 1e-6)
+    mc = O.gen_phsp(K, seed + 1, nm, W.PHSP_WMAX)
+    return data, mc
+
+
+def _engine(prec, res, data, mc):
+    e = kpsi.Engine(0, prec)
+    e.set_model(K, res)
+    e.set_floating([1 if r.name in FLOAT else 0 for r in res])
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    return e
+
+
+def _z_offset(res):
+    return W.coupling_offset(res, len(res) - 1)
+
+
+@pytest.mark.parametrize("prec,tg", [("fp64", 1e-9), ("fp32", None)])
+def test_free_helicity_likelihood_and_gradient_match_oracle(prec, tg):
+    print(f"[case] free Z helicities {prec}: 8191 data / 24593 normalisation events", flush=True)
+    res = W.model("full_zfree")
+    data, mc = _sets(8191, 24593, 301)
+    par = W.params(res, seed=303) + 0.04 * W.free_mask(res, FLOAT)
+    z = _z_offset(res)
+    assert W.n_params(res) == W.n_params(W.model("full")) + 2
+    assert abs(par[z + 2] - par[z + 4]) > 0.05           # H'_{+1} and H'_{-1} differ
+    e = _engine(prec, res, data, mc)
+    assert e.n_params == W.n_params(res)
+    dirs = np.flatnonzero(W.free_mask(res, FLOAT))
+    v, g = e.nll_and_grad(par)
+    st, ref, gref = O.nll(K, res, par, data, mc, dirs=dirs)
+    assert st == 0
+    check_nll(v, ref, prec, data.shape[1], "free Z")
+    check_grad(g[dirs], gref, prec, "free Z", norm=tg)
+    check_nll(e.nll(par), ref, prec, data.shape[1], "free Z nll-only")
+    # the three Z couplings' gradient entries, on their own
+    zk = np.searchsorted(dirs, np.arange(z, z + 6))
+    gz, gzr = g[dirs][zk], gref[zk]
+    print(f"[parity] free Z {prec} Z-coupling gradient {gz} oracle {gzr}", flush=True)
+    np.testing.assert_allclose(gz, gzr, rtol=1e-7 if prec == "fp64" else 2e-3,
+                               atol=(1e-9 if prec == "fp64" else 1e-6) * np.max(np.abs(gref)))
+    s = e.density(kpsi.NORM, par)[:4000]
+    o = O.density(K, res, par, mc[:, :4000])
+    rtol = 1e-11 if prec == "fp64" else 2e-5
+    np.testing.assert_allclose(s, o, rtol=rtol, atol=rtol * 0.1 * o.max())
+    e.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_free_helicities_at_the_parity_relation_are_the_constrained_model(prec):
+    res_c, res_f = W.model("full"), W.model("full_zfree")
+    data, mc = _sets(4099, 12007, 311)
+    pc = W.params(res_c, seed=313)
+    z = _z_offset(res_c)
+    nc = sum(2 * r.n_coup for r in res_c)
+    pf = np.concatenate([pc[: z + 4], pc[z + 2: z + 4], pc[nc:]])   # H'_{-1} = H'_{+1}
+    ec, ef = _engine(prec, res_c, data, mc), _engine(prec, res_f, data, mc)
+    vc, gc = ec.nll_and_grad(pc)
+    vf, gf = ef.nll_and_grad(pf)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    print(f"[zfree] {prec} constrained {vc:.12g} free {vf:.12g}", flush=True)
+    assert abs(vf - vc) <= tol * max(abs(vc), 2.0 * data.shape[1])
+    # d/dH'_{+1} of the constrained model = d/dH'_{+1} + d/dH'_{-1} of the free one
+    comb = gf[z + 2: z + 4] + gf[z + 4: z + 6]
+    scale = np.max(np.abs(gc[np.isfinite(gc)]))
+    gtol = 1e-9 if prec == "fp64" else 2e-6
+    print(f"[zfree] {prec} H'+1 gradient constrained {gc[z + 2: z + 4]} free sum {comb}", flush=True)
+    np.testing.assert_allclose(comb, gc[z + 2: z + 4], atol=gtol * scale)
+    np.testing.assert_allclose(gf[: z + 2], gc[: z + 2], atol=gtol * scale)
+    np.testing.assert_allclose(gf[z + 6:][np.isfinite(gc[nc:])], gc[nc:][np.isfinite(gc[nc:])], atol=gtol * scale)
+    ec.close()
+    ef.close()
+
+
+def test_model_generator_with_free_helicities_agrees_with_oracle():
+    res = W.model("full_zfree")
+    e = kpsi.Engine(0, "fp64")
+    e.set_model(K, res)
+    par = W.params(res, seed=17)
+    coef = W.acceptance_coefficients()
+    ev, npr, nov = e.generate_model(par, 779, 3000, W.PHSP_WMAX, 400.0, coef)
+    ref, npr_o, nov_o = O.gen_model(K, res, par, 779, 3000, W.PHSP_WMAX, 400.0, coef)
+    ev = ev.cpu().numpy()
+    assert npr == npr_o
+    assert np.all(ev == ref, axis=0).mean() > 0.999
+    e.close()
+
+
+def test_calls_without_free_helicity_support_refuse_them():
+    res = W.model("full_zfree")
+    e = kpsi.Engine(0, "fp64")
+    e.set_model(K, res)
+    data, mc = _sets(500, 2000, 321)
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    par = W.params(res, seed=5)
+    with pytest.raises(kpsi.KpsiError):
+        e.set_flavour(np.ones(500))
+    with pytest.raises(kpsi.KpsiError):
+        e.set_norm_cache(1)
+    with pytest.raises(kpsi.KpsiError):
+        e.fit_fractions(par)
+    assert np.isfinite(e.nll(par))          # the context is still usable
+    # two Z with one free, and a free K*, are rejected by set_model
+    z2 = dataclasses.replace(W.Z4240)
+    with pytest.raises(kpsi.KpsiError):
+        e.set_model(K, res + [z2])
+    bad = [dataclasses.replace(W.KSTAR892, hel_free=True)]
+    with pytest.raises(kpsi.KpsiError):
+        e.set_model(K, bad)
+    e.close()
