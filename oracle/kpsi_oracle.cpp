@@ -654,6 +654,81 @@ int oracle_nll_cc(const oracle_kin* kin, const oracle_res* res, int n_res, const
   return 0;
 }
 
+// Flavour-tagged events with the signal + background mixture of Eq. 14.  Reading: the
+// background density b is the same for both flavours, and each flavour's PDF is normalised, so
+//   f(x, q) = p eps(x) [(1 - w) S(x^(q)) + w S(x^(-q))] / N_q + (1 - p) b(x) / N_b,
+// with N_q = (1 - w) I(q) + w I(-q), I(s) = (1/N_MC) sum_j eps_j S(y_j^(s)), N_b = (1/N_MC) sum_j b_j
+// (the mixture above for the signal part, the tagged form above for the flavours), and
+// NLL = -2 sum_i ln f(x_i, q_i).  eps_d / eps_m may be NULL (efficiency 1).  Returns 0, -1 on bad
+// arguments, or -5 when some f(x_i) <= 0 or a normalisation is not positive.
+int oracle_nll_cc_mix(const oracle_kin* kin, const oracle_res* res, int n_res, const double* par, int64_t nd,
+                      const double* dm, const double* dck, const double* dcj, const double* dphi, const double* tag,
+                      int64_t nm, const double* mm, const double* mck, const double* mcj, const double* mphi,
+                      const double* eps_d, const double* b_d, const double* eps_m, const double* b_m, double purity,
+                      double mistag, int n_dir, const int* dirs, double* nll, double* grad) {
+  Kin k = to_kin(kin);
+  std::vector<Res> rs = to_res(res, n_res);
+  const int np = n_full_params(rs);
+  if (nd <= 0 || nm <= 0 || !tag || !b_d || !b_m) return -1;
+  if (!(purity > 0.0 && purity <= 1.0) || !(mistag >= 0.0 && mistag <= 0.5)) return -1;
+  if (n_dir < 0 || n_dir > KD) return -1;
+  for (int d = 0; d < n_dir; ++d) if (dirs[d] < 0 || dirs[d] >= np) return -1;
+  for (int64_t i = 0; i < nd; ++i) if (tag[i] != 1.0 && tag[i] != -1.0) return -1;
+  bool hasZ = false;
+  for (auto& r : rs) hasZ |= (r.chain == 1);
+  g_nd = n_dir;
+  std::vector<Dual> P(np);
+  for (int i = 0; i < np; ++i) P[i] = Dual(par[i]);
+  for (int d = 0; d < n_dir; ++d) P[dirs[d]].d[d] = 1.0;
+  auto dens = [&](double m, double cK, double cJ, double ph) {
+    Event ev{m, cK, cJ, ph};
+    ZAng za{0, 0, 0, 0, 0};
+    if (hasZ) za = z_angles(k, ev.m, ev.cK, ev.cJ, ev.phi);
+    return density<Dual>(k, rs, P.data(), ev, za);
+  };
+  // I(+1), I(-1) and N_b over the phase-space events
+  KSum sI[2], sB;
+  std::vector<double> gI[2] = {std::vector<double>(n_dir, 0.0), std::vector<double>(n_dir, 0.0)};
+  for (int64_t j = 0; j < nm; ++j) {
+    const double e = eps_m ? eps_m[j] : 1.0;
+    for (int f = 0; f < 2; ++f) {
+      const Dual s = dens(mm[j], mck[j], mcj[j], f == 0 ? mphi[j] : -mphi[j]);
+      sI[f].add(e * s.v);
+      for (int d = 0; d < n_dir; ++d) gI[f][d] += e * s.d[d];
+    }
+    sB.add(b_m[j]);
+  }
+  const double NB = sB.get() / (double)nm;
+  if (!(NB > 0.0)) { *nll = INFINITY; return -5; }
+  double N[2], dN[2][KD];
+  for (int f = 0; f < 2; ++f) {
+    const double Iq = sI[f].get() / (double)nm, Io = sI[1 - f].get() / (double)nm;
+    N[f] = (1.0 - mistag) * Iq + mistag * Io;
+    for (int d = 0; d < n_dir; ++d) dN[f][d] = ((1.0 - mistag) * gI[f][d] + mistag * gI[1 - f][d]) / (double)nm;
+    if (!(N[f] > 0.0)) { *nll = INFINITY; return -5; }
+  }
+  KSum L;
+  std::vector<double> gL(n_dir, 0.0);
+  for (int64_t i = 0; i < nd; ++i) {
+    const int f = tag[i] > 0.0 ? 0 : 1;
+    const double ph = dphi[i];
+    const Dual s_same = dens(dm[i], dck[i], dcj[i], f == 0 ? ph : -ph);
+    const Dual s_other = dens(dm[i], dck[i], dcj[i], f == 0 ? -ph : ph);
+    const double e = eps_d ? eps_d[i] : 1.0;
+    const double sig = (1.0 - mistag) * s_same.v + mistag * s_other.v;
+    const double fi = purity * e * sig / N[f] + (1.0 - purity) * b_d[i] / NB;
+    if (!(fi > 0.0) || !std::isfinite(fi)) { *nll = INFINITY; return -5; }
+    L.add(std::log(fi));
+    for (int d = 0; d < n_dir; ++d) {
+      const double dsig = (1.0 - mistag) * s_same.d[d] + mistag * s_other.d[d];
+      gL[d] += purity * e * (dsig / N[f] - sig * dN[f][d] / (N[f] * N[f])) / fi;
+    }
+  }
+  *nll = -2.0 * L.get();
+  for (int d = 0; d < n_dir; ++d) grad[d] = -2.0 * gL[d];
+  return 0;
+}
+
 // -2 ln L of the signal PDF eps*S normalised by the phase-space MC sum (Eq. 14 with
 // purity 1):  NLL = -2 sum_i ln S(x_i) + 2 N_d ln( (1/N_MC) sum_j eps_j S(y_j) ).
 // Parameter-independent terms (ln eps(x_i), phase-space factor, volume) are dropped.

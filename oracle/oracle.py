@@ -335,6 +335,32 @@ def nll_cc(kind: dict, res, par, data, tag, mc, mistag: float, eps_mc=None, dirs
     return st, out.value, (g[: len(dirs_arr)] if len(dirs_arr) else None)
 
 
+def nll_cc_mix(kind: dict, res, par, data, tag, mc, mistag: float, b_data, b_mc, purity: float, eps_data=None,
+               eps_mc=None, dirs=None):
+    """-2 ln L of flavour-tagged events with the Eq. 14 background mixture:
+    f = p eps [(1-w) S(x^q) + w S(x^-q)] / N_q + (1 - p) b / N_b.  Returns (status, nll, grad or None)."""
+    par = _f64(par)
+    dcols = [_f64(data[i]) for i in range(4)]
+    mcols = [_f64(mc[i]) for i in range(4)]
+    tg, bd, bm = _f64(tag), _f64(b_data), _f64(b_mc)
+    ed = _f64(eps_data) if eps_data is not None else None
+    em = _f64(eps_mc) if eps_mc is not None else None
+    dirs_arr = np.ascontiguousarray(dirs if dirs is not None else [], dtype=np.int32)
+    out = C.c_double(0.0)
+    g = np.zeros(max(1, len(dirs_arr)))
+    k = kin(kind)
+    f = lib().oracle_nll_cc_mix
+    dp = C.POINTER(C.c_double)
+    f.argtypes = [C.POINTER(Kin), C.POINTER(Res), C.c_int, dp, C.c_int64, dp, dp, dp, dp, dp, C.c_int64, dp, dp, dp,
+                  dp, dp, dp, dp, dp, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int), dp, dp]
+    f.restype = C.c_int
+    st = f(C.byref(k), res_array(res), len(res), _dp(par), dcols[0].size, *(_dp(c) for c in dcols), _dp(tg),
+           mcols[0].size, *(_dp(c) for c in mcols), _dp(ed) if ed is not None else None, _dp(bd),
+           _dp(em) if em is not None else None, _dp(bm), C.c_double(purity), C.c_double(mistag),
+           len(dirs_arr), dirs_arr.ctypes.data_as(C.POINTER(C.c_int)), C.byref(out), _dp(g))
+    return st, out.value, (g[: len(dirs_arr)] if len(dirs_arr) else None)
+
+
 def gauss_penalty(idx, mean, sigma, par):
     """Gaussian constraints: (sum_k ((p[idx_k] - mean_k)/sigma_k)^2, its gradient over par)."""
     par = _f64(par)

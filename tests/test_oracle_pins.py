@@ -972,6 +972,60 @@ def test_cc_gradient_matches_central_differences():
         assert g[5 * k] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(g).max())
 
 
+def _cc_mix_inputs(n_d=300, n_m=1500):
+    res, par, data, mc, eps_m, tag = _cc_inputs(n_d, n_m)
+    rng = np.random.default_rng(65)
+    eps_d = O.acceptance(W.acceptance_coefficients(), W.M_LO, W.M_HI, data)
+    return res, par, data, mc, eps_m, tag, eps_d, rng.uniform(0.2, 1.5, n_d), rng.uniform(0.2, 1.5, n_m)
+
+
+def test_cc_mixture_at_full_purity_is_the_tagged_signal_likelihood():
+    # p = 1: f = eps S~/N_q, i.e. the tagged likelihood with the data efficiencies' -2 sum ln eps_i
+    res, par, data, mc, eps_m, tag, eps_d, b_d, b_m = _cc_mix_inputs()
+    dirs = np.flatnonzero(W.free_mask(res, ("K*(1410)", "Z(4430)")))
+    st, v, g = O.nll_cc_mix(K, res, par, data, tag, mc, 0.07, b_d, b_m, 1.0, eps_d, eps_m, dirs)
+    st2, v2, g2 = O.nll_cc(K, res, par, data, tag, mc, 0.07, eps_m, dirs)
+    assert st == 0 and st2 == 0
+    assert v == pytest.approx(v2 - 2.0 * np.sum(np.log(eps_d)), rel=1e-13)
+    np.testing.assert_allclose(g, g2, rtol=1e-11, atol=1e-11 * np.abs(g2).max())
+
+
+@pytest.mark.parametrize("purity", [0.3, 0.85])
+def test_cc_mixture_with_b0_tags_and_no_mistag_is_the_untagged_mixture(purity):
+    res, par, data, mc, eps_m, _, eps_d, b_d, b_m = _cc_mix_inputs()
+    dirs = np.flatnonzero(W.free_mask(res, ("K*(1410)", "Z(4430)")))
+    ones = np.ones(data.shape[1])
+    st, v, g = O.nll_cc_mix(K, res, par, data, ones, mc, 0.0, b_d, b_m, purity, eps_d, eps_m, dirs)
+    st2, v2, g2 = O.nll_mix(K, res, par, data, mc, b_d, b_m, purity, eps_d, eps_m, dirs)
+    assert st == 0 and st2 == 0
+    assert v == pytest.approx(v2, rel=1e-13)
+    np.testing.assert_allclose(g, g2, rtol=1e-11, atol=1e-11 * np.abs(g2).max())
+
+
+def test_cc_mixture_is_invariant_under_mirroring_and_ignores_tags_at_half_mistag():
+    res, par, data, mc, eps_m, tag, eps_d, b_d, b_m = _cc_mix_inputs()
+    _, v, _ = O.nll_cc_mix(K, res, par, data, tag, mc, 0.07, b_d, b_m, 0.6, eps_d, eps_m)
+    _, v2, _ = O.nll_cc_mix(K, res, par, _mirror(data), -tag, _mirror(mc), 0.07, b_d, b_m, 0.6, eps_d, eps_m)
+    assert v == pytest.approx(v2, rel=1e-13)
+    _, h, _ = O.nll_cc_mix(K, res, par, data, tag, mc, 0.5, b_d, b_m, 0.6, eps_d, eps_m)
+    _, h2, _ = O.nll_cc_mix(K, res, par, data, -tag, mc, 0.5, b_d, b_m, 0.6, eps_d, eps_m)
+    assert h == pytest.approx(h2, rel=1e-13) and abs(h - v) > 1e-3
+
+
+def test_cc_mixture_gradient_matches_central_differences():
+    res, par, data, mc, eps_m, tag, eps_d, b_d, b_m = _cc_mix_inputs(120, 600)
+    dirs = np.flatnonzero(W.free_mask(res, ("K*(1410)", "Z(4430)")))
+    args = (0.06, b_d, b_m, 0.7, eps_d, eps_m)
+    _, v, g = O.nll_cc_mix(K, res, par, data, tag, mc, *args, dirs)
+    for k, i in enumerate(dirs[::5]):
+        h = 1e-6 * max(1.0, abs(par[i]))
+        pp, pm = par.copy(), par.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (O.nll_cc_mix(K, res, pp, data, tag, mc, *args)[1] - O.nll_cc_mix(K, res, pm, data, tag, mc, *args)[1]) / (2 * h)
+        assert g[5 * k] == pytest.approx(fd, rel=1e-5, abs=1e-6 * np.abs(g).max())
+
+
 # ---------------------------------------------------------------- Gaussian constraints
 def test_gauss_penalty_is_minus_two_log_of_the_normal_density():
     # a Gaussian factor N(p; mu, sigma) in the likelihood adds -2 ln N - ln(2 pi sigma^2) = z^2
