@@ -234,7 +234,9 @@ def extension_legs(stream, data, mc, par, res, floating, steps: int = 1000, warm
     normalisation events, FP32): the signal + background mixture of Eq. 14 with per-event
     efficiency and background values, flavour-tagged events with mistag (the normalisation
     events evaluated at phi and -phi), and the LASS S-wave model (LASS + 8 K* + two Z, the
-    K*(1410) and Z(4430) lineshapes floating)."""
+    K*(1410) and Z(4430) lineshapes floating), and the model whose Z has independent H'_{+1}
+    and H'_{-1}.  The flavour-tagged and untagged calls are also timed with the
+    interference-matrix cache (only the data events evaluated per call)."""
     import torch
     from paper_2007_14931_amd import kpsi
     from paper_2007_14931_amd import workloads as W
@@ -256,6 +258,17 @@ def extension_legs(stream, data, mc, par, res, floating, steps: int = 1000, warm
         return {"ms_per_step": ms, "evals_per_s": 1e3 / ms, "kernel_ms": leg["kernel_ms_mean"],
                 "kernel_ms_median": leg["kernel_ms_median"]}
 
+    def cached_rate(e, p, n=1000):
+        # calls at the lineshape point of the built matrices (the couplings move in a fit)
+        for _ in range(100):
+            e.nll_and_grad(p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            e.nll_and_grad(p)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n * 1e3
+
     out = {}
     e = kpsi.Engine(0, "fp32", stream)
     e.set_model(W.KIN, res)
@@ -275,6 +288,32 @@ def extension_legs(stream, data, mc, par, res, floating, steps: int = 1000, warm
     e.set_efficiency_values(eps_m)
     e.set_flavour(np.where(rng.random(nd) < 0.5, 1.0, -1.0), 0.05)
     out["flavour_tags"] = {"model": "10 K* + Z(4430)", "mistag": 0.05, **timed(e, par)}
+    # the same with the interference-matrix cache: both flavours' normalisations come from the
+    # +phi matrices, so a call evaluates only the data events (each at q phi and -q phi)
+    e.set_norm_cache(1)
+    e.nll_and_grad(par)
+    out["flavour_tags"]["cached_ms_per_step"] = cached_rate(e, par)
+    e.close()
+    # the same events without tags, cached, for the ratio
+    e = kpsi.Engine(0, "fp32", stream)
+    e.set_model(W.KIN, res)
+    e.set_floating([1 if r.name in floating else 0 for r in res])
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    e.set_efficiency_values(eps_m)
+    e.set_norm_cache(1)
+    e.nll_and_grad(par)
+    out["flavour_tags"]["untagged_cached_ms_per_step"] = cached_rate(e, par)
+    e.close()
+    # Z(4430) with H'_{+1} and H'_{-1} independent (no Eq. 11 relation)
+    fres = W.model("full_zfree")
+    fpar = W.params(fres, 37) + 0.05 * W.free_mask(fres, floating)
+    e = kpsi.Engine(0, "fp32", stream)
+    e.set_model(W.KIN, fres)
+    e.set_floating([1 if r.name in floating else 0 for r in fres])
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    out["free_z_helicities"] = {"model": "10 K* + Z(4430), H'+1 and H'-1 free", **timed(e, fpar)}
     e.close()
     lres = W.model("lass_full2z")
     lfl = ("K*(1410)", "Z(4430)")

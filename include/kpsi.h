@@ -326,9 +326,15 @@ kpsi_status kpsi_set_background(kpsi_ctx* ctx, double purity, const double* eps_
  *   tags:   n doubles (host, copied), n = the number of loaded data events; NULL switches the
  *           tags off (every event a B0).
  *   mistag: w in [0, 1/2].
+ * Together with the background mixture (kpsi_set_background), the background density is the
+ * same for both flavours and each flavour's PDF is normalised:
+ *   f(x, q) = p eps(x) [(1 - w) S(x^(q)) + w S(x^(-q))] / N_q + (1 - p) b(x) / N_b,
+ *   -2 ln L = -2 sum_i ln(p eps_i [(1 - w) S(x_i^(q_i)) + w S(x_i^(-q_i))] + (1 - p)(N_q / N_b) b_i)
+ *             + 2 sum_q n_q ln N_q
+ * (the data efficiencies enter here, as in the untagged mixture).  Each call then evaluates
+ * the normalisation events at +phi and -phi first, or takes both from the interference matrix.
  * Loading data events drops the tags.  Errors: KPSI_E_ARG for a wrong count, a tag other than
- * +-1 or w outside [0, 1/2]; KPSI_E_UNSUPPORTED while the background mixture is set (and
- * kpsi_set_background returns it while tags are set). */
+ * +-1 or w outside [0, 1/2]; KPSI_E_UNSUPPORTED with free Z helicity couplings. */
 kpsi_status kpsi_set_flavour(kpsi_ctx* ctx, const double* tags, int64_t n, double mistag);
 
 /* ---------------------------------------------------------------- Gaussian constraints

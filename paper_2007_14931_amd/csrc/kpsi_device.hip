@@ -311,7 +311,8 @@ template <class Sh> __host__ __device__ constexpr int acc_base(int J) {   // acc
 
 // Accumulator indices (per block record of NACC doubles):
 //   0, 1 : main sum and its (negated Kahan) compensation, total = [0] + [1]
-//          (data: sum ln S; norm: sum eps S)
+//          (data: sum ln S; norm: sum eps S).  Gradient mode, flavour tags with the Eq. 14
+//          mixture: data slot 0 is the whole sum and slot 1 the - flavour's sum of w S
 //   2    : number of data events with S <= 0 or non-finite
 //   then per K* slot (spin order) 2 (spin 0) or 6 (lambda = -1, 0, +1) values re/im of
 //   sum w * dS/dH' with H' = K H (before the factor 2), then per Z slot 4 values
@@ -354,36 +355,52 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
   float nbad = 0.f;   // events with a non-positive or non-finite density (exact count)
   // Eq. 14 mixture on the data set: background weight k from the reduced normalisation total
   const bool mix = (set == 0) && a.bkg_data != nullptr;
-  T kb = T(0);
+  T kb = T(0), kb2 = T(0);   // background weight k (flavour tags: of the + and - flavours)
   if (mix) {
-    double tot;
+    constexpr int NR = CC ? 2 : 1;   // normalisation records: phi (and -phi with tags)
+    double tot[2] = {0.0, 0.0};
     if (a.mc_part) {
       // sum eps S over the normalisation blocks in a fixed order (the same in every block):
       // strided compensated sums per lane, a butterfly of exact two-sum merges in each
       // wavefront (both partners get the same result), then the four wavefronts in order
-      __shared__ double kred[4][2];
-      double s = 0.0, c = 0.0;
-      for (int b = threadIdx.x; b < a.mc_nb; b += 256) {
-        neumaier(s, c, a.mc_part[b]);
-        neumaier(s, c, a.mc_part[a.pstride + b]);   // value 1: the Kahan correction
-      }
+      __shared__ double kred[4][2 * NR];
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) two_sum_merge(s, c, __shfl_xor(s, off, 64), __shfl_xor(c, off, 64));
-      if ((threadIdx.x & 63) == 0) {
-        kred[threadIdx.x >> 6][0] = s;
-        kred[threadIdx.x >> 6][1] = c;
+      for (int r = 0; r < NR; ++r) {
+        double s = 0.0, c = 0.0;
+        const double* mp = a.mc_part + r * a.mc_nb;
+        for (int b = threadIdx.x; b < a.mc_nb; b += 256) {
+          neumaier(s, c, mp[b]);
+          neumaier(s, c, mp[a.pstride + b]);   // value 1: the Kahan correction
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) two_sum_merge(s, c, __shfl_xor(s, off, 64), __shfl_xor(c, off, 64));
+        if ((threadIdx.x & 63) == 0) {
+          kred[threadIdx.x >> 6][2 * r] = s;
+          kred[threadIdx.x >> 6][2 * r + 1] = c;
+        }
       }
       __syncthreads();
-      s = kred[0][0];
-      c = kred[0][1];
-      for (int w = 1; w < 4; ++w) two_sum_merge(s, c, kred[w][0], kred[w][1]);
-      tot = s + c;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        double s = kred[0][2 * r], c = kred[0][2 * r + 1];
+        for (int w = 1; w < 4; ++w) two_sum_merge(s, c, kred[w][2 * r], kred[w][2 * r + 1]);
+        tot[r] = s + c;
+      }
     } else {
-      tot = a.norm_total[0] + a.norm_total[1];
+      tot[0] = a.norm_total[0] + a.norm_total[1];
+      if (CC) tot[1] = a.norm_total[NACC] + a.norm_total[NACC + 1];
     }
-    kb = (T)(a.bkg_coef * tot);
+    if constexpr (CC) {
+      // N_q = (1 - w) I(q) + w I(-q) for the event's flavour q
+      const double wm = (double)a.mistag, kp = 1.0 - wm;
+      kb = (T)(a.bkg_coef * (kp * tot[0] + wm * tot[1]));
+      kb2 = (T)(a.bkg_coef * (kp * tot[1] + wm * tot[0]));
+    } else {
+      kb = (T)(a.bkg_coef * tot[0]);
+    }
   }
-  A_t ws = A_t(0);   // sum_i w_i S_i (mixture, gradient mode)
+  A_t ws = A_t(0);    // sum_i w_i S_i (mixture, gradient mode; with tags: the + flavour's events)
+  A_t ws2 = A_t(0);   // with tags: the same over the - flavour's events
   // accumulators gk[LO, HI) live in this thread's LDS column accl[.][tid] (gradient kernel)
   constexpr bool LDSACC = GRAD && (Sh::LDS_HI > Sh::LDS_LO);
   constexpr int LO = LDSACC ? Sh::LDS_LO : 0, HI = LDSACC ? Sh::LDS_HI : 0;
@@ -606,21 +623,35 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     if (set == 0) {
       T arg = S;   // the quantity whose logarithm is summed
       if constexpr (CC) {
+        T S2 = T(0);
         if (a.mistag > T(0)) {
           // t = (1 - w) S(q phi) + w S(-q phi)
           kstar_at(-f1, ap2, am2);
           if constexpr (NZ > 0) {
             if (a.cnt[5] > 0) z_add(-f1, T0k, T1k, T1k, ap2, am2);   // (no third sum: ZF excludes CC)
           }
-          const T S2 = ap2.re * ap2.re + ap2.im * ap2.im + am2.re * am2.re + am2.im * am2.im;
+          S2 = ap2.re * ap2.re + ap2.im * ap2.im + am2.re * am2.re + am2.im * am2.im;
           arg = fma_(a.keep, S, a.mistag * S2);
-          if (!(arg > pos_floor<T>()) || !(arg < T(INFINITY))) { nbad += 1.f; continue; }
-          const T r = rcp_(arg);
+        }
+        // Eq. 14 with tags: t = p eps [(1 - w) S(q phi) + w S(-q phi)] + k_q b, k_q of the
+        // event's flavour; d ln t / dS = p eps (1 - w) / t
+        T pe = T(1);
+        if (mix) {
+          pe = a.purity * (a.eps_data ? ldoff(a.eps_data + e0, ob) : T(1));
+          arg = fma_(pe, arg, (f1 > T(0) ? kb : kb2) * ldoff(a.bkg_data + e0, ob));
+        }
+        if (!(arg > pos_floor<T>()) || !(arg < T(INFINITY))) { nbad += 1.f; continue; }
+        const T r = pe * rcp_(arg);
+        if (a.mistag > T(0)) {
           w = a.keep * r;
           w2 = a.mistag * r;
         } else {
-          if (!(S > pos_floor<T>()) || !(S < T(INFINITY))) { nbad += 1.f; continue; }
-          w = rcp_(S);
+          w = r;
+        }
+        if (mix) {
+          const A_t c = (A_t)fma_(w, S, w2 * S2);
+          if (f1 > T(0)) ws += c;
+          else ws2 += c;
         }
       } else if (mix) {
         // Eq. 14: t = p eps S + k b; d ln t / dS = p eps / t
@@ -811,6 +842,14 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     // row permutations (dpp_partner).  Slots 0 and 1 carry the FP64 likelihood sums and every value merged into
     // them (as double); the other slots move the accumulators at their own type (FP32 sums of
     // the wave's FP32 thread accumulators in the FP32 kernel).
+    if constexpr (CC) {
+      // tagged mixture: slot 1 carries the - flavour's sum of w S (the Kahan correction is
+      // folded into slot 0 first)
+      if (mix) {
+        ms = ms - mc;
+        mc = -(double)ws2;
+      }
+    }
     double d[2];
     A_t v[32];
 #pragma unroll

@@ -102,7 +102,7 @@ struct kpsi_ctx {
   double* red = nullptr;        // device view of red_host
   double* red_host = nullptr;   // [3][NACC], mapped pinned host memory: data, normalisation,
                                 // and the normalisation read with phi reversed (flavour tags)
-  double* red_dev = nullptr;    // [2][NACC] device copy of the normalisation record (mixture)
+  double* red_dev = nullptr;    // [3][NACC] device copy of the normalisation records 1, 2 (mixture)
   // Gaussian constraints on parameters (kpsi_set_constraints): position, mean, sigma
   std::vector<int> con_idx;
   std::vector<double> con_mean, con_sigma;
@@ -726,9 +726,13 @@ kpsi_status put_cached_record(kpsi_ctx* c, const double* params) {
       std::swap(r2[3 + 2 * k0 + 1], r2[3 + 2 * (k0 + 2) + 1]);
     }
   }
-  if (c->bkg_on)
+  if (c->bkg_on) {
     HIPCHECK(c, hipMemcpyAsync(c->red_dev + NACC, c->red_host + NACC, 2 * sizeof(double), hipMemcpyHostToDevice,
                                c->stream));
+    if (c->cc_on)
+      HIPCHECK(c, hipMemcpyAsync(c->red_dev + 2 * NACC, c->red_host + 2 * NACC, 2 * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream));
+  }
   return KPSI_OK;
 }
 
@@ -808,7 +812,7 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
     // Eq. 14: the data terms need the normalisation total, so the normalisation events run in
     // a launch of their own first, and the data launch sums their block partials (unless the
     // normalisation record comes from the interference matrix and is already in red_dev)
-    chunk_m = BLOCK * pick_ept<T, Sh>(c, mode, 0, nm);
+    chunk_m = BLOCK * pick_ept<T, Sh>(c, mode, 0, nmsets * nm);
     chunk_d = BLOCK * pick_ept<T, Sh>(c, mode, nd, 0);
   }
   const int nbd = (int)((nd + chunk_d - 1) / chunk_d), nbm = (int)((nm + chunk_m - 1) / chunk_m);
@@ -851,7 +855,7 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
       b.chunk = chunk_m;
       b.nb_data = 0;
       b.poff = nbd;
-      st = launch(b, nbm);
+      st = launch(b, nmsets * nbm);   // with tags: records 1 (phi) and 2 (-phi)
     }
     if (!st && nd > 0) {
       AmpArgs<T, Sh> b = a;
@@ -964,7 +968,7 @@ kpsi_status kpsi_create(int device, void* stream, kpsi_precision prec, kpsi_ctx*
   }
   if (hipHostMalloc(&c->red_host, 3 * NACC * sizeof(double), hipHostMallocMapped) != hipSuccess ||
       hipHostGetDevicePointer((void**)&c->red, c->red_host, 0) != hipSuccess ||
-      hipMalloc(&c->red_dev, 2 * NACC * sizeof(double)) != hipSuccess) {
+      hipMalloc(&c->red_dev, 3 * NACC * sizeof(double)) != hipSuccess) {
     kpsi_destroy(c);
     return fail(nullptr, KPSI_E_OOM, "result buffers");
   }
@@ -1159,7 +1163,6 @@ kpsi_status kpsi_set_background(kpsi_ctx* c, double purity, const double* eps_da
   hipSetDevice(c->device);
   drop_background(c);
   if (!b_data) return KPSI_OK;   // signal-only likelihood
-  if (c->cc_on) return fail(c, KPSI_E_UNSUPPORTED, "the background mixture and flavour tags cannot be combined");
   if (!b_norm) return fail(c, KPSI_E_ARG, "b_norm is NULL");
   if (!(purity > 0.0 && purity <= 1.0)) return fail(c, KPSI_E_ARG, "purity %g outside (0, 1]", purity);
   const int64_t nd = c->set[0].n, nm = c->set[1].n;
@@ -1196,7 +1199,6 @@ kpsi_status kpsi_set_flavour(kpsi_ctx* c, const double* tags, int64_t n, double 
   drop_flavour(c);
   invalidate_cache(c);
   if (!tags) return KPSI_OK;   // B0 only
-  if (c->bkg_on) return fail(c, KPSI_E_UNSUPPORTED, "the background mixture and flavour tags cannot be combined");
   if (c->zfree) return fail(c, KPSI_E_UNSUPPORTED, "flavour tags with free Z helicity couplings are not supported");
   if (n != c->set[0].n || n <= 0) return fail(c, KPSI_E_ARG, "expected %lld tags (one per data event)", (long long)c->set[0].n);
   if (!(mistag >= 0.0 && mistag <= 0.5)) return fail(c, KPSI_E_ARG, "mistag %g outside [0, 1/2]", mistag);
@@ -1460,7 +1462,9 @@ kpsi_status kpsi_set_norm_mixture(kpsi_ctx* c, const double* params0, int64_t n_
 // gradient factor 2 W / sum eps S (W = N_d, or sum_i w_i S_i with the mixture).  Flavour
 // tags: 2 sum_q n_q ln N_q with N_q = (1 - w) I(q) + w I(-q), I(+) and I(-) from records 1
 // and 2.  Returns false when a normalisation is not positive (value then holds it).
-static bool norm_term(const kpsi_ctx* c, double wsum, double* value, double* c1, double* c2) {
+// wp, wn: the weights W of the data events (per flavour with tags): their count, or with the
+// Eq. 14 mixture sum_i w_i S_i over them.
+static bool norm_term(const kpsi_ctx* c, double wp, double wn, double* value, double* c1, double* c2) {
   const double* r1 = c->red_host + NACC;
   const double nd = (double)c->set[0].n, nm = (double)c->set[1].n;
   const double s1 = r1[0] + r1[1];
@@ -1468,7 +1472,7 @@ static bool norm_term(const kpsi_ctx* c, double wsum, double* value, double* c1,
     *value = s1;
     if (!(s1 > 0.0)) return false;
     *value = 2.0 * nd * std::log(s1 / nm);
-    *c1 = 2.0 * wsum / s1;
+    *c1 = 2.0 * wp / s1;
     *c2 = 0.0;
     return true;
   }
@@ -1479,8 +1483,8 @@ static bool norm_term(const kpsi_ctx* c, double wsum, double* value, double* c1,
   *value = Np < Nn ? Np : Nn;
   if (!(Np > 0.0) || !(Nn > 0.0)) return false;
   *value = 2.0 * ((np > 0.0 ? np * std::log(Np) : 0.0) + (nn > 0.0 ? nn * std::log(Nn) : 0.0));
-  *c1 = 2.0 / nm * (np * (1.0 - w) / Np + nn * w / Nn);
-  *c2 = 2.0 / nm * (np * w / Np + nn * (1.0 - w) / Nn);
+  *c1 = 2.0 / nm * (wp * (1.0 - w) / Np + wn * w / Nn);
+  *c2 = 2.0 / nm * (wp * w / Np + wn * (1.0 - w) / Nn);
   return true;
 }
 
@@ -1529,7 +1533,7 @@ kpsi_status kpsi_nll(kpsi_ctx* c, const double* params, double* nll) {
   const double* rd = c->red_host;
   const double nd = (double)c->set[0].n;
   double nt, c1, c2;
-  const bool ok = norm_term(c, nd, &nt, &c1, &c2);
+  const bool ok = norm_term(c, (double)c->ntag[0], (double)c->ntag[1], &nt, &c1, &c2);   // (value only)
   if (rd[2] > 0.0 || !ok) {
     *nll = INFINITY;
     return fail(c, KPSI_E_NONFINITE, "%.0f data events with non-positive density; normalisation %g", rd[2],
@@ -1554,15 +1558,20 @@ static kpsi_status assemble_grad(kpsi_ctx* c, const double* params, bool cached,
   shape_counts(c->shape, N, &NZ);
   int nkacc = 0;
   for (int j = 0; j < 5; ++j) nkacc += N[j] * (j == 0 ? 2 : 6);
-  const double wsum = c->bkg_on ? rd[3 + nkacc + 4 * NZ + 2 * NFL] : nd;
+  // W per flavour: the data counts, or with the mixture sum_i w_i S_i (the - flavour's in slot 1
+  // of the data record, whose log sum is then slot 0 alone)
+  const bool tagmix = c->bkg_on && c->cc_on;
+  double wp = c->cc_on ? (double)c->ntag[0] : nd, wn = (double)c->ntag[1];
+  if (c->bkg_on) wp = rd[3 + nkacc + 4 * NZ + 2 * NFL];
+  if (tagmix) wn = rd[1];
   double nt, fm, fm2;
-  const bool ok = norm_term(c, wsum, &nt, &fm, &fm2);
+  const bool ok = norm_term(c, wp, wn, &nt, &fm, &fm2);
   if (rd[2] > 0.0 || !ok) {
     *nll = INFINITY;
     return fail(c, KPSI_E_NONFINITE, "%.0f data events with non-positive density; normalisation %g", rd[2],
                 ok ? 1.0 : nt);
   }
-  *nll = -2.0 * (rd[0] + rd[1]) + nt;
+  *nll = -2.0 * (tagmix ? rd[0] : rd[0] + rd[1]) + nt;
   const int ncr = c->nparams - 2 * (int)c->res.size();
   for (size_t i = 0; i < c->res.size(); ++i) {
     const kpsi_resonance& r = c->res[i];

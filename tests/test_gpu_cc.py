@@ -1,7 +1,8 @@
 """Flavour-tagged charge-conjugate likelihood with mistag (text after Eq. 12) in the HIP path
 against the FP64 oracle: NLL and gradient for random tags with and without mistag, the
 normalisation served from the interference matrix, the tag independence at w = 1/2, the
-reduction to the B0 likelihood, and the error paths of kpsi_set_flavour."""
+reduction to the B0 likelihood, the tags together with the Eq. 14 background mixture (direct and
+cached normalisation), and the error paths of kpsi_set_flavour."""
 import numpy as np
 import pytest
 
@@ -124,8 +125,6 @@ def test_cc_errors_and_reload():
     with pytest.raises(kpsi.KpsiError):
         e.set_flavour(tag, 0.6)
     e.set_flavour(tag, 0.02)
-    with pytest.raises(kpsi.KpsiError):
-        e.set_background(0.9, None, np.ones(data.shape[1]), np.ones(mc.shape[1]))
     par = W.params(res, seed=87)
     _, ref, _ = O.nll_cc(K, res, par, data, tag, mc, 0.02, eps_m)
     assert e.nll(par) == pytest.approx(ref, rel=1e-10)
@@ -133,3 +132,45 @@ def test_cc_errors_and_reload():
     e.load(kpsi.DATA, data)
     _, ref0, _ = O.nll(K, res, par, data, mc, eps=eps_m)
     assert e.nll(par) == pytest.approx(ref0, rel=1e-10)
+
+
+@pytest.mark.parametrize("prec,w,cached,tg", [
+    ("fp64", 0.06, False, 1e-9), ("fp32", 0.06, False, None), ("fp64", 0.0, False, 1e-9),
+    ("fp64", 0.04, True, 1e-9), ("fp32", 0.04, True, None)])
+def test_cc_with_background_mixture_matches_oracle(prec, w, cached, tg):
+    """Tags and the Eq. 14 mixture together: one background density for both flavours, each
+    flavour normalised (f = p eps S~/N_q + (1 - p) b/N_b)."""
+    floating = ("K*(1410)", "Z(4430)")
+    res, data, mc, eps_m, tag = _inputs("full", 5003, 15013, seed=91)
+    nd, nm = data.shape[1], mc.shape[1]
+    rng = np.random.default_rng(92)
+    eps_d = O.acceptance(W.acceptance_coefficients(), W.M_LO, W.M_HI, data)
+    b_d, b_m = rng.uniform(0.2, 1.5, nd), rng.uniform(0.2, 1.5, nm)
+    e = _engine(prec, res, data, mc, eps_m, floating)
+    if cached:   # the other order of the two calls
+        e.set_background(0.8, eps_d, b_d, b_m)
+        e.set_flavour(tag, w)
+        e.set_norm_cache(1)
+    else:
+        e.set_flavour(tag, w)
+        e.set_background(0.8, eps_d, b_d, b_m)
+    par = W.params(res, seed=93) + 0.04 * W.free_mask(res, floating)
+    dirs = np.flatnonzero(W.free_mask(res, floating))
+    pts = [par]
+    if cached:
+        p2 = par.copy()
+        p2[2] += 0.07
+        p2[9] -= 0.05
+        pts.append(p2)
+    for k, p in enumerate(pts):
+        st, ref, gref = O.nll_cc_mix(K, res, p, data, tag, mc, w, b_d, b_m, 0.8, eps_d, eps_m, dirs)
+        assert st == 0
+        v, g = e.nll_and_grad(p)
+        label = f"cc+mixture w={w}{' cached' if cached else ''} point {k}"
+        check_nll(v, ref, prec, nd, label)
+        check_grad(g[dirs], gref, prec, label, norm=tg)
+        check_nll(e.nll(p), ref, prec, nd, label + " nll-only")
+    if cached:
+        b, h, _ = e.norm_cache_stats()
+        assert b == 1 and h >= 1
+    e.close()
