@@ -6,6 +6,7 @@
     python -m paper_2007_14931_amd.studies z_sensitivity # Z fit fractions: null test and positive control
     python -m paper_2007_14931_amd.studies real_life     # efficiency + 15% background (Eq. 14) vs ideal fit
     python -m paper_2007_14931_amd.studies flavour_tags  # B0 + conjugate decays, 5% mistag, tagged fit
+    python -m paper_2007_14931_amd.studies size_scan     # per-event kernel time against the event count
 
 Each prints one JSON line.  All events are synthetic, from the library's seeded generators:
 flat phase space, accept labels under the seeded analytic acceptance (the paper's
@@ -628,10 +629,58 @@ def flavour_tags(args) -> dict:
     return out
 
 
+def size_scan(args) -> dict:
+    """Kernel time of the FP32 likelihood-only and gradient passes (kpsi_time_kernel: medians of
+    five batches of 50 back-to-back launches) for 1/8 to 4 times the benchmark's 1e6 + 2e6 phase-
+    space events of the full model, and the rate a plain torch reduction reaches over the same
+    numbers of bytes (64 per event): where the record stops fitting the last-level cache."""
+    import torch
+    res = W.model("full")
+    fl = ("K*(1410)", "Z(4430)")
+    par = W.params(res, seed=11)
+    rows = []
+    for nd in (125_000, 250_000, 500_000, 1_000_000, 2_000_000, 4_000_000):
+        e = kpsi.Engine(0, "fp32")
+        e.set_model(W.KIN, res)
+        e.set_floating([1 if r.name in fl else 0 for r in res])
+        mc = e.generate_phsp(1234, 2 * nd, W.PHSP_WMAX)
+        data = e.generate_phsp(4321, nd, W.PHSP_WMAX)
+        torch.cuda.synchronize()
+        e.load(kpsi.DATA, data)
+        e.load(kpsi.NORM, mc)
+        del mc, data
+        e.nll_and_grad(par)
+        t = {}
+        for grad in (False, True):
+            t["grad" if grad else "nll"] = float(np.median([e.time_kernel(par, grad=grad, reps=50) for _ in range(5)]))
+        e.close()
+        torch.cuda.empty_cache()
+        nbytes = 3 * nd * 64
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        for _ in range(5):
+            x.sum()
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(50):
+            x.sum()
+        t1.record()
+        torch.cuda.synchronize()
+        sum_ms = t0.elapsed_time(t1) / 50
+        del x
+        torch.cuda.empty_cache()
+        row = {"events": 3 * nd, "record_mb": nbytes / 1e6, "nll_us": 1e3 * t["nll"], "grad_us": 1e3 * t["grad"],
+               "nll_tbs": nbytes / (t["nll"] * 1e-3) / 1e12, "torch_sum_us": 1e3 * sum_ms,
+               "torch_sum_tbs": nbytes / (sum_ms * 1e-3) / 1e12}
+        log(json.dumps(row))
+        rows.append(row)
+    return {"study": "size_scan", "rows": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["learned_eff", "large_fit", "pulls", "z_sensitivity", "real_life",
-                                      "flavour_tags"])
+                                      "flavour_tags", "size_scan"])
     ap.add_argument("--train", type=int, default=5_000_000, help="labelled training events")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the large-fit event counts")
@@ -645,7 +694,8 @@ def main() -> int:
                          "the model at the truth point and weighted back (kpsi_set_norm_mixture)")
     args = ap.parse_args()
     out = {"learned_eff": learned_eff, "large_fit": large_fit, "pulls": pulls,
-           "z_sensitivity": z_sensitivity, "real_life": real_life, "flavour_tags": flavour_tags}[args.study](args)
+           "z_sensitivity": z_sensitivity, "real_life": real_life, "flavour_tags": flavour_tags,
+           "size_scan": size_scan}[args.study](args)
     print(json.dumps(out), flush=True)
     return 0
 
