@@ -90,8 +90,8 @@ typedef struct {
   int hel_free;  /* Z only (0 for a K*): 1 leaves H'_+1 and H'_-1 independent instead of tied by
                     Eq. 11 (the Discussion's unconstrained Z couplings); the Z then has three
                     couplings, lambda' = 0, +1, -1 in that order.  Supported for a model with
-                    exactly one Z, without flavour tags, the normalisation cache or fit
-                    fractions (those calls return KPSI_E_UNSUPPORTED) */
+                    exactly one Z and without flavour tags (kpsi_set_flavour then returns
+                    KPSI_E_UNSUPPORTED) */
 } kpsi_resonance;
 
 typedef struct {

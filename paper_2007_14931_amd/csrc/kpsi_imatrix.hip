@@ -34,12 +34,15 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 }  // namespace im
 
 // One wavefront per block.  Each tile holds 32 events (64 rows: xi = +1, -1).
-template <typename T, class Sh, int C>
+// ZF: one Z whose H'_{+1} and H'_{-1} are independent couplings: three Z components
+// (lambda' = 0, +1, -1), the third in the component position of the second Z.
+template <typename T, class Sh, int C, bool ZF>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void imatrix_kernel(const ImArgs<T, Sh> a) {
   using namespace im;
   constexpr int NT = C / 16;
   constexpr int NTILE = NT * (NT + 1) / 2;
-  constexpr int NZ = Sh::NZ;
+  static_assert(!ZF || Sh::NZ >= 2, "free Z helicities use the second Z's component position");
+  constexpr int NZ = ZF ? 1 : Sh::NZ;   // Z slots evaluated
   // Rows are staged at the context precision in dynamic LDS sized for the columns in use (the
   // padded width C is only the MFMA tiling): FP32 rows of the 76-column benchmark model take
   // 19.5 KB, so eight one-wavefront blocks fit per compute unit (two per SIMD), and one wave's
@@ -63,12 +66,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void im
 
   // The event columns of this lane's event in the next tile are fetched before the matrix phase
   // of the current one, so their latency hides behind it.  Column groups of four (K* chain:
-  // 0-11; Z angular factors: 12-15, present when the model has Z states).
+  // 0-11; Z angular factors: 12-15, present when the model has Z states; with free Z
+  // helicities 16-17 as well).
   using V4 = T __attribute__((ext_vector_type(4)));
   const V4* __restrict__ gcol = reinterpret_cast<const V4*>(a.cols);
   const int64_t ld = a.ld;
   const bool zon = NZ > 0 && a.cnt[5] > 0;
-  V4 g0{}, g1{}, g2{}, g3{};
+  V4 g0{}, g1{}, g2{}, g3{}, g4{};
   T wv = T(0);
   auto fetch = [&](int64_t tile) {
     const int64_t e = tile * 32 + (lane & 31);
@@ -77,6 +81,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void im
       g1 = gcol[ld + e];
       g2 = gcol[2 * ld + e];
       if (zon) g3 = gcol[3 * ld + e];
+      if (ZF && zon) g4 = gcol[4 * ld + e];
       wv = a.eps ? a.eps[e] : T(1);
     }
   };
@@ -192,8 +197,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void im
           // this row's Zang[l'][xi]: xi = +1 columns 12-13 (l' = 0) and 14-15 (l' = 1); xi = -1 is
           // (-Re, Im) of xi = +1
           const T z0r = xm ? -g3.x : g3.x, z0i = g3.y;
-          const T z1r = xm ? -g3.z : g3.z, z1i = g3.w;
+          T z1r = xm ? -g3.z : g3.z, z1i = g3.w;
+          T z2r = T(0), z2i = T(0);
+          if constexpr (ZF) {
+            // lambda' = +1: F++ (xi = +1, columns 14-15) or F+- (xi = -1, columns 16-17);
+            // lambda' = -1: -conj(F+-) (xi = +1) or -conj(F++) (xi = -1)
+            z1r = xm ? g4.x : g3.z;
+            z1i = xm ? g4.y : g3.w;
+            z2r = xm ? -g3.z : -g4.x;
+            z2i = xm ? g3.w : g4.y;
+          }
           constexpr int zc0 = comp_base<Sh>(5);
+          constexpr int ZN = ZF ? 3 : 2;   // components per Z slot
 #pragma unroll
           for (int z = 0; z < NZ; ++z) {
             if (z >= a.cnt[5]) continue;
@@ -204,6 +219,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void im
             const T Ar = sc * dre, Ai = -sc * dim;
             put(zc0 + 2 * z, Ar, Ai, z0r, z0i);
             put(zc0 + 2 * z + 1, Ar, Ai, z1r, z1i);
+            if constexpr (ZF) put(zc0 + 2, Ar, Ai, z2r, z2i);
             if (rc.flt >= 0) {
               const T pr = rc.twoM, pim = -rc.dP * gz;
               const T Yr = (pr * dre + pim * dim) * inv, Yi = (pim * dre - pr * dim) * inv;
@@ -215,8 +231,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void im
               const int dc = a.dcol[rc.flt];
               put(dc, dMr, dMi, z0r, z0i);
               put(dc + 1, dMr, dMi, z1r, z1i);
-              put(dc + 2, dGr, dGi, z0r, z0i);
-              put(dc + 3, dGr, dGi, z1r, z1i);
+              put(dc + ZN, dGr, dGi, z0r, z0i);
+              put(dc + ZN + 1, dGr, dGi, z1r, z1i);
+              if constexpr (ZF) {
+                put(dc + 2, dMr, dMi, z2r, z2i);
+                put(dc + 5, dGr, dGi, z2r, z2i);
+              }
             }
           }
         }
@@ -357,7 +377,17 @@ template <typename T> size_t imatrix_smem(int ncols) { return 64 * (size_t)(ncol
 template <typename T, class Sh, int C>
 hipError_t launch_imatrix_c(const ImArgs<T, Sh>& a, int nb, double* out, hipStream_t st) {
   if (a.ncols <= 0 || a.ncols > C || (a.ncols & 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((imatrix_kernel<T, Sh, C>), dim3(nb), dim3(64), imatrix_smem<T>(a.ncols), st, a);
+  if constexpr (Sh::NZ >= 2) {
+    if (a.zfree) {
+      if (a.cnt[5] != 1) return hipErrorInvalidValue;   // refused by the host API
+      hipLaunchKernelGGL((imatrix_kernel<T, Sh, C, true>), dim3(nb), dim3(64), imatrix_smem<T>(a.ncols), st, a);
+    } else {
+      hipLaunchKernelGGL((imatrix_kernel<T, Sh, C, false>), dim3(nb), dim3(64), imatrix_smem<T>(a.ncols), st, a);
+    }
+  } else {
+    if (a.zfree) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((imatrix_kernel<T, Sh, C, false>), dim3(nb), dim3(64), imatrix_smem<T>(a.ncols), st, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   constexpr int NT = C / 16;
@@ -369,7 +399,7 @@ hipError_t launch_imatrix_c(const ImArgs<T, Sh>& a, int nb, double* out, hipStre
 template <typename T, class Sh, int C> int imatrix_blocks_per_cu_c(int ncols) {
   int nb = 0;
   const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, imatrix_kernel<T, Sh, C>, 64, imatrix_smem<T>(ncols));
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, imatrix_kernel<T, Sh, C, false>, 64, imatrix_smem<T>(ncols));
   return (e == hipSuccess && nb > 0) ? nb : 0;
 }
 // Blocks (one wavefront each) of the interference-matrix kernel resident per compute unit.

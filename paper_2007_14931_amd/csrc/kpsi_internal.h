@@ -173,6 +173,7 @@ template <typename T, class Sh> struct ImArgs {
   T rR, rB, invMB;
   RC<T> ks[Sh::NK > 0 ? Sh::NK : 1];
   RC<T> zs[Sh::NZ > 0 ? Sh::NZ : 1];
+  int zfree;            // one Z with independent H'_{+1}, H'_{-1}: three Z components (0, +1, -1)
 };
 
 constexpr int MLP_NV = 4546;     // values per block record of the network gradient: 4545 parameters and the loss

@@ -437,7 +437,8 @@ kpsi_status validate(kpsi_ctx* c, int64_t n, const double* const* obs) {
 // ---------------------------------------------------------------- interference-matrix cache
 void invalidate_cache(kpsi_ctx* c) { c->cache_valid = false; c->last_ls.clear(); c->ls_streak = 0; }
 
-// Complex components in accumulator order: K* slots by spin (1 or 3 each), then Z slots (2).
+// Complex components in accumulator order: K* slots by spin (1 or 3 each), then Z slots (2; a
+// single Z with free helicities uses 3, the third in the second slot's first position).
 int n_components(int shape) {
   int N[5], NZ;
   shape_counts(shape, N, &NZ);
@@ -454,7 +455,7 @@ void components_of(const kpsi_ctx* c, size_t i, int* first, int* count) {
     int nk = 0;
     for (int j = 0; j < 5; ++j) nk += N[j] * (j == 0 ? 1 : 3);
     *first = nk + 2 * c->slot[i];
-    *count = 2;
+    *count = ncoup(r);   // 2, or 3 with free helicities (one Z: the third takes the next slot's first)
     return;
   }
   int base = 0, slot0 = 0;
@@ -540,6 +541,7 @@ kpsi_status gram_build_t(kpsi_ctx* c, const double* par, bool with_eps, bool wit
   a.eps = with_eps ? (const T*)c->eps : (const T*)c->wcol;   // wcol: importance weights or null
   a.partial = c->cache_partial;
   a.ncols = ncols;
+  a.zfree = c->zfree ? 1 : 0;
   a.skip_last = (NT > 1 && 16 * (NT - 1) >= 2 * ncomp) ? 1 : 0;
   for (int j = 0; j < 6; ++j) a.cnt[j] = pa.cnt[j];
   for (int f = 0; f < NFL; ++f) a.dcol[f] = dcol[f];
@@ -1042,8 +1044,8 @@ kpsi_status kpsi_set_model(kpsi_ctx* c, const kpsi_kinematics* kin, const kpsi_r
   }
   if (nfree && nz != 1)
     return fail(c, KPSI_E_UNSUPPORTED, "free Z helicity couplings need a model with exactly one Z (it has %d)", nz);
-  if (nfree && (c->cc_on || c->cache_mode != 0))
-    return fail(c, KPSI_E_UNSUPPORTED, "free Z helicity couplings: switch off flavour tags and the normalisation cache first");
+  if (nfree && c->cc_on)
+    return fail(c, KPSI_E_UNSUPPORTED, "free Z helicity couplings: switch off flavour tags first");
   int shape = -1;
   const int small[5] = {0, 1, 0, 0, 0}, full[5] = {3, 3, 2, 1, 1};
   bool fits_small = nz == 0, fits_full = nz <= 2;
@@ -2126,8 +2128,6 @@ kpsi_status kpsi_set_efficiency_mlp(kpsi_ctx* c, const float* params) {
 kpsi_status kpsi_set_norm_cache(kpsi_ctx* c, int mode) {
   if (!c) return KPSI_E_ARG;
   if (mode < 0 || mode > 2) return fail(c, KPSI_E_ARG, "cache mode must be 0, 1 or 2");
-  if (mode != 0 && c->zfree)
-    return fail(c, KPSI_E_UNSUPPORTED, "the interference-matrix cache does not cover free Z helicity couplings");
   c->cache_mode = mode;
   invalidate_cache(c);
   return KPSI_OK;
@@ -2145,7 +2145,6 @@ kpsi_status kpsi_fit_fractions(kpsi_ctx* c, const double* params, double* ff, do
   if (!c) return KPSI_E_ARG;
   if (!params || !ff) return fail(c, KPSI_E_ARG, "NULL argument");
   if (!c->has_model) return fail(c, KPSI_E_STATE, "no model set");
-  if (c->zfree) return fail(c, KPSI_E_UNSUPPORTED, "fit fractions with free Z helicity couplings are not supported");
   if (c->set[1].n <= 0) return fail(c, KPSI_E_STATE, "no normalisation events loaded");
   for (int i = 0; i < c->nparams; ++i)
     if (!std::isfinite(params[i])) return fail(c, KPSI_E_ARG, "parameter %d is not finite", i);

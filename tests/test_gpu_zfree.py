@@ -11,6 +11,8 @@ instead of H'_{-1} = H'_{+1} (Eq. 11 for a 1+ state).  Checked here:
 * at H'_{-1} = H'_{+1} the free model is the constrained one: the same NLL, and the constrained
   gradient of H'_{+1} is the sum of the free gradients of H'_{+1} and H'_{-1} (magnitude and
   phase, by the chain rule);
+* the normalisation served by the interference matrix (three Z components), with the lineshape
+  derivative columns of the floating Z, and the fit fractions of Eq. 13 from it;
 * the accept-reject generator draws the oracle's sample from the free model;
 * the calls that do not cover free helicities refuse them.
 """
@@ -130,10 +132,6 @@ def test_calls_without_free_helicity_support_refuse_them():
     par = W.params(res, seed=5)
     with pytest.raises(kpsi.KpsiError):
         e.set_flavour(np.ones(500))
-    with pytest.raises(kpsi.KpsiError):
-        e.set_norm_cache(1)
-    with pytest.raises(kpsi.KpsiError):
-        e.fit_fractions(par)
     assert np.isfinite(e.nll(par))          # the context is still usable
     # two Z with one free, and a free K*, are rejected by set_model
     z2 = dataclasses.replace(W.Z4240)
@@ -142,4 +140,45 @@ def test_calls_without_free_helicity_support_refuse_them():
     bad = [dataclasses.replace(W.KSTAR892, hel_free=True)]
     with pytest.raises(kpsi.KpsiError):
         e.set_model(K, bad)
+    e.close()
+
+
+@pytest.mark.parametrize("prec,tg", [("fp64", 1e-9), ("fp32", None)])
+def test_free_helicity_normalisation_from_the_interference_matrix(prec, tg):
+    res = W.model("full_zfree")
+    data, mc = _sets(4099, 12007, 331)
+    e = _engine(prec, res, data, mc)
+    e.set_norm_cache(1)
+    dirs = np.flatnonzero(W.free_mask(res, FLOAT))
+    par = W.params(res, seed=333) + 0.03 * W.free_mask(res, FLOAT)
+    z = _z_offset(res)
+    p2 = par.copy()
+    p2[z + 4] += 0.09          # H'_{-1} magnitude and phase: couplings only, served by the matrix
+    p2[z + 5] -= 0.2
+    for k, p in enumerate((par, p2)):
+        st, ref, gref = O.nll(K, res, p, data, mc, dirs=dirs)
+        assert st == 0
+        v, g = e.nll_and_grad(p)
+        check_nll(v, ref, prec, data.shape[1], f"free Z cached {k}")
+        check_grad(g[dirs], gref, prec, f"free Z cached {k}", norm=tg)
+        check_nll(e.nll(p), ref, prec, data.shape[1], f"free Z cached nll-only {k}")
+    b, h, _ = e.norm_cache_stats()
+    assert b == 1 and h >= 2
+    e.close()
+
+
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-9), ("fp32", 2e-5)])
+def test_free_helicity_fit_fractions_match_oracle(prec, rtol):
+    res = W.model("full_zfree")
+    mc = O.gen_phsp(K, 341, 20011, W.PHSP_WMAX)
+    e = kpsi.Engine(0, prec)
+    e.set_model(K, res)
+    e.load(kpsi.NORM, mc)
+    par = W.params(res, seed=343)
+    ff, tot = e.fit_fractions(par)
+    st, ref = O.fit_fractions(K, res, par, mc)
+    assert st == 0
+    print(f"[zfree] {prec} fit fractions Z {ff[-1]:.6f} oracle {ref[-1]:.6f}, sum {tot:.6f}", flush=True)
+    np.testing.assert_allclose(ff, ref, rtol=rtol, atol=rtol * 1e-3)
+    assert tot == pytest.approx(ref.sum(), rel=rtol)
     e.close()
