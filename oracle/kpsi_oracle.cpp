@@ -410,6 +410,8 @@ static std::vector<Res> to_res(const oracle_res* r, int n) {
 static Kin to_kin(const oracle_kin* k) { return Kin{k->mB, k->mJ, k->mK, k->mPi, k->rB, k->rR}; }
 
 int oracle_n_params(const oracle_res* res, int n_res) { return n_full_params(to_res(res, n_res)); }
+// Sizes of the structures the binding passes (a mismatched binding is refused at load).
+int oracle_struct_size(int which) { return which == 0 ? (int)sizeof(oracle_kin) : (int)sizeof(oracle_res); }
 
 double oracle_wigner_d(int j, int mp, int m, double theta) { return wigner_d(j, mp, m, theta); }
 double oracle_breakup(double M, double m1, double m2) { return breakup(M, m1, m2); }

@@ -70,6 +70,9 @@ def lib():
         L.oracle_acceptance.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
         L.oracle_acceptance.restype = C.c_double
         L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_struct_size.argtypes = [C.c_int]
+        if L.oracle_struct_size(0) != C.sizeof(Kin) or L.oracle_struct_size(1) != C.sizeof(Res):
+            raise RuntimeError("oracle library and binding disagree on the structure layouts")
         _lib = L
     return _lib
 
