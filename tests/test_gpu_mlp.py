@@ -45,6 +45,15 @@ def test_network_gradient_and_output_match_reference(n):
         assert np.linalg.norm(g[blk] - ref_g[blk]) <= 1e-3 * np.linalg.norm(ref_g[blk]) + 1e-9
     p = e.mlp_eval(par, _cuda(ev)).cpu().numpy()
     check_probabilities(p, ref_p, par, u)
+    # against the plain FP64 network (no BF16 rounding anywhere; its gradient is pinned by
+    # differences on the CPU): the device gradient is that network's gradient up to the BF16
+    # precision of the weights and 64x64 operands (8-bit significands: relative 2^-9 per rounding)
+    loss64, p64, g64 = O.mlp(par.astype(np.float64), u, y.astype(np.float64), grad=True, round_bf16=False)
+    eg = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    ep = float(np.max(np.abs(p - p64)))
+    print(f"[parity] network n={n} vs unrounded FP64 network: gradient {eg:.2e}, loss {abs(loss - loss64) / loss64:.2e}, "
+          f"max |dp| {ep:.2e}", flush=True)
+    assert eg < 2e-2 and abs(loss - loss64) < 1e-4 * loss64 and ep < 3e-3
 
 
 def test_labels_and_histogram():
