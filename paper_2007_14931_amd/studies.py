@@ -7,6 +7,7 @@
     python -m paper_2007_14931_amd.studies real_life     # efficiency + 15% background (Eq. 14) vs ideal fit
     python -m paper_2007_14931_amd.studies flavour_tags  # B0 + conjugate decays, 5% mistag, tagged fit
     python -m paper_2007_14931_amd.studies size_scan     # per-event kernel time against the event count
+    python -m paper_2007_14931_amd.studies z_helicities  # Z couplings free of Eq. 11: likelihood-ratio test
 
 Each prints one JSON line.  All events are synthetic, from the library's seeded generators:
 flat phase space, accept labels under the seeded analytic acceptance (the paper's
@@ -629,6 +630,82 @@ def flavour_tags(args) -> dict:
     return out
 
 
+def z_helicities(args) -> dict:
+    """Z helicity couplings free of the parity relation (Eq. 11; the Discussion's unconstrained Z
+    couplings).  Pseudo-data of the ten K* + Z(4430) model at 3.5% Z fit fraction, generated once
+    with H'_{-1} = H'_{+1} (parity conserved in Z -> J/psi pi) and once with H'_{-1} = 0.5 H'_{+1}
+    e^{i}, are fitted with the free and with the constrained model (FP32 adjoint MIGRAD, FP64
+    adjoint polish, HESSE).  Reported: the fitted difference H'_{-1} - H'_{+1} and its chi^2 from
+    the HESSE covariance (2 degrees of freedom), and the likelihood ratio -2 ln(L_constrained /
+    L_free), chi^2 with 2 degrees of freedom when the relation holds."""
+    import torch
+    stream = torch.cuda.current_stream().cuda_stream
+    n_data = int(args.data_events)
+    n_mc = int(args.norm_events) if args.norm_events else 2_000_000
+    res_f, res_c = W.model("full_zfree"), W.model("full")
+    iz = len(res_f) - 1
+    zf = W.coupling_offset(res_f, iz)
+    gen = kpsi.Engine(0, "fp64", stream)
+    gen.set_model(W.KIN, res_f)
+    mc = gen.generate_phsp(5601, n_mc, W.PHSP_WMAX)
+    scan = gen.generate_phsp(5602, 1_000_000, W.PHSP_WMAX)
+    gen.load(kpsi.DATA, scan)
+    gen.load(kpsi.NORM, mc)
+    base = W.params(res_f, 41)
+    out = {"study": "z_helicities", "data_events": n_data, "norm_events": n_mc}
+
+    def constrained_of(p):   # drop H'_{-1}
+        return np.concatenate([p[: zf + 4], p[zf + 6:]])
+
+    for case, (ratio, dphase) in (("parity_conserving", (1.0, 0.0)), ("parity_violating", (0.5, 1.0))):
+        truth = base.copy()
+        truth[zf + 4] = ratio * truth[zf + 2]
+        truth[zf + 5] = truth[zf + 3] + dphase
+        for _ in range(4):   # scale the Z couplings to a 3.5% fit fraction
+            ff, _ = gen.fit_fractions(truth)
+            f = math.sqrt(0.035 / ff[iz])
+            for k in (0, 2, 4):
+                truth[zf + k] *= f
+        smax = 1.5 * float(gen.density(kpsi.DATA, truth).max())
+        data, _, _ = gen.generate_model(truth, 5700 + len(out), n_data, W.PHSP_WMAX, smax)
+        rec = {}
+        for label, res, start, mask in (("free", res_f, truth.copy(), W.free_mask(res_f)),
+                                        ("constrained", res_c, constrained_of(truth), W.free_mask(res_c))):
+            x = start
+            for prec in ("fp32", "fp64"):
+                e = kpsi.Engine(0, prec, stream)
+                e.set_model(W.KIN, res)
+                e.load(kpsi.DATA, data)
+                e.load(kpsi.NORM, mc)
+                x, _, r = e.migrad(x, mask)
+                if prec == "fp64":
+                    cov, rh = e.hesse(x, mask)
+                e.close()
+            rec[label] = {"x": x, "fmin": r.fmin, "status": r.status, "hesse_status": rh.status, "cov": cov,
+                          "mask": mask}
+        x, cov, mask = rec["free"]["x"], rec["free"]["cov"], rec["free"]["mask"]
+        free = list(np.flatnonzero(mask))
+        ks = [free.index(zf + k) for k in (2, 3, 4, 5)]
+        rp, pp, rm, pm = (x[zf + k] for k in (2, 3, 4, 5))
+        d = np.array([rm * math.cos(pm) - rp * math.cos(pp), rm * math.sin(pm) - rp * math.sin(pp)])
+        J = np.array([[-math.cos(pp), rp * math.sin(pp), math.cos(pm), -rm * math.sin(pm)],
+                      [-math.sin(pp), -rp * math.cos(pp), math.sin(pm), rm * math.cos(pm)]])
+        cd = J @ cov[np.ix_(ks, ks)] @ J.T
+        chi2 = float(d @ np.linalg.solve(cd, d))
+        dt = truth[zf + 4] * np.exp(1j * truth[zf + 5]) - truth[zf + 2] * np.exp(1j * truth[zf + 3])
+        out[case] = {"generated_ratio": ratio, "generated_phase_offset": dphase,
+                     "generated_difference": [float(dt.real), float(dt.imag)],
+                     "fitted_difference": d.tolist(), "difference_errors": np.sqrt(np.diag(cd)).tolist(),
+                     "difference_chi2_2dof": chi2,
+                     "likelihood_ratio": rec["constrained"]["fmin"] - rec["free"]["fmin"],
+                     "fit_status": {k: (rec[k]["status"], rec[k]["hesse_status"]) for k in rec},
+                     "ff_z_generated": float(gen.fit_fractions(truth)[0][iz])}
+        log(f"{case}: {out[case]}")
+        del data
+    gen.close()
+    return out
+
+
 def size_scan(args) -> dict:
     """Kernel time of the FP32 likelihood-only and gradient passes (kpsi_time_kernel: medians of
     five batches of 50 back-to-back launches) for 1/8 to 4 times the benchmark's 1e6 + 2e6 phase-
@@ -680,7 +757,7 @@ def size_scan(args) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("study", choices=["learned_eff", "large_fit", "pulls", "z_sensitivity", "real_life",
-                                      "flavour_tags", "size_scan"])
+                                      "flavour_tags", "size_scan", "z_helicities"])
     ap.add_argument("--train", type=int, default=5_000_000, help="labelled training events")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the large-fit event counts")
@@ -695,7 +772,7 @@ def main() -> int:
     args = ap.parse_args()
     out = {"learned_eff": learned_eff, "large_fit": large_fit, "pulls": pulls,
            "z_sensitivity": z_sensitivity, "real_life": real_life, "flavour_tags": flavour_tags,
-           "size_scan": size_scan}[args.study](args)
+           "size_scan": size_scan, "z_helicities": z_helicities}[args.study](args)
     print(json.dumps(out), flush=True)
     return 0
 
