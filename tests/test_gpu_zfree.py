@@ -13,6 +13,7 @@ instead of H'_{-1} = H'_{+1} (Eq. 11 for a 1+ state).  Checked here:
   phase, by the chain rule);
 * the normalisation served by the interference matrix (three Z components), with the lineshape
   derivative columns of the floating Z, and the fit fractions of Eq. 13 from it;
+* the free model inside the Eq. 14 mixture;
 * the accept-reject generator draws the oracle's sample from the free model;
 * the calls that do not cover free helicities refuse them.
 """
@@ -181,4 +182,26 @@ def test_free_helicity_fit_fractions_match_oracle(prec, rtol):
     print(f"[zfree] {prec} fit fractions Z {ff[-1]:.6f} oracle {ref[-1]:.6f}, sum {tot:.6f}", flush=True)
     np.testing.assert_allclose(ff, ref, rtol=rtol, atol=rtol * 1e-3)
     assert tot == pytest.approx(ref.sum(), rel=rtol)
+    e.close()
+
+
+@pytest.mark.parametrize("prec,tg", [("fp64", 1e-9), ("fp32", None)])
+def test_free_helicities_with_the_background_mixture(prec, tg):
+    """Free Z helicities inside the Eq. 14 mixture (per-event efficiency and background)."""
+    res = W.model("full_zfree")
+    data, mc = _sets(4099, 12007, 351)
+    rng = np.random.default_rng(352)
+    eps_d = O.acceptance(W.acceptance_coefficients(), W.M_LO, W.M_HI, data)
+    eps_m = O.acceptance(W.acceptance_coefficients(), W.M_LO, W.M_HI, mc)
+    b_d, b_m = rng.uniform(0.2, 1.5, data.shape[1]), rng.uniform(0.2, 1.5, mc.shape[1])
+    e = _engine(prec, res, data, mc)
+    e.set_efficiency_values(eps_m)
+    e.set_background(0.8, eps_d, b_d, b_m)
+    par = W.params(res, seed=353) + 0.03 * W.free_mask(res, FLOAT)
+    dirs = np.flatnonzero(W.free_mask(res, FLOAT))
+    st, ref, gref = O.nll_mix(K, res, par, data, mc, b_d, b_m, 0.8, eps_d, eps_m, dirs)
+    assert st == 0
+    v, g = e.nll_and_grad(par)
+    check_nll(v, ref, prec, data.shape[1], "free Z mixture")
+    check_grad(g[dirs], gref, prec, "free Z mixture", norm=tg)
     e.close()
