@@ -90,8 +90,7 @@ typedef struct {
   int hel_free;  /* Z only (0 for a K*): 1 leaves H'_+1 and H'_-1 independent instead of tied by
                     Eq. 11 (the Discussion's unconstrained Z couplings); the Z then has three
                     couplings, lambda' = 0, +1, -1 in that order.  Supported for a model with
-                    exactly one Z and without flavour tags (kpsi_set_flavour then returns
-                    KPSI_E_UNSUPPORTED) */
+                    exactly one Z (kpsi_set_model returns KPSI_E_UNSUPPORTED otherwise) */
 } kpsi_resonance;
 
 typedef struct {
@@ -334,7 +333,7 @@ kpsi_status kpsi_set_background(kpsi_ctx* ctx, double purity, const double* eps_
  * (the data efficiencies enter here, as in the untagged mixture).  Each call then evaluates
  * the normalisation events at +phi and -phi first, or takes both from the interference matrix.
  * Loading data events drops the tags.  Errors: KPSI_E_ARG for a wrong count, a tag other than
- * +-1 or w outside [0, 1/2]; KPSI_E_UNSUPPORTED with free Z helicity couplings. */
+ * +-1 or w outside [0, 1/2]. */
 kpsi_status kpsi_set_flavour(kpsi_ctx* ctx, const double* tags, int64_t n, double mistag);
 
 /* ---------------------------------------------------------------- Gaussian constraints

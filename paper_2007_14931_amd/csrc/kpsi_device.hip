@@ -335,7 +335,7 @@ template <typename T, class Sh, int MODE> struct AmpWaves {
 template <typename T, class Sh, int MODE, bool CC, bool ZF>
 __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(const AmpArgs<T, Sh> a) {
   constexpr int NK = Sh::NK;
-  static_assert(!ZF || (Sh::NZ >= 2 && !CC), "free Z helicities: one Z, untagged events");
+  static_assert(!ZF || Sh::NZ >= 2, "free Z helicities use the second Z's record slots");
   constexpr int NZ = ZF ? 1 : Sh::NZ;   // Z slots evaluated
   constexpr bool GRAD = (MODE == MODE_GRAD);
   using A_t = typename AccType<T>::type;   // per-thread gradient accumulator type
@@ -571,7 +571,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
     // (AZ holds the bare Breit-Wigner; the Z barrier factor n_Z is in the angular columns)
     Cx<T> AZ[NZ > 0 ? NZ : 1];
     T gzv = T(0);
-    Cx<T> T0k{T(0), T(0)}, T1k{T(0), T(0)};   // Z coupling sums, kept for a second reading
+    Cx<T> T0k{T(0), T(0)}, T1k{T(0), T(0)}, T2k{T(0), T(0)};   // Z coupling sums, kept for a second reading
     if constexpr (NZ > 0) {
       if (a.cnt[5] > 0) {
         const T mz2 = g2.y;
@@ -605,6 +605,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
         if constexpr (CC) {
           T0k = T0;
           T1k = T1;
+          if constexpr (ZF) T2k = T2;
         }
       }
     }
@@ -628,7 +629,7 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
           // t = (1 - w) S(q phi) + w S(-q phi)
           kstar_at(-f1, ap2, am2);
           if constexpr (NZ > 0) {
-            if (a.cnt[5] > 0) z_add(-f1, T0k, T1k, T1k, ap2, am2);   // (no third sum: ZF excludes CC)
+            if (a.cnt[5] > 0) z_add(-f1, T0k, T1k, T2k, ap2, am2);
           }
           S2 = ap2.re * ap2.re + ap2.im * ap2.im + am2.re * am2.re + am2.im * am2.im;
           arg = fma_(a.keep, S, a.mistag * S2);
@@ -778,18 +779,25 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
             WZ1 = Cx<T>{za[4] * bp_.re - z5 * bp_.im + za[6] * bm_.re - z7 * bm_.im,
                         za[4] * bp_.im + z5 * bp_.re + za[6] * bm_.im + z7 * bm_.re};
           };
+          // (free helicities) WZ_{-1} from the l' = -1 factors, same form
+          auto wz2 = [&](T f, const Cx<T>& bp_, const Cx<T>& bm_) -> Cx<T> {
+            const T z9 = f * za[9], z11 = f * za[11];
+            return Cx<T>{za[8] * bp_.re - z9 * bp_.im + za[10] * bm_.re - z11 * bm_.im,
+                         za[8] * bp_.im + z9 * bp_.re + za[10] * bm_.im + z11 * bm_.re};
+          };
           Cx<T> WZ0, WZ1, WZ2{T(0), T(0)};
           wz(f1, bp, bm, WZ0, WZ1);
-          if constexpr (ZF) {
-            WZ2 = Cx<T>{za[8] * bp.re - za[9] * bp.im + za[10] * bm.re - za[11] * bm.im,
-                        za[8] * bp.im + za[9] * bp.re + za[10] * bm.im + za[11] * bm.re};
-          }
+          if constexpr (ZF) WZ2 = wz2(f1, bp, bm);
           if constexpr (CC) {
             if (two) {
               Cx<T> X0, X1;
               wz(-f1, bp2, bm2, X0, X1);
               WZ0.re += X0.re; WZ0.im += X0.im;
               WZ1.re += X1.re; WZ1.im += X1.im;
+              if constexpr (ZF) {
+                const Cx<T> X2 = wz2(-f1, bp2, bm2);
+                WZ2.re += X2.re; WZ2.im += X2.im;
+              }
             }
           }
 #pragma unroll
@@ -1109,12 +1117,12 @@ template hipError_t launch_invariants<double>(const InvArgs<double>&, hipStream_
 
 template <typename T, class Sh, bool ZF>
 hipError_t launch_amp_zf(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_t st) {
-  const bool cc = !ZF && a.tag != nullptr && mode != MODE_DENSITY;
+  const bool cc = a.tag != nullptr && mode != MODE_DENSITY;
   if (mode == MODE_GRAD) {
-    if (cc) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_GRAD, true, false>), dim3(nblocks), dim3(256), 0, st, a);
+    if (cc) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_GRAD, true, ZF>), dim3(nblocks), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_GRAD, false, ZF>), dim3(nblocks), dim3(256), 0, st, a);
   } else if (mode == MODE_NLL) {
-    if (cc) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_NLL, true, false>), dim3(nblocks), dim3(256), 0, st, a);
+    if (cc) hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_NLL, true, ZF>), dim3(nblocks), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_NLL, false, ZF>), dim3(nblocks), dim3(256), 0, st, a);
   } else {
     hipLaunchKernelGGL((amp_kernel<T, Sh, MODE_DENSITY, false, ZF>), dim3(nblocks), dim3(256), 0, st, a);
@@ -1126,7 +1134,7 @@ hipError_t launch_amp(const AmpArgs<T, Sh>& a, int mode, int nblocks, hipStream_
   if (nblocks <= 0) return hipSuccess;
   if constexpr (Sh::NZ >= 2) {
     if (a.zfree) {
-      if (a.tag != nullptr || a.cnt[5] != 1) return hipErrorInvalidValue;   // refused by the host API
+      if (a.cnt[5] != 1) return hipErrorInvalidValue;   // refused by the host API
       return launch_amp_zf<T, Sh, true>(a, mode, nblocks, st);
     }
   } else {
@@ -1141,10 +1149,10 @@ int amp_blocks_per_cu_zf(int mode, bool cc) {
   int nb = 0;
   hipError_t e;
   if (mode == MODE_GRAD)
-    e = cc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_GRAD, true, false>, 256, 0)
+    e = cc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_GRAD, true, ZF>, 256, 0)
            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_GRAD, false, ZF>, 256, 0);
   else if (mode == MODE_NLL)
-    e = cc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_NLL, true, false>, 256, 0)
+    e = cc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_NLL, true, ZF>, 256, 0)
            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_NLL, false, ZF>, 256, 0);
   else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, amp_kernel<T, Sh, MODE_DENSITY, false, ZF>, 256, 0);
   return (e == hipSuccess && nb > 0) ? nb : 0;
@@ -1152,7 +1160,7 @@ int amp_blocks_per_cu_zf(int mode, bool cc) {
 template <typename T, class Sh>
 int amp_blocks_per_cu(int mode, bool cc, bool zfree) {
   if constexpr (Sh::NZ >= 2) {
-    if (zfree && !cc) return amp_blocks_per_cu_zf<T, Sh, true>(mode, false);
+    if (zfree) return amp_blocks_per_cu_zf<T, Sh, true>(mode, cc);
   }
   return amp_blocks_per_cu_zf<T, Sh, false>(mode, cc);
 }

@@ -131,8 +131,8 @@ struct kpsi_ctx {
   double bench_ms = 0.0;          // their duration per launch
   int ept_override = 0;
   int n_cu = 0;                                                   // compute units of the device
-  int blocks_per_cu[2][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
-                                {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}};   // [shape][mode][cc / zfree]
+  int blocks_per_cu[2][3][4] = {{{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}},
+                                {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}}};   // [shape][mode][cc + 2 zfree]
   // interference-matrix cache of the normalisation sum (mode 0 off, 1 on, 2 auto)
   int cache_mode = 0;
   bool cache_valid = false;
@@ -335,7 +335,7 @@ template <typename T, class Sh>
 int pick_ept(kpsi_ctx* c, int mode, int64_t nd, int64_t nm) {
   if (c->ept_override > 0) return c->ept_override;
   const bool cc = c->cc_on && mode != MODE_DENSITY;
-  int& bpc = c->blocks_per_cu[c->shape][mode][cc ? 1 : (c->zfree ? 2 : 0)];
+  int& bpc = c->blocks_per_cu[c->shape][mode][(cc ? 1 : 0) + (c->zfree ? 2 : 0)];
   if (bpc < 0) bpc = amp_blocks_per_cu<T, Sh>(mode, cc, c->zfree);
   const int64_t cap = (int64_t)(c->n_cu > 0 ? c->n_cu : 256) * (bpc > 0 ? bpc : 3);
   auto blocks = [&](int64_t ept) {
@@ -701,7 +701,9 @@ kpsi_status use_cache(kpsi_ctx* c, const double* par, bool* use) {
 // With flavour tags the second record is the normalisation at -phi.  Reversing phi of an event
 // gives the density of the original event with the lambda = -1 and lambda = +1 couplings of
 // every K* of spin >= 1 exchanged (the d^1_{lambda xi} symmetry takes e^{-i lambda phi} to the
-// opposite helicities; the Z-chain terms of the two xi swap, with a common sign), so
+// opposite helicities; the Z-chain terms of the two xi swap, with a common sign: the Z angular
+// factors conjugate, Zang[l'][xi] -> -Zang[-l'][-xi], which leaves Eq. 11 couplings as they are
+// and exchanges free H'_{+1} and H'_{-1}), so
 // I(-phi; H) = I(+phi; H') with H' the exchanged couplings, and the +phi matrix serves both
 // records: record 2 is the +phi record at H', its coupling entries mapped back through the
 // same exchange (its lineshape-derivative entries need no mapping).
@@ -714,6 +716,9 @@ kpsi_status put_cached_record(kpsi_ctx* c, const double* params) {
       if (r.chain == 0 && r.spin > 0) {
         std::swap(sw[off], sw[off + 4]);
         std::swap(sw[off + 1], sw[off + 5]);
+      } else if (r.chain == 1 && r.hel_free) {   // lambda' = +1 and -1 (order 0, +1, -1)
+        std::swap(sw[off + 2], sw[off + 4]);
+        std::swap(sw[off + 3], sw[off + 5]);
       }
       off += 2 * ncoup(r);
     }
@@ -721,11 +726,13 @@ kpsi_status put_cached_record(kpsi_ctx* c, const double* params) {
     cached_norm_record(c, sw.data(), r2);
     for (size_t i = 0; i < c->res.size(); ++i) {
       const kpsi_resonance& r = c->res[i];
-      if (r.chain != 0 || r.spin == 0) continue;
+      const bool kst = r.chain == 0 && r.spin > 0, zf = r.chain == 1 && r.hel_free;
+      if (!kst && !zf) continue;
       int k0, nk;
       components_of(c, i, &k0, &nk);
-      std::swap(r2[3 + 2 * k0], r2[3 + 2 * (k0 + 2)]);
-      std::swap(r2[3 + 2 * k0 + 1], r2[3 + 2 * (k0 + 2) + 1]);
+      const int ka = kst ? k0 : k0 + 1;   // the exchanged components: k0 + {0, 2} or k0 + {1, 2}
+      std::swap(r2[3 + 2 * ka], r2[3 + 2 * (k0 + 2)]);
+      std::swap(r2[3 + 2 * ka + 1], r2[3 + 2 * (k0 + 2) + 1]);
     }
   }
   if (c->bkg_on) {
@@ -1044,8 +1051,6 @@ kpsi_status kpsi_set_model(kpsi_ctx* c, const kpsi_kinematics* kin, const kpsi_r
   }
   if (nfree && nz != 1)
     return fail(c, KPSI_E_UNSUPPORTED, "free Z helicity couplings need a model with exactly one Z (it has %d)", nz);
-  if (nfree && c->cc_on)
-    return fail(c, KPSI_E_UNSUPPORTED, "free Z helicity couplings: switch off flavour tags first");
   int shape = -1;
   const int small[5] = {0, 1, 0, 0, 0}, full[5] = {3, 3, 2, 1, 1};
   bool fits_small = nz == 0, fits_full = nz <= 2;
@@ -1201,7 +1206,6 @@ kpsi_status kpsi_set_flavour(kpsi_ctx* c, const double* tags, int64_t n, double 
   drop_flavour(c);
   invalidate_cache(c);
   if (!tags) return KPSI_OK;   // B0 only
-  if (c->zfree) return fail(c, KPSI_E_UNSUPPORTED, "flavour tags with free Z helicity couplings are not supported");
   if (n != c->set[0].n || n <= 0) return fail(c, KPSI_E_ARG, "expected %lld tags (one per data event)", (long long)c->set[0].n);
   if (!(mistag >= 0.0 && mistag <= 0.5)) return fail(c, KPSI_E_ARG, "mistag %g outside [0, 1/2]", mistag);
   int64_t np = 0, nn = 0;

@@ -13,9 +13,11 @@ instead of H'_{-1} = H'_{+1} (Eq. 11 for a 1+ state).  Checked here:
   phase, by the chain rule);
 * the normalisation served by the interference matrix (three Z components), with the lineshape
   derivative columns of the floating Z, and the fit fractions of Eq. 13 from it;
-* the free model inside the Eq. 14 mixture;
+* the free model inside the Eq. 14 mixture, and with flavour tags (direct, and with both
+  flavours' normalisations from the +phi interference matrix, which exchanges H'_{+1} and
+  H'_{-1} for the -phi record);
 * the accept-reject generator draws the oracle's sample from the free model;
-* the calls that do not cover free helicities refuse them.
+* models the free helicities do not cover are refused.
 """
 import dataclasses
 
@@ -123,7 +125,7 @@ def test_model_generator_with_free_helicities_agrees_with_oracle():
     e.close()
 
 
-def test_calls_without_free_helicity_support_refuse_them():
+def test_models_without_free_helicity_support_are_refused():
     res = W.model("full_zfree")
     e = kpsi.Engine(0, "fp64")
     e.set_model(K, res)
@@ -131,9 +133,6 @@ def test_calls_without_free_helicity_support_refuse_them():
     e.load(kpsi.DATA, data)
     e.load(kpsi.NORM, mc)
     par = W.params(res, seed=5)
-    with pytest.raises(kpsi.KpsiError):
-        e.set_flavour(np.ones(500))
-    assert np.isfinite(e.nll(par))          # the context is still usable
     # two Z with one free, and a free K*, are rejected by set_model
     z2 = dataclasses.replace(W.Z4240)
     with pytest.raises(kpsi.KpsiError):
@@ -141,6 +140,7 @@ def test_calls_without_free_helicity_support_refuse_them():
     bad = [dataclasses.replace(W.KSTAR892, hel_free=True)]
     with pytest.raises(kpsi.KpsiError):
         e.set_model(K, bad)
+    assert np.isfinite(e.nll(par))          # the context keeps its model
     e.close()
 
 
@@ -204,4 +204,39 @@ def test_free_helicities_with_the_background_mixture(prec, tg):
     v, g = e.nll_and_grad(par)
     check_nll(v, ref, prec, data.shape[1], "free Z mixture")
     check_grad(g[dirs], gref, prec, "free Z mixture", norm=tg)
+    e.close()
+
+
+@pytest.mark.parametrize("prec,w,cached,tg", [("fp64", 0.06, False, 1e-9), ("fp32", 0.06, False, None),
+                                              ("fp64", 0.04, True, 1e-9), ("fp32", 0.04, True, None)])
+def test_free_helicities_with_flavour_tags(prec, w, cached, tg):
+    res = W.model("full_zfree")
+    data, mc = _sets(4099, 12007, 361)
+    eps_m = O.acceptance(W.acceptance_coefficients(), W.M_LO, W.M_HI, mc)
+    tag = np.where(np.random.default_rng(362).random(data.shape[1]) < 0.45, 1.0, -1.0)
+    e = _engine(prec, res, data, mc)
+    e.set_efficiency_values(eps_m)
+    e.set_flavour(tag, w)
+    if cached:
+        e.set_norm_cache(1)
+    par = W.params(res, seed=363) + 0.03 * W.free_mask(res, FLOAT)
+    dirs = np.flatnonzero(W.free_mask(res, FLOAT))
+    z = _z_offset(res)
+    pts = [par]
+    if cached:
+        p2 = par.copy()
+        p2[z + 4] += 0.08    # H'_{-1}: a couplings-only change, served by the matrix
+        p2[z + 3] -= 0.15
+        pts.append(p2)
+    for k, p in enumerate(pts):
+        st, ref, gref = O.nll_cc(K, res, p, data, tag, mc, w, eps_m, dirs)
+        assert st == 0
+        v, g = e.nll_and_grad(p)
+        label = f"free Z tags w={w}{' cached' if cached else ''} {k}"
+        check_nll(v, ref, prec, data.shape[1], label)
+        check_grad(g[dirs], gref, prec, label, norm=tg)
+        check_nll(e.nll(p), ref, prec, data.shape[1], label + " nll-only")
+    if cached:
+        b, h, _ = e.norm_cache_stats()
+        assert b == 1 and h >= 2
     e.close()

@@ -886,22 +886,27 @@ def test_conjugate_density_of_the_z_chain_alone_is_phi_even_and_the_full_model_i
 
 
 def _swap_helicities(res, par):
-    """The lambda = -1 and lambda = +1 couplings of every K* of spin >= 1 exchanged."""
+    """The lambda = -1 and lambda = +1 couplings of every K* of spin >= 1 exchanged, and
+    H'_{+1} and H'_{-1} of a Z whose helicities are free (order lambda' = 0, +1, -1)."""
     p = np.array(par, dtype=float, copy=True)
     k = 0
     for r in res:
-        if r.n_coup == 3:
+        if r.chain == W.KSTAR and r.n_coup == 3:
             p[k:k + 2], p[k + 4:k + 6] = par[k + 4:k + 6], par[k:k + 2]
+        elif r.chain == W.ZCHAIN and r.hel_free:
+            p[k + 2:k + 4], p[k + 4:k + 6] = par[k + 4:k + 6], par[k + 2:k + 4]
         k += 2 * r.n_coup
     return p
 
 
-@pytest.mark.parametrize("model", ["full", "full2z", "lass_full2z"])
+@pytest.mark.parametrize("model", ["full", "full2z", "lass_full2z", "full_zfree"])
 def test_reversing_phi_exchanges_the_kstar_helicity_couplings(model):
     # d^1_{lambda xi} = (-1)^(lambda - xi) d^1_{-lambda,-xi} and d^J_{-lambda 0} = (-1)^lambda d^J_{lambda 0}
     # turn e^{-i lambda phi} into the opposite helicity: a_xi(-phi; H) = -a_{-xi}(phi; H') with
     # H'_lambda = H_{-lambda} for the K* chain, and the Z-chain terms of xi = +-1 swap with the
-    # same sign (Eq. 11), so S(-phi; H) = S(phi; H') event by event.
+    # same sign: with Eq. 11 the Z couplings stay, with free Z helicities H'_{+1} and H'_{-1}
+    # exchange too (the Z angular factors conjugate: Zang[l'][xi] -> -Zang[-l'][-xi]), so
+    # S(-phi; H) = S(phi; H') event by event.
     res = W.model(model)
     par = W.params(res, seed=9)
     ev = W.neutral_events(200, 73)
