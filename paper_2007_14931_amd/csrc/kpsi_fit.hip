@@ -132,7 +132,23 @@ bool spd_inverse(std::vector<double>& A, int n) {
   return true;
 }
 
-kpsi_status hesse_impl(Problem& p, const std::vector<double>& x, double up, double* cov, bool* pd) {
+// Inverse of H + tau I for the smallest tau in {0, 1e-6, 1e-5, ..., 10} x max |H_ii| for which the
+// shifted matrix is positive definite (MINUIT's positive-definite forcing); false if none is.
+bool forced_pd_inverse(const std::vector<double>& H, int n, std::vector<double>& inv) {
+  double dmax = 0.0;
+  for (int i = 0; i < n; ++i) dmax = std::max(dmax, std::fabs(H[(size_t)i * n + i]));
+  if (!(dmax > 0.0) || !std::isfinite(dmax)) dmax = 1.0;
+  for (int k = -7; k <= 1; ++k) {
+    const double tau = k < -6 ? 0.0 : dmax * std::pow(10.0, k);
+    inv = H;
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] += tau;
+    if (spd_inverse(inv, n)) return true;
+  }
+  return false;
+}
+
+kpsi_status hesse_impl(Problem& p, const std::vector<double>& x, double up, double* cov, bool* pd,
+                       std::vector<double>* hraw = nullptr) {
   const int n = p.n();
   std::vector<double> H((size_t)n * n, 0.0);
   if (p.analytic) {
@@ -176,6 +192,7 @@ kpsi_status hesse_impl(Problem& p, const std::vector<double>& x, double up, doub
     }
   }
   // covariance of the parameters for an NLL scale with error definition `up`: 2 up H^-1
+  if (hraw) *hraw = H;
   *pd = spd_inverse(H, n);
   if (cov) for (size_t k = 0; k < H.size(); ++k) cov[k] = *pd ? 2.0 * up * H[k] : NAN;
   return KPSI_OK;
@@ -294,7 +311,8 @@ restart:
     // minimum; recompute EDM with the numerical Hessian and continue from it if needed.
     bool pd = false;
     Hm.assign((size_t)n * n, 0.0);
-    st = hesse_impl(p, x, up, Hm.data(), &pd);
+    std::vector<double> Hraw;
+    st = hesse_impl(p, x, up, Hm.data(), &pd, &Hraw);
     if (st) return st;
     if (pd) {
       have_cov = true;
@@ -312,7 +330,24 @@ restart:
         goto restart;
       }
     } else {
+      // The numerical Hessian is not positive definite.  The variable-metric estimate may have
+      // stopped the search early (it can understate the distance to the minimum far from it):
+      // with the Hessian forced positive definite, continue if the distance it predicts is
+      // above the target; otherwise (a saddle or a flat direction) report status 3.
+      std::vector<double> Vf;
       status = 3;
+      if (restarts < 3 && p.budget() && forced_pd_inverse(Hraw, n, Vf)) {
+        double e2 = 0.0;
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) e2 += g[i] * Vf[(size_t)i * n + j] * g[j];
+        edm = 0.5 * e2;
+        if (edm >= edm_target) {
+          ++restarts;
+          V = Vf;
+          status = 1;
+          goto restart;
+        }
+      }
     }
   }
   r->fmin = fx;
