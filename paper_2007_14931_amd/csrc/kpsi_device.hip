@@ -779,8 +779,9 @@ __global__ __launch_bounds__(256, (AmpWaves<T, Sh, MODE>::v)) void amp_kernel(co
             WZ1 = Cx<T>{za[4] * bp_.re - z5 * bp_.im + za[6] * bm_.re - z7 * bm_.im,
                         za[4] * bp_.im + z5 * bp_.re + za[6] * bm_.im + z7 * bm_.re};
           };
-          // (free helicities) WZ_{-1} from the l' = -1 factors, same form
-          auto wz2 = [&](T f, const Cx<T>& bp_, const Cx<T>& bm_) -> Cx<T> {
+          // (free helicities) WZ_{-1} from the l' = -1 factors, same form; a generic lambda, so
+          // that its body exists only in the instantiations that call it (za has 12 entries there)
+          auto wz2 = [&](auto f, const auto& bp_, const auto& bm_) -> Cx<T> {
             const T z9 = f * za[9], z11 = f * za[11];
             return Cx<T>{za[8] * bp_.re - z9 * bp_.im + za[10] * bm_.re - z11 * bm_.im,
                          za[8] * bp_.im + z9 * bp_.re + za[10] * bm_.im + z11 * bm_.re};
