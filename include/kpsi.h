@@ -19,10 +19,12 @@
  *    reloaded; the library never frees them.
  *  - All device work runs on the context's stream (the one given to kpsi_create, or a
  *    stream the library creates).  Calls returning results to the host wait once for the
- *    work they enqueued: kpsi_nll and kpsi_nll_and_grad poll a completion word that the
- *    stream writes into pinned host memory after their last kernel (bounded at 50 ms, then
- *    a stream synchronize, which also reports kernel errors); the others synchronize the
- *    stream.  When a call returns, the work it enqueued has completed.  A context is not
+ *    work they enqueued: kpsi_nll, kpsi_nll_and_grad and its _noalloc form poll the values
+ *    their final reduction stores into pinned host memory (each marked pending beforehand;
+ *    bounded at 50 ms, then a stream synchronize, which also reports kernel errors); the
+ *    others synchronize the stream.  When a call returns, its results are written and every
+ *    kernel it enqueued has made its last memory access (the reduction's final kernel may
+ *    still be retiring; later work on the stream is ordered after it).  A context is not
  *    thread-safe; separate contexts are independent.
  *
  * Observables (Eq. 1, with theta_K* in place of m_J/psi pi, which it determines at

@@ -93,15 +93,12 @@ struct kpsi_ctx {
   std::vector<double> norm_w_host;
   double* partial = nullptr;
   size_t partial_cap = 0;       // in doubles
-  // Completion flag of a call: the stream writes done_seq into done_host (mapped pinned memory)
-  // after the call's last kernel, and the host polls it instead of blocking in the runtime.
-  uint64_t* done_host = nullptr;
-  uint64_t* done_dev = nullptr;
-  uint64_t done_seq = 0;
-  bool done_flag = false;       // the stream write is available (else: stream synchronize)
   double* red = nullptr;        // device view of red_host
-  double* red_host = nullptr;   // [3][NACC], mapped pinned host memory: data, normalisation,
-                                // and the normalisation read with phi reversed (flavour tags)
+  double* red_host = nullptr;   // [3][NACC], mapped pinned host memory (fine-grained, so the
+                                // reduction's stores reach it as they are made): data,
+                                // normalisation, and the normalisation read with phi reversed
+                                // (flavour tags).  A call marks the values its reduction writes
+                                // with kPending and polls them (wait_results).
   double* red_dev = nullptr;    // [3][NACC] device copy of the normalisation records 1, 2 (mixture)
   // Gaussian constraints on parameters (kpsi_set_constraints): position, mean, sigma
   std::vector<int> con_idx;
@@ -746,31 +743,43 @@ kpsi_status put_cached_record(kpsi_ctx* c, const double* params) {
 }
 
 // ---------------------------------------------------------------- per-call driver
-// Wait for the work enqueued on the context stream.  With the completion flag, the stream writes
-// a new sequence number into mapped pinned memory after the last kernel and the host polls that
-// word: a call returns a few microseconds sooner than through a blocking stream synchronize.  The
-// poll is bounded (50 ms); past it, or when the flag write is unavailable or fails, the stream is
-// synchronized, which also reports any error of the call's kernels.
-kpsi_status wait_stream(kpsi_ctx* c) {
-  if (c->done_flag) {
-    const uint64_t want = ++c->done_seq;
-    if (hipStreamWriteValue64(c->stream, c->done_dev, want, 0) == hipSuccess) {
-      const auto t0 = std::chrono::steady_clock::now();
-      for (unsigned k = 1;; ++k) {
-        // acquire: the reduced record the GPU wrote before the sequence number is read after it
-        if (__atomic_load_n(c->done_host, __ATOMIC_ACQUIRE) == want) {
-          // a launch error of this call's kernels (their asynchronous faults stop the stream,
-          // so the word never changes and the synchronisation below reports them)
-          const hipError_t le = hipGetLastError();
-          if (le != hipSuccess) return fail(c, KPSI_E_HIP, "kernel launch: %s", hipGetErrorString(le));
-          return KPSI_OK;
-        }
-        if ((k & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) break;
+// Bit pattern of a result value not yet written: a NaN payload that no arithmetic produces
+// (operations on NaN inputs return them with their payload, and the inputs here are computed).
+constexpr uint64_t kPending = 0x7ff4c0de5e9d0001ull;
+
+static uint64_t* result_word(kpsi_ctx* c, int k) { return reinterpret_cast<uint64_t*>(c->red_host) + k; }
+
+// Mark the values the final reduction of this call will write: sets [first, first + nsets) of
+// nv values each.  Called before the reduction is enqueued; the previous call's reduction has
+// written all its values by then (its wait saw them), so nothing else writes these words.
+static void mark_pending(kpsi_ctx* c, int first, int nsets, int nv) {
+  for (int s = first; s < first + nsets; ++s)
+    for (int v = 0; v < nv; ++v) __atomic_store_n(result_word(c, s * NACC + v), kPending, __ATOMIC_RELAXED);
+}
+
+// Wait for a call: the final reduction's blocks each store one value into the fine-grained
+// mapped result buffer, and the call is complete when every marked value has been replaced.
+// Each is one aligned 8-byte store, read here as one 8-byte load, so a value is either pending
+// or whole.  The poll is bounded (50 ms; a long call or a faulted kernel): past it the stream
+// is synchronized, which also reports any error of the call's kernels.
+kpsi_status wait_results(kpsi_ctx* c, int first, int nsets, int nv) {
+  const auto t0 = std::chrono::steady_clock::now();
+  int s = first, v = 0;
+  for (unsigned k = 1;; ++k) {
+    while (s < first + nsets && __atomic_load_n(result_word(c, s * NACC + v), __ATOMIC_ACQUIRE) != kPending) {
+      if (++v == nv) {
+        v = 0;
+        ++s;
       }
-    } else {
-      (void)hipGetLastError();
-      c->done_flag = false;
     }
+    if (s == first + nsets) {
+      // a launch error of this call's kernels (their asynchronous faults stop the stream, so the
+      // values never arrive and the synchronisation below reports them)
+      const hipError_t le = hipGetLastError();
+      if (le != hipSuccess) return fail(c, KPSI_E_HIP, "kernel launch: %s", hipGetErrorString(le));
+      return KPSI_OK;
+    }
+    if ((k & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) break;
   }
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   return KPSI_OK;
@@ -881,14 +890,12 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   }
   if (st) return st;
   if (c->timing || c->bench_reps > 0) hipEventRecord(c->ev1, c->stream);   // end of the per-event work
-  if (mode != MODE_DENSITY) {
-    hipError_t e = launch_reduce_final(part, nbd, nbm, nmsets, nv, c->red, nd > 0 ? 0 : 1,
-                                       (nd > 0) + (nm > 0) * nmsets, c->stream);
-    if (e != hipSuccess) return fail(c, KPSI_E_HIP, "reduction kernel: %s", hipGetErrorString(e));
-  }
-  if (st) return st;
   if (mode == MODE_DENSITY) return KPSI_OK;
-  if (kpsi_status ws = wait_stream(c)) return ws;
+  const int first_set = nd > 0 ? 0 : 1, nsets = (nd > 0) + (nm > 0) * nmsets;
+  mark_pending(c, first_set, nsets, nv);
+  hipError_t e = launch_reduce_final(part, nbd, nbm, nmsets, nv, c->red, first_set, nsets, c->stream);
+  if (e != hipSuccess) return fail(c, KPSI_E_HIP, "reduction kernel: %s", hipGetErrorString(e));
+  if (kpsi_status ws = wait_results(c, first_set, nsets, nv)) return ws;
   if (c->bench_reps > 0) {
     float ms = 0.f;
     if (hipEventSynchronize(c->ev1) != hipSuccess || hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess)
@@ -968,14 +975,8 @@ kpsi_status kpsi_create(int device, void* stream, kpsi_precision prec, kpsi_ctx*
     }
     c->own_stream = true;
   }
-  if (hipHostMalloc((void**)&c->done_host, 64, hipHostMallocMapped) == hipSuccess &&
-      hipHostGetDevicePointer((void**)&c->done_dev, c->done_host, 0) == hipSuccess) {
-    *c->done_host = 0;
-    c->done_flag = true;
-  } else {
-    (void)hipGetLastError();
-  }
-  if (hipHostMalloc(&c->red_host, 3 * NACC * sizeof(double), hipHostMallocMapped) != hipSuccess ||
+  if (hipHostMalloc(&c->red_host, 3 * NACC * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
       hipHostGetDevicePointer((void**)&c->red, c->red_host, 0) != hipSuccess ||
       hipMalloc(&c->red_dev, 3 * NACC * sizeof(double)) != hipSuccess) {
     kpsi_destroy(c);
@@ -1004,7 +1005,6 @@ kpsi_status kpsi_destroy(kpsi_ctx* c) {
   if (c->cache_partial) hipFree(c->cache_partial);
   if (c->cache_out) hipFree(c->cache_out);
   if (c->red_host) hipHostFree(c->red_host);
-  if (c->done_host) hipHostFree(c->done_host);
   if (c->red_dev) hipFree(c->red_dev);
   if (c->eps_data) hipFree(c->eps_data);
   if (c->bkg_data) hipFree(c->bkg_data);
