@@ -196,6 +196,21 @@ class Engine:
         self.n = [0, 0]
         self._out = C.c_double()
         self._out_addr = C.addressof(self._out)
+        self._bufs(0)
+
+    def _bufs(self, n: int) -> None:
+        # parameter and gradient buffers of the per-call entry points, with their addresses taken
+        # once (reading an array's address through numpy costs more than the call itself)
+        self._pbuf = np.zeros(n)
+        self._gbuf = np.zeros(n)
+        self._pbuf_addr = self._pbuf.ctypes.data
+        self._gbuf_addr = self._gbuf.ctypes.data
+
+    def _put(self, params) -> int:
+        if np.shape(params) != self._pbuf.shape:
+            raise ValueError(f"expected {self._pbuf.size} parameters, got shape {np.shape(params)}")
+        self._pbuf[...] = params
+        return self._pbuf_addr
 
     def close(self):
         if getattr(self, "h", None):
@@ -220,6 +235,7 @@ class Engine:
         self._chk(self.L.kpsi_n_params(self.h, C.byref(n)))
         self.n_params = n.value
         self.n_res = len(res)
+        self._bufs(self.n_params)
 
     def set_floating(self, flags) -> None:
         f = np.ascontiguousarray(flags, dtype=np.int32)
@@ -264,28 +280,23 @@ class Engine:
         self._chk(self.L.kpsi_set_norm_mixture(self.h, _dp(p), int(n_flat)))
 
     def nll(self, params) -> float:
-        p = _f64(params)
-        st = self.L.kpsi_nll(self.h, p.ctypes.data, self._out_addr)
+        st = self.L.kpsi_nll(self.h, self._put(params), self._out_addr)
         if st:
             self._chk(st)
         return self._out.value
 
     def nll_and_grad(self, params) -> tuple[float, np.ndarray]:
-        p = _f64(params)
-        g = np.empty(self.n_params)
-        st = self.L.kpsi_nll_and_grad(self.h, p.ctypes.data, self._out_addr, g.ctypes.data)
+        st = self.L.kpsi_nll_and_grad(self.h, self._put(params), self._out_addr, self._gbuf_addr)
         if st:
             self._chk(st)
-        return self._out.value, g
+        return self._out.value, self._gbuf.copy()
 
     def nll_and_grad_noalloc(self, params) -> tuple[float, np.ndarray]:
         """kpsi_nll_and_grad_noalloc: the same pass with no device allocation (static scratch)."""
-        p = _f64(params)
-        g = np.empty(self.n_params)
-        st = self.L.kpsi_nll_and_grad_noalloc(self.h, p.ctypes.data, self._out_addr, g.ctypes.data)
+        st = self.L.kpsi_nll_and_grad_noalloc(self.h, self._put(params), self._out_addr, self._gbuf_addr)
         if st:
             self._chk(st)
-        return self._out.value, g
+        return self._out.value, self._gbuf.copy()
 
     def nll_status(self, params, grad: bool = False) -> tuple[int, float]:
         """Raw status and value (for error-path tests)."""
