@@ -944,7 +944,16 @@ __global__ __launch_bounds__(256) void reduce_final(const double* __restrict__ p
   const int nb = set ? nb_mc : nb_data;
   const double* __restrict__ p = partial + (int64_t)v * nbt + b0;
   double s = 0.0, c = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 256) neumaier(s, c, p[b]);
+  // blocks tid, tid + 256, ... in that order; four loads are issued before their sums, so a
+  // thread waits for memory once per four values rather than once per value
+  for (int b0 = threadIdx.x; b0 < nb; b0 += 4 * 256) {
+    double x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = b0 + k * 256 < nb ? p[b0 + k * 256] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (b0 + k * 256 < nb) neumaier(s, c, x[k]);
+  }
   // butterfly of exact two-sum merges in each wavefront (every lane ends with the wavefront's
   // total), then the four wavefronts in order
 #pragma unroll
