@@ -64,6 +64,7 @@ struct DevSet {
 
 std::string g_create_error;
 constexpr size_t kTimingSamples = 65536;   // timed kernel durations kept for the median
+constexpr int kTimingPairs = 64;            // timed calls whose events are read together
 
 }  // namespace
 
@@ -119,6 +120,10 @@ struct kpsi_ctx {
   int timing_every = 0;          // time every k-th call (0: off)
   int64_t timing_calls = 0;      // calls since timing was set
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // event pairs of the timed calls (kpsi_set_timing), read when all are used or when the
+  // timings are asked for, so that a timed call does not wait for its events
+  std::vector<hipEvent_t> tev;
+  int t_pend = 0;                // recorded pairs not yet read
   double t_ms = 0.0;
   int64_t t_n = 0;
   std::vector<float> t_samples;  // the first kTimingSamples timed durations since the last reset
@@ -742,6 +747,23 @@ kpsi_status put_cached_record(kpsi_ctx* c, const double* params) {
   return KPSI_OK;
 }
 
+// Read the recorded event pairs of timed calls (each waits on its end event first: the runtime
+// can mark an event complete after the call that recorded it has seen its results).
+static void drain_timing(kpsi_ctx* c) {
+  for (int i = 0; i < c->t_pend; ++i) {
+    float ms = 0.f;
+    if (hipEventSynchronize(c->tev[2 * i + 1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]) == hipSuccess) {
+      c->t_ms += ms;
+      c->t_n += 1;
+      if (c->t_samples.size() < kTimingSamples) c->t_samples.push_back(ms);
+    } else {
+      c->t_dropped += 1;
+    }
+  }
+  c->t_pend = 0;
+}
+
 // ---------------------------------------------------------------- per-call driver
 // Bit pattern of a result value not yet written: a NaN payload that no arithmetic produces
 // (operations on NaN inputs return them with their payload, and the inputs here are computed).
@@ -810,7 +832,10 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   }
   c->timing = !fixed && c->bench_reps == 0 && mode != MODE_DENSITY && c->timing_every > 0 &&
               (c->timing_calls++ % c->timing_every) == 0;
-  if (c->timing) hipEventRecord(c->ev0, c->stream);
+  if (c->timing) {
+    if (c->t_pend == kTimingPairs) drain_timing(c);
+    hipEventRecord(c->tev[2 * c->t_pend], c->stream);
+  }
   // Launches over the events of [nd data, nm normalisation] write block partials (rows of
   // nbd + nbm blocks, data first); one reduction then writes the record of each set covered
   // (by the GPU straight into mapped pinned host memory).
@@ -889,7 +914,9 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
   }
   }
   if (st) return st;
-  if (c->timing || c->bench_reps > 0) hipEventRecord(c->ev1, c->stream);   // end of the per-event work
+  // end of the per-event work
+  if (c->bench_reps > 0) hipEventRecord(c->ev1, c->stream);
+  else if (c->timing) hipEventRecord(c->tev[2 * c->t_pend + 1], c->stream);
   if (mode == MODE_DENSITY) return KPSI_OK;
   const int first_set = nd > 0 ? 0 : 1, nsets = (nd > 0) + (nm > 0) * nmsets;
   mark_pending(c, first_set, nsets, nv);
@@ -903,18 +930,7 @@ kpsi_status run_amp(kpsi_ctx* c, int mode, const double* par, int which /*-1: bo
     c->bench_ms = (double)ms / reps;
     return KPSI_OK;
   }
-  if (c->timing) {
-    // the polled completion word can change before the runtime marks ev1 complete: wait for it,
-    // so that no timed sample is lost
-    float ms = 0.f;
-    if (hipEventSynchronize(c->ev1) == hipSuccess && hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) {
-      c->t_ms += ms;
-      c->t_n += 1;
-      if (c->t_samples.size() < kTimingSamples) c->t_samples.push_back(ms);
-    } else {
-      c->t_dropped += 1;
-    }
-  }
+  if (c->timing) ++c->t_pend;   // read later (drain_timing)
   return KPSI_OK;
 }
 
@@ -1009,6 +1025,8 @@ kpsi_status kpsi_destroy(kpsi_ctx* c) {
   if (c->eps_data) hipFree(c->eps_data);
   if (c->bkg_data) hipFree(c->bkg_data);
   if (c->tag) hipFree(c->tag);
+  for (hipEvent_t e : c->tev)
+    if (e) hipEventDestroy(e);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -1862,6 +1880,18 @@ kpsi_status kpsi_time_kernel(kpsi_ctx* c, const double* params, int grad, int re
 kpsi_status kpsi_set_timing(kpsi_ctx* c, int every) {
   if (!c) return KPSI_E_ARG;
   if (every < 0) return fail(c, KPSI_E_ARG, "timing interval %d < 0", every);
+  drain_timing(c);
+  if (every > 0 && c->tev.empty()) {
+    std::vector<hipEvent_t> ev(2 * kTimingPairs, nullptr);
+    for (hipEvent_t& e : ev) {
+      if (hipEventCreate(&e) != hipSuccess) {
+        for (hipEvent_t x : ev)
+          if (x) hipEventDestroy(x);
+        return fail(c, KPSI_E_HIP, "timing events");
+      }
+    }
+    c->tev = std::move(ev);
+  }
   c->timing_every = every;
   c->timing_calls = 0;
   c->timing = false;
@@ -1870,6 +1900,7 @@ kpsi_status kpsi_set_timing(kpsi_ctx* c, int every) {
 
 kpsi_status kpsi_timing(kpsi_ctx* c, double* ms, int64_t* n, int reset) {
   if (!c) return KPSI_E_ARG;
+  drain_timing(c);
   if (ms) *ms = c->t_ms;
   if (n) *n = c->t_n;
   if (reset) { c->t_ms = 0.0; c->t_n = 0; c->t_dropped = 0; c->t_samples.clear(); }
@@ -1878,6 +1909,7 @@ kpsi_status kpsi_timing(kpsi_ctx* c, double* ms, int64_t* n, int reset) {
 
 kpsi_status kpsi_timing_median(kpsi_ctx* c, double* ms) {
   if (!c || !ms) return KPSI_E_ARG;
+  drain_timing(c);
   std::vector<float> v = c->t_samples;
   if (v.empty()) { *ms = NAN; return KPSI_OK; }
   std::sort(v.begin(), v.end());

@@ -287,3 +287,9 @@ def test_kernel_timing_samples_every_kth_call_and_reports_the_median():
     e.set_timing(False)
     e.nll_and_grad(par)
     assert e.timing()[1] == 0
+    # more timed calls than the library keeps event pairs for between reads
+    e.set_timing(1)
+    for _ in range(150):
+        e.nll_and_grad(par)
+    ms, n = e.timing()
+    assert n == 150 and 0.0 < e.timing_median() <= ms / 100
