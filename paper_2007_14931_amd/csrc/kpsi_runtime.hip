@@ -991,9 +991,15 @@ kpsi_status kpsi_create(int device, void* stream, kpsi_precision prec, kpsi_ctx*
     }
     c->own_stream = true;
   }
+  // fine-grained where the system has it (each value is seen as the reduction stores it);
+  // otherwise the values appear when the reduction kernel ends, and the poll still works
   if (hipHostMalloc(&c->red_host, 3 * NACC * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
-          hipSuccess ||
-      hipHostGetDevicePointer((void**)&c->red, c->red_host, 0) != hipSuccess ||
+      hipSuccess) {
+    (void)hipGetLastError();
+    c->red_host = nullptr;
+    if (hipHostMalloc(&c->red_host, 3 * NACC * sizeof(double), hipHostMallocMapped) != hipSuccess) c->red_host = nullptr;
+  }
+  if (!c->red_host || hipHostGetDevicePointer((void**)&c->red, c->red_host, 0) != hipSuccess ||
       hipMalloc(&c->red_dev, 3 * NACC * sizeof(double)) != hipSuccess) {
     kpsi_destroy(c);
     return fail(nullptr, KPSI_E_OOM, "result buffers");
