@@ -136,3 +136,27 @@ def test_time_kernel_reports_a_duration_and_leaves_results_unchanged():
     with pytest.raises(kpsi.KpsiError):
         e.time_kernel(par, reps=0)
     e.close()
+
+
+def test_call_longer_than_the_result_poll_bound_returns_the_same_results():
+    """A call whose device work outlasts the 50 ms bound on polling its results (here 4000
+    back-to-back launches of the per-event work over 1.2e6 events, kpsi_time_kernel) falls back
+    to a stream synchronisation and still returns; later calls give the same results."""
+    import torch
+    res = W.model("full")
+    par = W.params(res, seed=84) + 0.04 * W.free_mask(res, FLOAT)
+    g = kpsi.Engine(0, "fp64")
+    g.set_model(K, res)
+    mc = g.generate_phsp(85, 1_000_000, W.PHSP_WMAX)
+    data = g.generate_phsp(86, 200_000, W.PHSP_WMAX)
+    torch.cuda.synchronize()
+    g.close()
+    e = _engine("fp32", res, data, mc)
+    v0, g0 = e.nll_and_grad(par)
+    ms = e.time_kernel(par, grad=True, reps=4000)
+    print(f"[paths] 4000 launches: {ms * 4000:.1f} ms of per-event work", flush=True)
+    assert 0.0 < ms < 1.0
+    v1, g1 = e.nll_and_grad(par)
+    fin = np.isfinite(g0)
+    assert v1 == v0 and np.array_equal(g1[fin], g0[fin])
+    e.close()
