@@ -293,3 +293,33 @@ def test_kernel_timing_samples_every_kth_call_and_reports_the_median():
         e.nll_and_grad(par)
     ms, n = e.timing()
     assert n == 150 and 0.0 < e.timing_median() <= ms / 100
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", None)])
+@pytest.mark.parametrize("nd,nm", [(1, 1), (2, 3), (255, 257), (3072, 3073)])
+def test_tiny_and_block_edge_sets_match_oracle(prec, tol, nd, nm):
+    """Degenerate sizes: one event per set, sets smaller than a wavefront, and sizes one past a
+    whole number of 256-thread block passes; NLL and gradient of the full model with two floating
+    lineshapes against the oracle."""
+    floating = ("K*(1410)", "Z(4430)")
+    e, res = _engine("full", prec, floating)
+    par = W.params(res, seed=29) + 0.05 * W.free_mask(res, floating)
+    data, mc = _sets(nd, nm, seed=31, edges=False)
+    data = _interior(data)
+    e.load(kpsi.DATA, data)
+    e.load(kpsi.NORM, mc)
+    dirs = np.flatnonzero(W.free_mask(res, floating))
+    st, ref_v, ref_g = O.nll(K, res, par, data, mc, dirs=dirs)
+    assert st == 0
+    v, g = e.nll_and_grad(par)
+    check_nll(v, ref_v, prec, nd, f"{nd}+{nm}")
+    check_grad(g[dirs], ref_g, prec, f"{nd}+{nm}", norm=tol)
+    check_nll(e.nll(par), ref_v, prec, nd, f"{nd}+{nm} nll-only")
+
+
+def test_empty_set_is_refused():
+    e, res = _engine("full", "fp32")
+    with pytest.raises(kpsi.KpsiError):
+        e.load(kpsi.DATA, np.zeros((4, 0)))
+    st, _ = e.nll_status(W.params(res))
+    assert st == kpsi.KPSI_E_STATE                 # nothing loaded: the call reports the state
