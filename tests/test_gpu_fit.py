@@ -181,3 +181,51 @@ def test_full_model_fits_from_far_starts_reach_the_minimum_or_report_failure():
                 assert r.fmin > rt.fmin + 1.0, (seed, r.as_dict())
         reached += ok == 2
     assert reached >= 2
+
+
+def test_full_model_gpu_minimum_is_the_oracle_minimum():
+    """The full model (54 free parameters, K*(1410) and Z(4430) masses and widths floating) on
+    8e3 data and 2.4e4 normalisation events.  The FP32-adjoint fit with its FP64 polish, from the
+    generated point, ends at a minimum of the FP64 oracle's likelihood: there the oracle's NLL
+    equals the fit's, the distance to the minimum that the oracle's own gradient predicts (with
+    the fit's HESSE covariance) is below 1e-3, and an independent minimiser (scipy BFGS with the
+    oracle's dual-number gradient) started there moves by less than 0.05 sigma and finds nothing
+    lower.  The same minimiser started at the generated point ends no lower either."""
+    import time
+    res = W.model("full")
+    floating = ("K*(1410)", "Z(4430)")
+    truth = W.params(res, seed=11)
+    smax = _smax(res, truth, 320)
+    data, _, nover = O.gen_model(K, res, truth, 321, 8_000, W.PHSP_WMAX, smax)
+    assert nover == 0
+    mc = O.gen_phsp(K, 322, 24_000, W.PHSP_WMAX)
+    mask = W.free_mask(res, floating)
+    free = np.flatnonzero(mask)
+    xa, _, ra = _engine(res, "fp32", data, mc, floating).migrad(truth, mask, gradient=1)
+    xp, cp, rp = _engine(res, "fp64", data, mc, floating).migrad(xa, mask, gradient=1)
+    assert rp.status == 0, (ra.as_dict(), rp.as_dict())
+
+    def f(z):
+        p = truth.copy()
+        p[free] = z
+        st, v, g = O.nll(K, res, p, data, mc, dirs=free)
+        return (v, g) if st == 0 else (np.inf, np.zeros_like(z))
+
+    v, g = f(xp[free])
+    edm = 0.25 * float(g @ cp @ g)   # cov = 2 H^-1 (UP = 1): EDM = g^T H^-1 g / 2
+    print(f"[fit] GPU fp32 {ra.wall_seconds:.3f} s + fp64 polish {rp.wall_seconds:.3f} s: fmin {rp.fmin:.6f}; "
+          f"oracle there {v:.6f}, EDM from the oracle gradient {edm:.2e}", flush=True)
+    assert v == pytest.approx(rp.fmin, rel=1e-10) and edm < 1e-3
+    sig = np.sqrt(np.diag(cp))
+    o = optimize.minimize(f, xp[free], jac=True, method="BFGS", options={"gtol": 1e-5, "maxiter": 200})
+    xo = truth.copy()
+    xo[free] = o.x
+    dev = np.abs(W.canonical(res, xp)[free] - W.canonical(res, xo)[free]) / sig
+    print(f"[fit] oracle BFGS from the GPU minimum: {o.nit} iterations, fmin {o.fun:.6f}, largest move "
+          f"{dev.max():.4f} sigma", flush=True)
+    assert dev.max() < 0.05 and o.fun > rp.fmin - 1e-3
+    t0 = time.perf_counter()
+    o2 = optimize.minimize(f, truth[free], jac=True, method="BFGS", options={"gtol": 1e-5, "maxiter": 2000})
+    print(f"[fit] oracle BFGS from the generated point: {o2.nit} iterations, {time.perf_counter() - t0:.1f} s, "
+          f"fmin {o2.fun:.6f} ({o2.message})", flush=True)
+    assert o2.fun > rp.fmin - 1e-3
