@@ -39,7 +39,8 @@ def _engine(prec, res, data, mc, eps_m, floating=()):
 @pytest.mark.parametrize("model,prec,w,tg", [
     ("full", "fp64", 0.0, 1e-9), ("full", "fp64", 0.06, 1e-9), ("kstar10", "fp64", 0.06, 1e-9),
     ("full", "fp32", 0.0, None), ("full", "fp32", 0.06, None), ("kstar10", "fp32", 0.06, None),
-    ("lass_full2z", "fp64", 0.04, 1e-9)])
+    ("lass_full2z", "fp64", 0.04, 1e-9), ("lass_full2z", "fp32", 0.04, None), ("full2z", "fp64", 0.06, 1e-9),
+    ("full2z", "fp32", 0.06, None)])
 def test_cc_nll_and_gradient_match_oracle(model, prec, w, tg):
     floating = ("K*(1410)", "Z(4430)") if model == "full" else ("K*(1410)",)
     res, data, mc, eps_m, tag = _inputs(model)
