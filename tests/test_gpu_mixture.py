@@ -15,8 +15,8 @@ pytestmark = pytest.mark.gpu
 FLOAT = ("K*(1410)", "Z(4430)")
 
 
-def _inputs(nd=5003, nm=20011):
-    res = W.model("full")
+def _inputs(nd=5003, nm=20011, model="full"):
+    res = W.model(model)
     data = W.neutral_events(nd, 51, peaked=True)
     data[0] = np.clip(data[0], W.M_LO + 1e-6, W.M_HI - 1e-6)
     mc = O.gen_phsp(K, 52, nm, W.PHSP_WMAX)
@@ -39,9 +39,12 @@ def _engine(prec, res, data, mc, eps_m):
     return e
 
 
-@pytest.mark.parametrize("prec,tg,cache", [("fp64", 1e-9, 0), ("fp64", 1e-9, 1), ("fp32", None, 0), ("fp32", None, 1)])
-def test_mixture_matches_oracle(prec, tg, cache):
-    res, data, mc, eps_d, eps_m, b_d, b_m = _inputs()
+@pytest.mark.parametrize("prec,tg,cache,model", [
+    ("fp64", 1e-9, 0, "full"), ("fp64", 1e-9, 1, "full"), ("fp32", None, 0, "full"), ("fp32", None, 1, "full"),
+    ("fp64", 1e-9, 0, "full2z"), ("fp32", None, 1, "full2z"), ("fp64", 1e-9, 1, "lass_full2z"),
+    ("fp32", None, 0, "lass_full2z")])
+def test_mixture_matches_oracle(prec, tg, cache, model):
+    res, data, mc, eps_d, eps_m, b_d, b_m = _inputs(model=model)
     e = _engine(prec, res, data, mc, eps_m)
     e.set_background(0.85, eps_d, b_d, b_m)
     e.set_norm_cache(cache)
@@ -51,7 +54,7 @@ def test_mixture_matches_oracle(prec, tg, cache):
     assert st == 0
     v, g = e.nll_and_grad(par)
     nd = data.shape[1]
-    tag = f"mixture cache={cache}"
+    tag = f"mixture {model} cache={cache}"
     check_nll(v, ref, prec, nd, tag)
     check_grad(g[free], gref, prec, tag, norm=tg)
     check_nll(e.nll(par), ref, prec, nd, tag + " nll-only")
