@@ -251,6 +251,18 @@ kpsi_status kpsi_fit_default_options(kpsi_fit_options* opts);
  * is 0. */
 kpsi_status kpsi_migrad(kpsi_ctx* ctx, double* params, const int* free_mask, const kpsi_fit_options* opts,
                         kpsi_fit_result* result, double* cov);
+/* kpsi_migrad with limits on the free parameters (MINUIT's transformations; the paper fits
+ * with MINUIT).  lower, upper: host arrays of kpsi_n_params doubles, or NULL for none; an entry
+ * that is not finite (NaN, +-inf) leaves that side open, and the entries of fixed parameters
+ * are ignored.  The minimiser works on an internal variable u per limited parameter:
+ * lo + (hi - lo)(sin u + 1)/2 with both limits, lo - 1 + sqrt(u^2 + 1) with a lower one,
+ * hi + 1 - sqrt(u^2 + 1) with an upper one, so every trial point lies inside its limits.
+ * cov is the internal covariance mapped with the derivatives of the transformations at the
+ * minimum (it shrinks towards zero for a parameter that ends at a limit).  KPSI_E_ARG if a
+ * lower limit is not below its upper one or the start is not strictly inside its limits. */
+kpsi_status kpsi_migrad_limited(kpsi_ctx* ctx, double* params, const int* free_mask, const double* lower,
+                                const double* upper, const kpsi_fit_options* opts, kpsi_fit_result* result,
+                                double* cov);
 /* Covariance 2 up H^-1 at params from a numerical Hessian (gradient differences in the
  * analytic mode, second differences of the NLL otherwise). */
 kpsi_status kpsi_hesse(kpsi_ctx* ctx, const double* params, const int* free_mask, const kpsi_fit_options* opts,

@@ -12,10 +12,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
-#include "kpsi.h"
+#include "kpsi_internal.h"
 
 namespace {
 
@@ -29,8 +30,38 @@ struct Problem {
   int64_t max_calls;
   std::vector<double> gfull;
 
+  // Limits (MINUIT's transformations): the minimiser works on an internal variable u per free
+  // parameter; a parameter limited on both sides is lo + (hi - lo)(sin u + 1)/2, one limited
+  // below is lo - 1 + sqrt(u^2 + 1), one limited above is hi + 1 - sqrt(u^2 + 1).
+  std::vector<int> kind;        // per free parameter: 0 none, 1 both, 2 below, 3 above
+  std::vector<double> lo, hi;
+
   int n() const { return (int)idx.size(); }
-  void put(const std::vector<double>& x) { for (int i = 0; i < n(); ++i) full[idx[i]] = x[i]; }
+  double ext(int i, double u) const {
+    switch (kind.empty() ? 0 : kind[i]) {
+      case 1: return lo[i] + 0.5 * (hi[i] - lo[i]) * (std::sin(u) + 1.0);
+      case 2: return lo[i] - 1.0 + std::sqrt(u * u + 1.0);
+      case 3: return hi[i] + 1.0 - std::sqrt(u * u + 1.0);
+      default: return u;
+    }
+  }
+  double dext(int i, double u) const {   // d ext / d u
+    switch (kind.empty() ? 0 : kind[i]) {
+      case 1: return 0.5 * (hi[i] - lo[i]) * std::cos(u);
+      case 2: return u / std::sqrt(u * u + 1.0);
+      case 3: return -u / std::sqrt(u * u + 1.0);
+      default: return 1.0;
+    }
+  }
+  double intl(int i, double x) const {   // the internal value of an external one inside its limits
+    switch (kind.empty() ? 0 : kind[i]) {
+      case 1: return std::asin(2.0 * (x - lo[i]) / (hi[i] - lo[i]) - 1.0);
+      case 2: { const double t = x - lo[i] + 1.0; return std::sqrt(t * t - 1.0); }
+      case 3: { const double t = hi[i] - x + 1.0; return std::sqrt(t * t - 1.0); }
+      default: return x;
+    }
+  }
+  void put(const std::vector<double>& x) { for (int i = 0; i < n(); ++i) full[idx[i]] = ext(i, x[i]); }
   bool budget() const { return n_nll + n_grad < max_calls; }
 
   // f(x); +inf when the point is rejected (non-finite density, unphysical mass or width)
@@ -56,7 +87,7 @@ struct Problem {
       kpsi_status st = kpsi_nll_and_grad(c, full.data(), &v, gfull.data());
       if (st == KPSI_E_NONFINITE || st == KPSI_E_ARG) return INFINITY;
       if (st != KPSI_OK) return NAN;
-      for (int i = 0; i < n(); ++i) g[i] = gfull[idx[i]];
+      for (int i = 0; i < n(); ++i) g[i] = gfull[idx[i]] * dext(i, x[i]);
       return v;
     }
     const double f0 = f(x);
@@ -198,7 +229,8 @@ kpsi_status hesse_impl(Problem& p, const std::vector<double>& x, double up, doub
   return KPSI_OK;
 }
 
-kpsi_status setup(Problem& p, kpsi_ctx* c, const double* params, const int* free_mask, const kpsi_fit_options* o) {
+kpsi_status setup(Problem& p, kpsi_ctx* c, const double* params, const int* free_mask, const kpsi_fit_options* o,
+                  const double* lower = nullptr, const double* upper = nullptr) {
   int np = 0;
   kpsi_status st = kpsi_n_params(c, &np);
   if (st) return st;
@@ -206,6 +238,32 @@ kpsi_status setup(Problem& p, kpsi_ctx* c, const double* params, const int* free
   p.full.assign(params, params + np);
   p.idx.clear();
   for (int i = 0; i < np; ++i) if (free_mask[i]) p.idx.push_back(i);
+  p.kind.clear();
+  if (lower || upper) {
+    const int n = p.n();
+    p.kind.assign(n, 0);
+    p.lo.assign(n, 0.0);
+    p.hi.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      const int k = p.idx[i];
+      const double a = lower ? lower[k] : NAN, b = upper ? upper[k] : NAN;
+      const bool la = std::isfinite(a), lb = std::isfinite(b);
+      char msg[160];
+      if (la && lb && !(a < b)) {
+        snprintf(msg, sizeof msg, "parameter %d: lower limit %g is not below the upper limit %g", k, a, b);
+        return kpsi::set_error(c, KPSI_E_ARG, msg);
+      }
+      p.kind[i] = la && lb ? 1 : (la ? 2 : (lb ? 3 : 0));
+      p.lo[i] = a;
+      p.hi[i] = b;
+      // the start must lie strictly inside its limits
+      if ((la && !(params[k] > a)) || (lb && !(params[k] < b))) {
+        snprintf(msg, sizeof msg, "parameter %d: start %g is not strictly inside its limits (%g, %g)", k, params[k],
+                 a, b);
+        return kpsi::set_error(c, KPSI_E_ARG, msg);
+      }
+    }
+  }
   p.analytic = o->gradient != 0;
   p.h_rel = o->fd_rel_step > 0.0 ? o->fd_rel_step : 1e-5;
   p.max_calls = o->max_calls > 0 ? o->max_calls : 100000;
@@ -227,19 +285,19 @@ kpsi_status kpsi_fit_default_options(kpsi_fit_options* o) {
   return KPSI_OK;
 }
 
-kpsi_status kpsi_migrad(kpsi_ctx* c, double* params, const int* free_mask, const kpsi_fit_options* o,
-                        kpsi_fit_result* r, double* cov) {
+static kpsi_status migrad_impl(kpsi_ctx* c, double* params, const int* free_mask, const double* lower,
+                               const double* upper, const kpsi_fit_options* o, kpsi_fit_result* r, double* cov) {
   if (!c || !params || !free_mask || !o || !r) return KPSI_E_ARG;
   const auto t0 = std::chrono::steady_clock::now();
   Problem p;
-  kpsi_status st = setup(p, c, params, free_mask, o);
+  kpsi_status st = setup(p, c, params, free_mask, o, lower, upper);
   if (st) return st;
   const int n = p.n();
   const double up = o->up > 0.0 ? o->up : 1.0;
   const double edm_target = 0.002 * (o->tolerance > 0.0 ? o->tolerance : 0.1) * up;
   std::memset(r, 0, sizeof *r);
   std::vector<double> x(n), g, g2(n, 0.0), V((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) x[i] = p.full[p.idx[i]];
+  for (int i = 0; i < n; ++i) x[i] = p.intl(i, p.full[p.idx[i]]);
   double fx = p.fg(x, g, p.analytic ? nullptr : &g2);
   if (!std::isfinite(fx)) { r->status = 4; r->fmin = fx; return std::isnan(fx) ? KPSI_E_HIP : KPSI_E_NONFINITE; }
   if (p.analytic) curvature(p, x, g2);
@@ -354,7 +412,7 @@ restart:
   r->edm = edm;
   r->n_iter = it;
   r->status = status;
-  for (int i = 0; i < n; ++i) params[p.idx[i]] = x[i];
+  for (int i = 0; i < n; ++i) params[p.idx[i]] = p.ext(i, x[i]);
   if (o->hesse) {
     if (have_cov) {
       if (cov) std::copy(Hm.begin(), Hm.end(), cov);
@@ -368,10 +426,26 @@ restart:
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) cov[(size_t)i * n + j] = 2.0 * up * V[(size_t)i * n + j];
   }
+  // limited parameters: the internal covariance mapped to the external parameters with the
+  // derivatives of the transformations at the minimum (first order, as MINUIT reports it)
+  if (cov && !p.kind.empty()) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) cov[(size_t)i * n + j] *= p.dext(i, x[i]) * p.dext(j, x[j]);
+  }
   r->n_nll = p.n_nll;
   r->n_grad = p.n_grad;
   r->wall_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return KPSI_OK;
+}
+
+kpsi_status kpsi_migrad(kpsi_ctx* c, double* params, const int* free_mask, const kpsi_fit_options* o,
+                        kpsi_fit_result* r, double* cov) {
+  return migrad_impl(c, params, free_mask, nullptr, nullptr, o, r, cov);
+}
+
+kpsi_status kpsi_migrad_limited(kpsi_ctx* c, double* params, const int* free_mask, const double* lower,
+                                const double* upper, const kpsi_fit_options* o, kpsi_fit_result* r, double* cov) {
+  return migrad_impl(c, params, free_mask, lower, upper, o, r, cov);
 }
 
 kpsi_status kpsi_hesse(kpsi_ctx* c, const double* params, const int* free_mask, const kpsi_fit_options* o,

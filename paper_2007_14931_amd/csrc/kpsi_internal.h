@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kpsi.h"
+
 namespace kpsi {
 
 constexpr int BLOCK = 256;      // threads per block (4 wavefronts of 64)
@@ -235,5 +237,8 @@ hipError_t launch_phsp(const GenArgs& a, hipStream_t st);
 hipError_t launch_accept(const AcceptArgs& a, hipStream_t st);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t st);
 hipError_t exclusive_scan_int(const int* in, int* out, int64_t n, void* tmp, size_t* tmp_bytes, hipStream_t st);
+
+// Record an error message on a context (the host runtime's kpsi_last_error) and return s.
+kpsi_status set_error(kpsi_ctx* c, kpsi_status s, const char* msg);
 
 }  // namespace kpsi

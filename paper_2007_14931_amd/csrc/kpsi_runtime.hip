@@ -165,6 +165,12 @@ kpsi_status fail(kpsi_ctx* c, kpsi_status s, const char* fmt, ...) {
   return s;
 }
 
+}  // namespace
+
+kpsi_status kpsi::set_error(kpsi_ctx* c, kpsi_status s, const char* msg) { return fail(c, s, "%s", msg); }
+
+namespace {
+
 #define HIPCHECK(c, call)                                                                        \
   do {                                                                                           \
     hipError_t e_ = (call);                                                                      \

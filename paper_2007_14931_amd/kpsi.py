@@ -26,7 +26,7 @@ EXPORTS = [
     "kpsi_load_events_device", "kpsi_set_efficiency_flat", "kpsi_set_efficiency_values", "kpsi_set_efficiency_hist",
     "kpsi_nll", "kpsi_nll_and_grad", "kpsi_density", "kpsi_invariants", "kpsi_generate_phsp", "kpsi_generate_model",
     "kpsi_set_timing", "kpsi_timing", "kpsi_timing_median", "kpsi_set_events_per_thread", "kpsi_last_error",
-    "kpsi_fit_default_options", "kpsi_migrad", "kpsi_hesse", "kpsi_set_norm_cache", "kpsi_norm_cache_stats",
+    "kpsi_fit_default_options", "kpsi_migrad", "kpsi_migrad_limited", "kpsi_hesse", "kpsi_set_norm_cache", "kpsi_norm_cache_stats",
     "kpsi_mlp_default_options", "kpsi_accept_labels", "kpsi_hist_efficiency", "kpsi_mlp_grad", "kpsi_mlp_train",
     "kpsi_mlp_eval", "kpsi_set_efficiency_mlp", "kpsi_fit_fractions", "kpsi_measure_peaks", "kpsi_set_background",
     "kpsi_template_values", "kpsi_set_flavour", "kpsi_set_constraints", "kpsi_nll_and_grad_noalloc",
@@ -122,6 +122,8 @@ def lib() -> C.CDLL:
         L.kpsi_set_events_per_thread.argtypes = [vp, C.c_int]
         L.kpsi_fit_default_options.argtypes = [C.POINTER(FitOptions)]
         L.kpsi_migrad.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(FitOptions), C.POINTER(FitResult), dp]
+        L.kpsi_migrad_limited.argtypes = [vp, dp, C.POINTER(C.c_int), dp, dp, C.POINTER(FitOptions),
+                                          C.POINTER(FitResult), dp]
         L.kpsi_hesse.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(FitOptions), dp, C.POINTER(FitResult)]
         L.kpsi_set_norm_cache.argtypes = [vp, C.c_int]
         L.kpsi_norm_cache_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), dp]
@@ -369,17 +371,28 @@ class Engine:
             setattr(o, k, v)
         return o
 
-    def migrad(self, params, free_mask, **kw):
-        """Minimise from params over the free entries.  Returns (params_at_min, covariance of
-        the free parameters, FitResult)."""
+    def migrad(self, params, free_mask, lower=None, upper=None, **kw):
+        """Minimise from params over the free entries, optionally within limits (arrays of
+        kpsi_n_params values; non-finite entries leave that side open: kpsi_migrad_limited).
+        Returns (params_at_min, covariance of the free parameters, FitResult)."""
         x = _f64(params).copy()
         m = np.ascontiguousarray(free_mask, dtype=np.int32)
         nf = int(m.sum())
         cov = np.empty((nf, nf))
         o = self.fit_options(**kw)
         r = FitResult()
-        self._chk(self.L.kpsi_migrad(self.h, _dp(x), m.ctypes.data_as(C.POINTER(C.c_int)), C.byref(o), C.byref(r),
-                                     _dp(cov)))
+        mp = m.ctypes.data_as(C.POINTER(C.c_int))
+        if lower is None and upper is None:
+            self._chk(self.L.kpsi_migrad(self.h, _dp(x), mp, C.byref(o), C.byref(r), _dp(cov)))
+        else:
+            lo = _f64(lower) if lower is not None else None
+            hi = _f64(upper) if upper is not None else None
+            for a in (lo, hi):
+                if a is not None and a.shape != x.shape:
+                    raise ValueError(f"limits need {x.size} entries, got shape {a.shape}")
+            self._chk(self.L.kpsi_migrad_limited(self.h, _dp(x), mp, _dp(lo) if lo is not None else None,
+                                                 _dp(hi) if hi is not None else None, C.byref(o), C.byref(r),
+                                                 _dp(cov)))
         return x, cov, r
 
     def hesse(self, params, free_mask, **kw):

@@ -229,3 +229,87 @@ def test_full_model_gpu_minimum_is_the_oracle_minimum():
     print(f"[fit] oracle BFGS from the generated point: {o2.nit} iterations, {time.perf_counter() - t0:.1f} s, "
           f"fmin {o2.fun:.6f} ({o2.message})", flush=True)
     assert o2.fun > rp.fmin - 1e-3
+
+
+def test_limits_that_do_not_bind_leave_the_fit_unchanged(single_kstar):
+    """kpsi_migrad_limited with limits far from the minimum (both sides on the magnitudes, a lower
+    one on the first phase, an upper one on the others) reaches the unlimited minimum; the
+    covariance mapped back from the internal variables agrees with the unlimited HESSE."""
+    res, truth, data, mc, mask = single_kstar
+    x0 = _start(truth, mask, 4)
+    xu, cu, ru = _engine(res, "fp64", data, mc).migrad(x0, mask, gradient=1)
+    lo = np.full(truth.size, np.nan)
+    hi = np.full(truth.size, np.nan)
+    lo[0::2], hi[0::2] = -20.0, 20.0            # magnitudes: both sides
+    lo[1], hi[3::2] = -30.0, 30.0               # one phase below only, the others above only
+    xl, cl, rl = _engine(res, "fp64", data, mc).migrad(x0, mask, lower=lo, upper=hi, gradient=1)
+    assert ru.status == 0 and rl.status == 0, (ru.as_dict(), rl.as_dict())
+    free = np.flatnonzero(mask)
+    sig = np.sqrt(np.diag(cu))
+    assert np.all(np.abs(xl[free] - xu[free]) / sig < 0.01)
+    assert rl.fmin == pytest.approx(ru.fmin, abs=1e-4)
+    np.testing.assert_allclose(np.sqrt(np.diag(cl)), sig, rtol=0.02)
+
+
+def test_limits_refuse_a_start_outside_and_empty_ranges(single_kstar):
+    res, truth, data, mc, mask = single_kstar
+    e = _engine(res, "fp64", data, mc)
+    lo = np.full(truth.size, -np.inf)
+    hi = np.full(truth.size, np.inf)
+    k = int(np.flatnonzero(mask)[0])
+    hi[k] = truth[k] - 0.1                     # the start lies above the upper limit
+    with pytest.raises(kpsi.KpsiError):
+        e.migrad(truth, mask, lower=lo, upper=hi)
+    hi[k], lo[k] = truth[k] - 0.1, truth[k] + 0.1  # lower above upper
+    with pytest.raises(kpsi.KpsiError):
+        e.migrad(truth, mask, lower=lo, upper=hi)
+
+
+def test_limits_keep_a_floating_mass_off_the_kinematic_edge():
+    """The far start of the test above whose FP32-adjoint and finite-difference searches ran the
+    floating Z(4430) mass into the kinematic edge (4.786 GeV): with its mass limited to (4.20, 4.65) GeV and
+    its width to (0.05, 0.40) GeV, every minimiser reaches the minimum found from the generated
+    point."""
+    import torch
+    res = W.model("full")
+    floating = ("K*(1410)", "Z(4430)")
+    truth = W.params(res, seed=11)
+    gen = kpsi.Engine(0, "fp64")
+    gen.set_model(K, res)
+    mc = gen.generate_phsp(331, 600_000, W.PHSP_WMAX)
+    gen.load(kpsi.NORM, mc)
+    scan = gen.generate_phsp(332, 200_000, W.PHSP_WMAX)
+    gen.load(kpsi.DATA, scan)
+    smax = 1.5 * float(gen.density(kpsi.DATA, truth).max())
+    data, _, nover = gen.generate_model(truth, 333, 300_000, W.PHSP_WMAX, smax)
+    torch.cuda.synchronize()
+    assert nover == 0
+    gen.close()
+    mask = W.free_mask(res, floating)
+    free = np.flatnonzero(mask)
+    nc = sum(2 * r.n_coup for r in res)
+    xt, ct, rt = _engine(res, "fp64", data, mc, floating).migrad(truth, mask, gradient=1)
+    rng = np.random.default_rng(23)
+    x0 = truth.copy()
+    for i in free:
+        if i < nc:
+            x0[i] = x0[i] * np.exp(0.3 * rng.standard_normal()) if i % 2 == 0 else x0[i] + 0.3 * rng.standard_normal()
+        else:
+            x0[i] *= 1.0 + 0.02 * rng.standard_normal()
+    lo = np.full(truth.size, np.nan)
+    hi = np.full(truth.size, np.nan)
+    iz = W.lineshape_offset(res, [r.name for r in res].index("Z(4430)"))
+    lo[iz], hi[iz] = 4.20, 4.65
+    lo[iz + 1], hi[iz + 1] = 0.05, 0.40
+    lim = dict(lower=lo, upper=hi)
+    xa, _, ra = _engine(res, "fp32", data, mc, floating).migrad(x0, mask, gradient=1, **lim)
+    xp, _, rp = _engine(res, "fp64", data, mc, floating).migrad(xa, mask, gradient=1, **lim)
+    xf, _, rf = _engine(res, "fp64", data, mc, floating).migrad(x0, mask, gradient=0, **lim)
+    print(f"[fit] limited far start: fp32 adjoint status {ra.status} ({ra.n_iter} iterations), polish status "
+          f"{rp.status}, fd status {rf.status}; fmin {rp.fmin:.4f} / {rf.fmin:.4f} vs {rt.fmin:.4f}; "
+          f"Z mass {xp[iz]:.4f} / {xf[iz]:.4f}", flush=True)
+    sig = np.sqrt(np.diag(ct))
+    for x, r in ((xp, rp), (xf, rf)):
+        assert r.status == 0 and abs(r.fmin - rt.fmin) < 0.01, r.as_dict()
+        dev = np.abs(W.canonical(res, x)[free] - W.canonical(res, xt)[free]) / sig
+        assert dev.max() < 0.5, np.sort(dev)[-5:]
